@@ -1,0 +1,434 @@
+"""FP64 CPU oracle for the weak-lensing P+B data vector, covariance and S/N.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``; nothing in the product package
+imports it.  It shares no code with the HIP library.
+
+The combinatorics (ell-bins, triangles, tomographic orderings, counts) are
+plain Python here; the heavy sums are plain C in ``wlc_oracle.c`` (built with
+gcc, loaded through ctypes).  Each function cites the passage of Rizzato et
+al. (2019), arXiv 1812.07437, that it writes out.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+import subprocess
+from itertools import product
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wlc_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force=False):
+    """Compile the C part of the oracle (gcc -O3 -fopenmp)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+class _Tables(ct.Structure):
+    _fields_ = [("n_z", ct.c_int), ("n_chi", ct.c_int), ("n_k", ct.c_int), ("n_m", ct.c_int),
+                ("chi", ct.c_void_p), ("w_chi", ct.c_void_p), ("k", ct.c_void_p),
+                ("m", ct.c_void_p), ("w_m", ct.c_void_p), ("W", ct.c_void_p), ("P", ct.c_void_p),
+                ("u", ct.c_void_p), ("nmf", ct.c_void_p), ("b1", ct.c_void_p), ("b2", ct.c_void_p),
+                ("rho", ct.c_double), ("k_max", ct.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ct.CDLL(_LIB)
+        L.or_interp.restype = ct.c_double
+        L.or_neff.restype = ct.c_double
+        L.or_halo_I.restype = ct.c_double
+        L.or_F2.restype = ct.c_double
+        L.or_lattice_modes.restype = ct.c_uint64
+        L.or_lattice_triangles.restype = ct.c_uint64
+        L.or_lattice_modes.argtypes = [ct.c_int64] * 2
+        L.or_lattice_triangles.argtypes = [ct.c_int64] * 6
+        L.or_F2.argtypes = [ct.c_double] * 3
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ct.c_void_p) if a is not None else None
+
+
+# ===================================================================
+# Combinatorics (Sec. 3.2.1, Sec. 5, App. A)
+# ===================================================================
+def ell_bins(ell_min, ell_max, n_ell):
+    """Bins equally spaced in log ell (Sec. 3.2.1, App. A).  Each bin is the
+    symmetric interval of width Delta around its centre, so the centre is the
+    arithmetic mid-point of its two edges."""
+    a, b = math.log(ell_min), math.log(ell_max)
+    edges = [math.exp(a + i * (b - a) / n_ell) for i in range(n_ell + 1)]
+    centres = [(edges[i] + edges[i + 1]) / 2.0 for i in range(n_ell)]
+    widths = [edges[i + 1] - edges[i] for i in range(n_ell)]
+    return edges, centres, widths
+
+
+def n_ell_used(centres, ell_cut):
+    """Bins kept when the S/N is cut at ell_max (eq. eq:SN): those whose
+    centre lies below the cut; all bins when there is no cut."""
+    if not ell_cut or ell_cut <= 0:
+        return len(centres)
+    return sum(1 for c in centres if c < ell_cut)
+
+
+def triangles(centres):
+    """Binned triangles l_i <= l_j <= l_k in data-vector order (Sec. 5: j runs
+    fastest, k slowest; i in between).  A bin triplet is a triangle when its
+    centres obey the strict triangle inequality.  Returns (i, j, k, class)
+    with class 'E' (all equal), 'I' (two equal) or 'S' (all different)."""
+    out = []
+    n = len(centres)
+    for k in range(n):
+        for i in range(k + 1):
+            for j in range(i, k + 1):
+                if centres[i] + centres[j] > centres[k]:
+                    cls = "E" if i == j == k else ("I" if (i == j or j == k) else "S")
+                    out.append((i, j, k, cls))
+    return out
+
+
+def bispectrum_tomo(n_z, tri):
+    """Tomographic bin triplets of one triangle, k fastest and i slowest
+    (Sec. 5).  Scalene triangles keep all n_z^3 combinations; when two sides
+    share an ell-bin only one ordering of their redshift bins is kept, since
+    swapping those two legs leaves the bispectrum unchanged."""
+    i, j, k, cls = tri
+    out = []
+    for a, b, c in product(range(n_z), repeat=3):
+        if cls == "S":
+            out.append((a, b, c))
+        elif cls == "E":
+            if a <= b <= c:
+                out.append((a, b, c))
+        elif i == j:          # l1 = l2 < l3
+            if a <= b:
+                out.append((a, b, c))
+        else:                 # l1 < l2 = l3
+            if b <= c:
+                out.append((a, b, c))
+    return out
+
+
+def enumerate_rows(n_z, n_ell, centres, tomo="paper"):
+    """Data vector D = {P, B} (eq. eq:SN2, Sec. 5).  P block: ell-bins in
+    increasing order, pairs i <= j with j fastest.  B block: triangles in the
+    order above, each with its tomographic triplets contiguous.  With
+    tomo="sorted" every triangle keeps only triplets i <= j <= k.
+
+    Returns dict of numpy arrays kind, lbin[N,3], zbin[N,3], cfg, tri and the
+    triangle list.  cfg indexes the ell-configuration: the ell-bin for P rows,
+    n_ell + triangle index for B rows."""
+    cen = centres[:n_ell]
+    tris = triangles(cen)
+    kind, lbin, zbin, cfg, tri = [], [], [], [], []
+    for b in range(n_ell):
+        for i in range(n_z):
+            for j in range(i, n_z):
+                kind.append(2); lbin.append((b, b, -1)); zbin.append((i, j, -1))
+                cfg.append(b); tri.append(-1)
+    for t, trg in enumerate(tris):
+        trip = bispectrum_tomo(n_z, trg) if tomo == "paper" else \
+            [(a, b, c) for a in range(n_z) for b in range(a, n_z) for c in range(b, n_z)]
+        for (a, b, c) in trip:
+            kind.append(3); lbin.append(trg[:3]); zbin.append((a, b, c))
+            cfg.append(n_ell + t); tri.append(t)
+    return dict(kind=np.array(kind, np.int32), lbin=np.array(lbin, np.int32),
+                zbin=np.array(zbin, np.int32), cfg=np.array(cfg, np.int32),
+                tri=np.array(tri, np.int32), triangles=tris)
+
+
+def canonical_rows(rows):
+    """Row value classes.  Under Limber every bin sees the same chi, so a
+    row's data-vector value, response and one-halo covariance depend only on
+    its ell-configuration and the multiset of its redshift bins.  Returns
+    (canon[N] -> class id, index of one representative row per class)."""
+    key_to_id, canon, reps = {}, [], []
+    for a in range(len(rows["kind"])):
+        p = int(rows["kind"][a])
+        key = (int(rows["cfg"][a]), tuple(sorted(int(x) for x in rows["zbin"][a][:p])))
+        if key not in key_to_id:
+            key_to_id[key] = len(reps)
+            reps.append(a)
+        canon.append(key_to_id[key])
+    return np.array(canon, np.int32), np.array(reps, np.int64)
+
+
+# ===================================================================
+# Counts (Sec. 3.2.2, App. B)
+# ===================================================================
+def n_modes(centres, widths, f_sky):
+    """N(l_b) = 2 l Delta l f_sky (Sec. 3.2.2), read as a number of modes."""
+    return [2.0 * c * w * f_sky for c, w in zip(centres, widths)]
+
+
+def n_tri_closed(l1, l2, l3, d1, d2, d3, f_sky):
+    """Continuum triangle count at the bin centres (App. B).  The printed
+    closed form is garbled; this is the count its own definition gives with a
+    mode density Omega/(2 pi)^2:
+        N_tri = Omega^2 l1 l2 l3 D1 D2 D3 / (2 pi^3 Lambda),
+        Lambda = sqrt(2 l1^2 l2^2 + 2 l1^2 l3^2 + 2 l2^2 l3^2 - l1^4 - l2^4 - l3^4)."""
+    om = 4.0 * math.pi * f_sky
+    lam2 = 2 * l1 ** 2 * l2 ** 2 + 2 * l1 ** 2 * l3 ** 2 + 2 * l2 ** 2 * l3 ** 2 - l1 ** 4 - l2 ** 4 - l3 ** 4
+    if lam2 <= 0:
+        raise ValueError("degenerate triangle")
+    return om ** 2 * l1 * l2 * l3 * d1 * d2 * d3 / (2.0 * math.pi ** 3 * math.sqrt(lam2))
+
+
+def lattice_thresholds(edges, f_sky):
+    """Integer thresholds on |q|^2 for the mode lattice: fundamental mode
+    l_f = 2 pi / sqrt(Omega) (a square patch of area Omega; reading of
+    Sec. 3.2.2), bin b holds q with ceil((e_b/l_f)^2) <= |q|^2 < ceil((e_{b+1}/l_f)^2)."""
+    om = 4.0 * math.pi * f_sky
+    lf = 2.0 * math.pi / math.sqrt(om)
+    return [int(math.ceil((e / lf) ** 2)) for e in edges]
+
+
+def lattice_modes(thr, b):
+    return int(lib().or_lattice_modes(thr[b], thr[b + 1]))
+
+
+def lattice_triangles(thr, b1, b2, b3):
+    """Ordered pairs (q1, q2) with q1 in b1, q2 in b2, q1 + q2 in b3 (App. B,
+    definition of N_tri as the sum of the selection function)."""
+    return int(lib().or_lattice_triangles(thr[b1], thr[b1 + 1], thr[b2], thr[b2 + 1],
+                                          thr[b3], thr[b3 + 1]))
+
+
+# ===================================================================
+# Numerics (C)
+# ===================================================================
+class Oracle:
+    """Holds one set of input tables and evaluates the method on them."""
+
+    def __init__(self, tables, tomo="paper"):
+        self.t = tables
+        cfg = tables.cfg
+        self.cfg = cfg
+        self.n_z = int(cfg["n_z"])
+        edges, centres, widths = ell_bins(cfg["ell_min"], cfg["ell_max"], int(cfg["n_ell"]))
+        self.n_ell = n_ell_used(centres, cfg.get("ell_cut", 0.0))
+        self.edges, self.centres, self.widths = edges, centres, widths
+        self.rows = enumerate_rows(self.n_z, self.n_ell, centres, tomo)
+        self.tris = self.rows["triangles"]
+        self.N = len(self.rows["kind"])
+        self.f_sky = float(cfg["f_sky"])
+        self.omega = 4.0 * math.pi * self.f_sky
+        self._keep = []
+        arr = {}
+        for name in ("chi", "w_chi", "k", "m", "w_m", "W", "P", "u", "n_m", "b1", "b2"):
+            a = getattr(tables, name)
+            if a is not None:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                self._keep.append(a)
+            arr[name] = a
+        self.arr = arr
+        self.T = _Tables(n_z=self.n_z, n_chi=len(arr["chi"]), n_k=len(arr["k"]), n_m=len(arr["m"]),
+                         chi=_p(arr["chi"]), w_chi=_p(arr["w_chi"]), k=_p(arr["k"]), m=_p(arr["m"]),
+                         w_m=_p(arr["w_m"]), W=_p(arr["W"]), P=_p(arr["P"]), u=_p(arr["u"]),
+                         nmf=_p(arr["n_m"]), b1=_p(arr["b1"]), b2=_p(arr["b2"]),
+                         rho=float(cfg["rho_mean"]), k_max=float(cfg["k_max"]))
+        self.n_chi = len(arr["chi"])
+        self.n_m = len(arr["m"])
+        self._spectra = None
+        self._U = None
+
+    # ---- ell-configurations
+    def configs(self):
+        kinds, ells = [], []
+        for b in range(self.n_ell):
+            kinds.append(2); ells.append((self.centres[b], 0.0, 0.0))
+        for (i, j, k, _) in self.tris:
+            kinds.append(3); ells.append((self.centres[i], self.centres[j], self.centres[k]))
+        return np.array(kinds, np.int32), np.array(ells, np.float64)
+
+    def _check(self):
+        if lib().or_range_error():
+            lib().or_clear_error()
+            raise ValueError("a needed k = ell/chi lies outside the k table")
+
+    def spectra(self):
+        """3-D spectra and responses at every (configuration, chi) node."""
+        if self._spectra is None:
+            kinds, ells = self.configs()
+            nc = len(kinds)
+            X = np.zeros((nc, self.n_chi)); R = np.zeros((nc, self.n_chi))
+            lib().or_clear_error()
+            lib().or_spectra_table(ct.byref(self.T), ct.c_int(nc), _p(kinds), _p(ells), _p(X), _p(R))
+            self._check()
+            self._spectra = (X, R)
+        return self._spectra
+
+    def data_vector(self, rows=None):
+        """(D, r): eq. nProjection of the halo-model spectra (data vector) and
+        of their responses (the projected response of eq. WLSSCflatskyLimber)."""
+        rows = rows or self.rows
+        X, R = self.spectra()
+        n = len(rows["kind"])
+        d = np.zeros(n); r = np.zeros(n)
+        zb = np.ascontiguousarray(rows["zbin"], np.int32)
+        lib().or_project(ct.byref(self.T), ct.c_int(n), _p(rows["kind"]), _p(zb), _p(rows["cfg"]),
+                         _p(X), _p(R), _p(d), _p(r))
+        return d, r
+
+    def shot_noise(self):
+        """sigma_eps^2 / n_i (eq. ShotNoise); equipopulated bins hold n_tot/n_z
+        sources per steradian each."""
+        nbar = float(self.cfg["n_gal_arcmin2"]) * (10800.0 / math.pi) ** 2 / self.n_z
+        return float(self.cfg["sigma_eps"]) ** 2 / nbar
+
+    def ps_table(self):
+        """P^s_ij(l_b) for all bins and pairs (eq. ShotNoise)."""
+        d, _ = self.data_vector()
+        ps = np.zeros((self.n_ell, self.n_z, self.n_z))
+        a = 0
+        for b in range(self.n_ell):
+            for i in range(self.n_z):
+                for j in range(i, self.n_z):
+                    ps[b, i, j] = ps[b, j, i] = d[a]
+                    a += 1
+            for i in range(self.n_z):
+                ps[b, i, i] += self.shot_noise()
+        return ps
+
+    def nmodes(self):
+        return np.array(n_modes(self.centres[:self.n_ell], self.widths[:self.n_ell], self.f_sky))
+
+    def ntri(self, lattice=None):
+        if lattice is not None:
+            return np.asarray(lattice, np.float64)
+        c, w = self.centres, self.widths
+        return np.array([n_tri_closed(c[i], c[j], c[k], w[i], w[j], w[k], self.f_sky)
+                         for (i, j, k, _) in self.tris], np.float64)
+
+    def u_table(self):
+        if self._U is None:
+            ell = np.array(self.centres[:self.n_ell], np.float64)
+            U = np.zeros((self.n_ell, self.n_chi, self.n_m))
+            lib().or_clear_error()
+            lib().or_tab_u(ct.byref(self.T), ct.c_int(self.n_ell), _p(ell), _p(U))
+            self._check()
+            self._U = (ell, U)
+        return self._U
+
+    # ---- covariance
+    def cov1h_pairs(self, pairs):
+        ell, U = self.u_table()
+        pairs = np.ascontiguousarray(pairs, np.int64)
+        out = np.zeros(len(pairs))
+        zb = np.ascontiguousarray(self.rows["zbin"], np.int32)
+        lb = np.ascontiguousarray(self.rows["lbin"], np.int32)
+        lib().or_cov1h_pairs(ct.byref(self.T), _p(ell), _p(U), ct.c_double(self.omega),
+                             _p(self.rows["kind"]), _p(lb), _p(zb), ct.c_int64(len(pairs)),
+                             _p(pairs), _p(out))
+        return out
+
+    def gauss_pairs(self, pairs, ntri=None):
+        ps = self.ps_table()
+        nm = self.nmodes()
+        nt = self.ntri(ntri)
+        pairs = np.ascontiguousarray(pairs, np.int64)
+        out = np.zeros(len(pairs))
+        zb = np.ascontiguousarray(self.rows["zbin"], np.int32)
+        lb = np.ascontiguousarray(self.rows["lbin"], np.int32)
+        lib().or_gauss_pairs(ct.c_int(self.n_z), _p(ps), _p(nm), _p(nt), ct.c_double(self.omega),
+                             _p(self.rows["kind"]), _p(lb), _p(zb), _p(self.rows["tri"]),
+                             ct.c_int64(len(pairs)), _p(pairs), _p(out))
+        return out
+
+    def cov_pairs(self, pairs, ntri=None):
+        """Covariance entries C[a, b] for the given (a, b) pairs: Gaussian +
+        one-halo + rank-one super-sample term."""
+        _, r = self.data_vector()
+        pairs = np.ascontiguousarray(pairs, np.int64)
+        ssc = float(self.cfg["sigma_b2"]) * r[pairs[:, 0]] * r[pairs[:, 1]]
+        return self.gauss_pairs(pairs, ntri) + self.cov1h_pairs(pairs) + ssc
+
+    def covariance(self, ntri=None):
+        """Full joint covariance C^D (eq. eq:SN2) on the lower triangle,
+        mirrored."""
+        canon, reps = canonical_rows(self.rows)
+        nc = len(reps)
+        ell, U = self.u_table()
+        kind = np.ascontiguousarray(self.rows["kind"][reps], np.int32)
+        lb = np.ascontiguousarray(self.rows["lbin"][reps], np.int32)
+        zb = np.ascontiguousarray(self.rows["zbin"][reps], np.int32)
+        c1h = np.zeros((nc, nc))
+        lib().or_cov1h_canon(ct.byref(self.T), _p(ell), _p(U), ct.c_double(self.omega), ct.c_int(nc),
+                             _p(kind), _p(lb), _p(zb), _p(c1h))
+        _, r = self.data_vector()
+        ps = self.ps_table()
+        nm = self.nmodes()
+        nt = self.ntri(ntri)
+        C = np.zeros((self.N, self.N))
+        zbf = np.ascontiguousarray(self.rows["zbin"], np.int32)
+        lbf = np.ascontiguousarray(self.rows["lbin"], np.int32)
+        lib().or_cov_full(ct.c_int(self.N), _p(c1h), ct.c_int(nc), _p(canon), ct.c_int(self.n_z),
+                          _p(ps), _p(nm), _p(nt), ct.c_double(self.omega), _p(self.rows["kind"]),
+                          _p(lbf), _p(zbf), _p(self.rows["tri"]), _p(r),
+                          ct.c_double(float(self.cfg["sigma_b2"])), _p(C))
+        return C
+
+    @staticmethod
+    def snr2(C, d):
+        """(S/N)^2 = D^T C^-1 D (eq. SNprim) by Cholesky-Banachiewicz."""
+        C = np.ascontiguousarray(C, np.float64)
+        d = np.ascontiguousarray(d, np.float64)
+        out = ct.c_double(0.0)
+        rc = lib().or_snr2(ct.c_int(len(d)), _p(C), _p(d), ct.byref(out))
+        if rc == -1:
+            raise np.linalg.LinAlgError("covariance is not positive definite")
+        if rc != 0:
+            raise MemoryError("oracle S/N allocation failed")
+        return out.value
+
+    def run(self, ntri=None):
+        d, r = self.data_vector()
+        C = self.covariance(ntri)
+        return dict(d=d, r=r, C=C, snr2=self.snr2(C, d))
+
+    # ---- scalar pieces for pins
+    def halo_I(self, mu, beta, ks):
+        ks = np.ascontiguousarray(ks, np.float64)
+        return lib().or_halo_I(ct.byref(self.T), ct.c_int(mu), ct.c_int(beta), _p(ks))
+
+    def spectrum(self, n, ks):
+        ks = np.ascontiguousarray(ks, np.float64)
+        X = ct.c_double(); R = ct.c_double()
+        kind = 2 if len(ks) == 1 else 3
+        lib().or_spectrum(ct.byref(self.T), ct.c_int(n), ct.c_int(kind), _p(ks), ct.byref(X), ct.byref(R))
+        return X.value, R.value
+
+
+def interp(kgrid, row, k):
+    kgrid = np.ascontiguousarray(kgrid, np.float64)
+    row = np.ascontiguousarray(row, np.float64)
+    lib().or_interp.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_double]
+    return lib().or_interp(_p(kgrid), _p(row), len(kgrid), float(k))
+
+
+def neff(kgrid, row, k):
+    kgrid = np.ascontiguousarray(kgrid, np.float64)
+    row = np.ascontiguousarray(row, np.float64)
+    lib().or_neff.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_double]
+    return lib().or_neff(_p(kgrid), _p(row), len(kgrid), float(k))
+
+
+def F2(ki, kj, kl):
+    return lib().or_F2(ki, kj, kl)
