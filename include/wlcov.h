@@ -1,0 +1,177 @@
+/*
+ * wlcov.h -- C ABI of libwlcov, an MI355X (gfx950) library that predicts the
+ * binned tomographic weak-lensing convergence power spectrum and bispectrum
+ * and their joint non-Gaussian covariance, following Rizzato, Benabed,
+ * Bernardeau & Lacasa (2019), "Tomographic weak lensing bispectrum"
+ * (arXiv 1812.07437).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns int: WLC_OK (0) or a negative WLC_E* code; the text
+ *     of the last error of the calling thread is wlc_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns every buffer
+ *     it passes; the library owns plans.  Nothing returned aliases a caller
+ *     buffer.
+ *   - Work is enqueued on the given HIP stream (NULL = the null stream) and is
+ *     asynchronous unless the entry point says it synchronises.
+ *   - Matrices are row-major.  The covariance is returned scaled:
+ *       C_true[a][b] = C[a][b] * 2^-(row_exp2[a] + row_exp2[b]),
+ *     so that every diagonal entry of C lies in [1, 4); the scaling is exact.
+ */
+#ifndef WLCOV_H
+#define WLCOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes */
+enum {
+  WLC_OK = 0,
+  WLC_EINVAL = -1,  /* bad argument or table (non-finite, non-positive, unsorted)   */
+  WLC_ERANGE = -2,  /* the k table does not cover some ell/chi below k_max        */
+  WLC_ENOMEM = -3,  /* host allocation failed                                      */
+  WLC_ENOTPD = -4,  /* covariance not positive definite (Cholesky pivot <= 0)      */
+  WLC_EDEVICE = -5, /* HIP runtime error                                           */
+  WLC_EBUSY = -6    /* serving: request refused by memory admission               */
+};
+
+/* ---- data-vector tomography convention (Sec. 5, ordering of eq. eq:SN2)
+ * PAPER : bispectrum triplets as in the paper (all n^3 for scalene triangles,
+ *         one ordering of the bins on equal sides);
+ * SORTED: only i <= j <= k for every triangle (the distinct values). */
+enum { WLC_TOMO_PAPER = 0, WLC_TOMO_SORTED = 1 };
+
+/* ---- arithmetic of the one-halo Gram product (everything else is FP64)
+ * FP64   : f64 MFMA, FP64 covariance output;
+ * BF16   : bf16 MFMA with FP32 accumulation, FP32 covariance output;
+ * BF16X3 : split bf16 (hi + lo) compensated product hi.hi + hi.lo + lo.hi;
+ * FP32   : f32 MFMA;
+ * BF16X3 and FP32 also return an FP32 covariance. */
+enum { WLC_FP64 = 0, WLC_BF16 = 1, WLC_BF16X3 = 2, WLC_FP32 = 3 };
+
+/* ---- flags */
+enum {
+  WLC_FLAG_NOCHECK = 1 /* skip the table validation pass (and its one stream sync) */
+};
+
+typedef struct {
+  int32_t n_z;        /* tomographic (redshift) bins                          */
+  int32_t n_ell;      /* log-spaced ell-bins over [ell_min, ell_max]          */
+  int32_t n_chi;      /* line-of-sight nodes of the tables                     */
+  int32_t n_k;        /* k nodes of the P and u tables                         */
+  int32_t n_m;        /* mass nodes                                            */
+  int32_t tomo_mode;  /* WLC_TOMO_*                                            */
+  int32_t precision;  /* WLC_FP64 / WLC_BF16 / WLC_BF16X3 / WLC_FP32           */
+  int32_t flags;      /* WLC_FLAG_*                                            */
+  double ell_min, ell_max;
+  double ell_cut;     /* keep only ell-bins whose centre is below this (<= 0: all), eq. eq:SN */
+  double f_sky;       /* sky fraction; Omega_sky = 4 pi f_sky                  */
+  double sigma_eps;   /* shape noise (eq. ShotNoise)                           */
+  double n_gal_arcmin2; /* total source density, split evenly over the bins    */
+  double sigma_b2;    /* variance of the long background mode (super-sample)   */
+  double k_max;       /* line-of-sight integrand vanishes above this k (Sec. 4.4) */
+  double rho_mean;    /* comoving mean matter density, (M_sun/h)/(Mpc/h)^3     */
+} wlc_config;
+
+/* Input tables, all DEVICE pointers to float64, row-major:
+ *   chi, w_chi [n_chi]  line-of-sight nodes (increasing, > 0) and weights;
+ *   k [n_k]             strictly increasing, > 0;
+ *   m, w_m [n_m]        masses and quadrature weights of the mass integrals;
+ *   W [n_z][n_chi]      lensing kernels (eqs. KernelLensing1, LensEff), >= 0;
+ *   P [n_chi][n_k]      linear matter power at each chi node, > 0;
+ *   u [n_m][n_k]        Fourier halo profile, > 0;
+ *   n_m [n_m]           halo mass function, > 0;
+ *   b1, b2 [n_m]        halo biases or NULL (b1 = 1, b2 = 0);
+ *   n_tri [n_tri]       optional triangle counts replacing the closed form
+ *                       (e.g. from wlc_lattice_counts), or NULL.
+ * Values at k = ell/chi are read by linear interpolation of ln X in ln k. */
+typedef struct {
+  const double *chi, *w_chi, *k, *m, *w_m;
+  const double *W, *P, *u, *n_m, *b1, *b2;
+  const double *n_tri;
+} wlc_tables;
+
+typedef struct {
+  int64_t n_data;      /* rows of the data vector in the chosen convention    */
+  int64_t n_distinct;  /* distinct rows (= SORTED vector length)              */
+  int64_t n_p;         /* power-spectrum rows of the data vector              */
+  int64_t n_tri;       /* binned triangles                                    */
+  int64_t n_cfg;       /* ell-configurations: ell-bins + triangles            */
+  int64_t n_ell_used;  /* ell-bins below ell_cut                              */
+  int64_t k_len;       /* contraction length n_chi * n_m of the Gram product  */
+  size_t c_elem_bytes; /* 8 (FP64) or 4 (mixed precisions)                    */
+  size_t ws_run_bytes; /* device workspace needed by wlc_run                  */
+  size_t ws_snr_bytes; /* device workspace needed by wlc_snr2                 */
+} wlc_sizes;
+
+typedef struct wlc_plan_s *wlc_plan;
+
+/* Build a plan (host only, no device work): the ell-bins (Sec. 3.2.1,
+ * App. A), the binned triangles l1 <= l2 <= l3 with strict triangle inequality
+ * on the bin centres, the tomographic rows in data-vector order (Sec. 5) and
+ * the map from each row to its distinct row.  Errors: WLC_EINVAL for
+ * non-positive sizes or inconsistent scalars, WLC_ENOMEM. */
+int wlc_plan_create(const wlc_config *cfg, wlc_plan *out);
+void wlc_plan_destroy(wlc_plan plan);
+int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out);
+
+/* Copy the plan's index tables into HOST buffers (any may be NULL):
+ *   tri [n_tri][3]          ell-bin indices of each triangle, data-vector order;
+ *   rows [n_data][8]        kind (2 = P, 3 = B), cfg, ell-bins l1 l2 l3 and
+ *                           redshift bins z1 z2 z3 (-1 where unused);
+ *   distinct [n_data]       index of the row's distinct (sorted) row. */
+int wlc_plan_index(wlc_plan plan, int32_t *tri, int32_t *rows, int32_t *distinct);
+
+/* Closed-form counts into HOST buffers (Sec. 3.2.2, App. B):
+ *   n_modes [n_ell_used] = 2 l Delta_l f_sky;
+ *   n_tri   [n_tri]      = Omega^2 l1 l2 l3 D1 D2 D3 / (2 pi^3 Lambda), the
+ *                          continuum count at the bin centres. */
+int wlc_counts_closed(wlc_plan plan, double *n_modes, double *n_tri);
+
+/* Integer lattice counts into DEVICE buffers (Sec. 3.2.2 lattice, App. B
+ * N_tri as a sum of the selection function): modes q != 0 of the lattice of
+ * fundamental l_f = 2 pi / sqrt(Omega) with ceil((e_b/l_f)^2) <= |q|^2 <
+ * ceil((e_{b+1}/l_f)^2) per ell-bin, and ordered pairs (q1, q2) with q1, q2,
+ * q1 + q2 in the three bins of each triangle.  Bit-exact; asynchronous.
+ * ws: DEVICE workspace of at least ws_run_bytes (only its index part is used);
+ * modes [n_ell_used] and tris [n_tri] may each be NULL to skip. */
+int wlc_lattice_counts(wlc_plan plan, void *ws, uint64_t *modes, uint64_t *tris, void *stream);
+
+/* The hot path.  From the device tables, compute into DEVICE buffers:
+ *   d [n_data]        data vector: Limber projections (eq. nProjection) of the
+ *                     halo-model P (eq. PspHMtot2) and B (eqs. B1halo,
+ *                     B2halos, first line of B3halos);
+ *   r [n_data]        projected responses to a long mode (eqs. PowerHMResp,
+ *                     BispHMResp, RespP, RespB);
+ *   C [n_data][n_data] scaled covariance (FP64 if precision == WLC_FP64 else
+ *                     FP32): Gaussian (eq. CovPPG and its bispectrum
+ *                     analogue, App. B) + one-halo 4/5/6-point terms (eqs.
+ *                     CovPPNG, Ins5P, Ins6P with eq. General1h) computed as the
+ *                     Gram product A A^T over the flattened (chi, M) axis +
+ *                     sigma_b2 r r^T (eq. WLSSCflatskyLimber, single long mode);
+ *   row_exp2 [n_data] the power-of-two scaling of C (see above).
+ * ws: DEVICE workspace of at least ws_run_bytes, 256-byte aligned.
+ * Unless WLC_FLAG_NOCHECK is set, validates the tables first and synchronises
+ * the stream once (WLC_EINVAL / WLC_ERANGE); everything else is asynchronous. */
+int wlc_run(wlc_plan plan, const wlc_tables *tables, void *ws, double *d, double *r, void *C,
+            int32_t *row_exp2, void *stream);
+
+/* (S/N)^2 = d^T C_true^-1 d (eq. SNprim) from wlc_run's outputs (DEVICE
+ * C, row_exp2, d), by an FP64 Cholesky factorisation of the scaled matrix
+ * bordered with the scaled data vector.  Result in *snr2_host.
+ * ws: DEVICE workspace of at least ws_snr_bytes.  Synchronises the stream.
+ * WLC_ENOTPD if a pivot is not positive. */
+int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
+             double *snr2_host, void *stream);
+
+const char *wlc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WLCOV_H */

@@ -1,0 +1,326 @@
+// C ABI of libwlcov: plans, workspace layout and the launch sequence of the
+// hot path (see include/wlcov.h for the contract of every entry point).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.h"
+#include "plan.h"
+
+struct wlc_plan_s {
+  wlc::Plan p;
+};
+
+namespace wlc {
+
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+constexpr int64_t GRAM_TILE = 128;
+constexpr int64_t K_ALIGN = 64;
+
+enum Buf {
+  B_ROWR, B_ROWO, B_CFGT, B_CENT, B_NMODES, B_NTRI, B_THR, B_TRI, B_FLAGS,
+  B_U, B_PK, B_NE, B_X, B_R, B_DR, B_RR, B_PS, B_G, B_GMAX, B_TS, B_SEXP,
+  B_A0, B_A1, B_GM, B_PART, NBUF
+};
+
+struct Layout {
+  size_t off[NBUF];
+  size_t total;
+};
+
+static int gram_prec(int precision) { return precision; }
+
+static Layout run_layout(const Plan &p) {
+  const auto &c = p.cfg;
+  size_t sz[NBUF] = {};
+  const int64_t n_cfg = (int64_t)p.cfgs.size();
+  const int nl = p.n_ell;
+  sz[B_ROWR] = p.rowR.size() * 4;
+  sz[B_ROWO] = p.rowO.size() * 4;
+  sz[B_CFGT] = (size_t)n_cfg * 16;
+  sz[B_CENT] = (size_t)p.n_ell_all * 8;
+  sz[B_NMODES] = (size_t)nl * 8;
+  sz[B_NTRI] = (size_t)std::max(1, p.n_tri) * 8;
+  sz[B_THR] = p.lattice_thr.size() * 8;
+  sz[B_TRI] = (size_t)std::max(1, p.n_tri) * 12;
+  sz[B_FLAGS] = 64 * 4;
+  sz[B_U] = (size_t)nl * c.n_chi * c.n_m * 8;
+  sz[B_PK] = sz[B_NE] = (size_t)nl * c.n_chi * 8;
+  sz[B_X] = sz[B_R] = (size_t)n_cfg * c.n_chi * 8;
+  sz[B_DR] = sz[B_RR] = (size_t)p.n_R * 8;
+  sz[B_PS] = (size_t)nl * c.n_z * c.n_z * 8;
+  sz[B_G] = (size_t)n_cfg * c.n_chi * c.n_m * 8;
+  sz[B_GMAX] = (size_t)n_cfg * c.n_chi * 8;
+  sz[B_TS] = (size_t)p.n_R * c.n_chi * 8;
+  sz[B_SEXP] = (size_t)p.n_R * 4;
+  const size_t ael = c.precision == WLC_FP64 ? 8 : (c.precision == WLC_FP32 ? 4 : 2);
+  sz[B_A0] = (size_t)p.r_pad * p.k_pad * ael;
+  sz[B_A1] = c.precision == WLC_BF16X3 ? sz[B_A0] : 0;
+  const size_t gel = c.precision == WLC_FP64 ? 8 : 4;
+  sz[B_GM] = (size_t)p.r_pad * p.r_pad * gel;
+  GramShape g{p.r_pad, p.k_pad, p.r_pad};
+  sz[B_PART] = gram_partial_bytes(gram_prec(c.precision), g);
+  Layout L{};
+  size_t o = 0;
+  for (int b = 0; b < NBUF; ++b) {
+    L.off[b] = o;
+    o = align_up(o + sz[b], 256);
+  }
+  L.total = o;
+  return L;
+}
+
+static int64_t snr_ld(int64_t n) { return round_up(n + 1, 8); }
+
+static size_t snr_bytes(const Plan &p) {
+  const int64_t n = p.n_out, ld = snr_ld(n);
+  return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(64 * 64 * 8, 256) + 256 + 256;
+}
+
+static void finish_sizes(Plan &p) {
+  p.k_len = (int64_t)p.cfg.n_chi * p.cfg.n_m;
+  p.k_pad = round_up(p.k_len, K_ALIGN);
+  p.r_pad = round_up(p.n_R, GRAM_TILE);
+  p.ws_run = run_layout(p).total;
+  p.ws_snr = snr_bytes(p);
+}
+
+static int hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return WLC_OK;
+  return fail(WLC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
+template <typename T>
+static T *at(void *ws, const Layout &L, Buf b) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + L.off[b]);
+}
+
+// Copy the plan's index tables into the workspace.
+static int upload_index(const Plan &p, void *ws, const Layout &L, hipStream_t s) {
+  struct Up { Buf b; const void *src; size_t bytes; } ups[] = {
+      {B_ROWR, p.rowR.data(), p.rowR.size() * 4},
+      {B_ROWO, p.rowO.data(), p.rowO.size() * 4},
+      {B_CFGT, p.cfgT.data(), p.cfgT.size() * 4},
+      {B_CENT, p.centres.data(), p.centres.size() * 8},
+      {B_NMODES, p.n_modes.data(), p.n_modes.size() * 8},
+      {B_NTRI, p.n_tri_closed.data(), p.n_tri_closed.size() * 8},
+      {B_THR, p.lattice_thr.data(), p.lattice_thr.size() * 8},
+      {B_TRI, p.triT.data(), p.triT.size() * 4},
+  };
+  // the sources live in the plan, which outlives every run using it
+  for (const auto &u : ups) {
+    if (!u.bytes) continue;
+    int rc = hip_check(hipMemcpyAsync(at<char>(ws, L, u.b), u.src, u.bytes, hipMemcpyHostToDevice, s),
+                       "index upload");
+    if (rc) return rc;
+  }
+  return WLC_OK;
+}
+
+}  // namespace wlc
+
+using namespace wlc;
+
+extern "C" {
+
+const char *wlc_last_error(void) { return last_error(); }
+
+int wlc_plan_create(const wlc_config *cfg, wlc_plan *out) {
+  if (!cfg || !out) return fail(WLC_EINVAL, "null argument");
+  *out = nullptr;
+  try {
+    auto *h = new wlc_plan_s();
+    int rc = build_plan(*cfg, h->p);
+    if (rc) {
+      delete h;
+      return rc;
+    }
+    finish_sizes(h->p);
+    *out = h;
+    return WLC_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(WLC_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(WLC_EINVAL, "plan construction failed");
+  }
+}
+
+void wlc_plan_destroy(wlc_plan plan) { delete plan; }
+
+int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out) {
+  if (!plan || !out) return fail(WLC_EINVAL, "null argument");
+  const Plan &p = plan->p;
+  out->n_data = p.n_out;
+  out->n_distinct = p.n_R;
+  out->n_p = p.n_p;
+  out->n_tri = p.n_tri;
+  out->n_cfg = (int64_t)p.cfgs.size();
+  out->n_ell_used = p.n_ell;
+  out->k_len = p.k_len;
+  out->c_elem_bytes = p.cfg.precision == WLC_FP64 ? 8 : 4;
+  out->ws_run_bytes = p.ws_run;
+  out->ws_snr_bytes = p.ws_snr;
+  return WLC_OK;
+}
+
+int wlc_plan_index(wlc_plan plan, int32_t *tri, int32_t *rows, int32_t *distinct) {
+  if (!plan) return fail(WLC_EINVAL, "null plan");
+  const Plan &p = plan->p;
+  if (tri)
+    for (int t = 0; t < p.n_tri; ++t)
+      for (int a = 0; a < 3; ++a) tri[3 * t + a] = p.cfgs[p.n_ell + t].leg[a];
+  for (int64_t a = 0; a < p.n_out; ++a) {
+    const int32_t *r = &p.rowO[8 * a];
+    const int kind = p.cfgs[r[0]].kind;
+    if (rows) {
+      int32_t *o = rows + 8 * a;
+      o[0] = kind;
+      o[1] = r[0];
+      o[2] = r[5]; o[3] = r[6]; o[4] = r[7];
+      o[5] = r[2]; o[6] = r[3]; o[7] = r[4];
+    }
+    if (distinct) distinct[a] = r[1];
+  }
+  return WLC_OK;
+}
+
+int wlc_counts_closed(wlc_plan plan, double *n_modes, double *n_tri) {
+  if (!plan) return fail(WLC_EINVAL, "null plan");
+  const Plan &p = plan->p;
+  if (n_modes) std::memcpy(n_modes, p.n_modes.data(), p.n_modes.size() * 8);
+  if (n_tri) std::memcpy(n_tri, p.n_tri_closed.data(), p.n_tri_closed.size() * 8);
+  return WLC_OK;
+}
+
+int wlc_lattice_counts(wlc_plan plan, void *ws, uint64_t *modes, uint64_t *tris, void *stream) {
+  if (!plan || !ws) return fail(WLC_EINVAL, "null argument");
+  const Plan &p = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  const Layout L = run_layout(p);
+  int rc = upload_index(p, ws, L, s);
+  if (rc) return rc;
+  const int64_t thr_max = p.lattice_thr[p.n_ell];
+  launch_lattice(at<int64_t>(ws, L, B_THR), thr_max, p.n_ell, at<int32_t>(ws, L, B_TRI), p.n_tri, modes, tris, s);
+  return hip_check(hipGetLastError(), "lattice launch");
+}
+
+int wlc_run(wlc_plan plan, const wlc_tables *tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
+            void *stream) {
+  if (!plan || !tb || !ws || !d || !r || !C || !row_exp2) return fail(WLC_EINVAL, "null argument");
+  if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "workspace must be 256-byte aligned");
+  if (!tb->chi || !tb->w_chi || !tb->k || !tb->m || !tb->w_m || !tb->W || !tb->P || !tb->u || !tb->n_m)
+    return fail(WLC_EINVAL, "missing table");
+  const Plan &p = plan->p;
+  const wlc_config &c = p.cfg;
+  hipStream_t s = (hipStream_t)stream;
+  const Layout L = run_layout(p);
+  int rc = upload_index(p, ws, L, s);
+  if (rc) return rc;
+
+  DevTables T{tb->chi, tb->w_chi, tb->k, tb->m, tb->w_m, tb->W, tb->P, tb->u, tb->n_m, tb->b1, tb->b2,
+              c.n_z, c.n_chi, c.n_k, c.n_m, c.rho_mean, c.k_max};
+  const double *cent = at<double>(ws, L, B_CENT);
+  int32_t *flags = at<int32_t>(ws, L, B_FLAGS);
+  if (!(c.flags & WLC_FLAG_NOCHECK)) {
+    launch_fill_i32(flags, 64, 0, s);
+    launch_validate(T, cent, p.n_ell, flags, s);
+    int32_t hf[2] = {0, 0};
+    rc = hip_check(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s), "validation copy");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "validation sync");
+    if (rc) return rc;
+    if (hf[0]) return fail(WLC_EINVAL, "tables must be finite, positive where required, and grids increasing");
+    if (hf[1]) return fail(WLC_ERANGE, "the k table does not cover every ell/chi below k_max");
+  }
+  const int n_cfg = (int)p.cfgs.size();
+  const int32_t *cfgT = at<int32_t>(ws, L, B_CFGT);
+  const int32_t *rowR = at<int32_t>(ws, L, B_ROWR);
+  double *U = at<double>(ws, L, B_U), *Pk = at<double>(ws, L, B_PK), *Ne = at<double>(ws, L, B_NE);
+  double *X = at<double>(ws, L, B_X), *R = at<double>(ws, L, B_R);
+  double *dR = at<double>(ws, L, B_DR), *rR = at<double>(ws, L, B_RR);
+  double *Ps = at<double>(ws, L, B_PS);
+  double *G = at<double>(ws, L, B_G), *Gmax = at<double>(ws, L, B_GMAX), *Ts = at<double>(ws, L, B_TS);
+  int32_t *sexp = at<int32_t>(ws, L, B_SEXP);
+
+  launch_stage(T, cent, p.n_ell, U, Pk, Ne, s);
+  launch_spectra(T, cfgT, n_cfg, U, Pk, Ne, cent, X, R, s);
+  launch_project(T, rowR, cfgT, p.n_R, X, R, dR, rR, s);
+  launch_ps(dR, Ps, p.n_ell, c.n_z, p.noise, s);
+  launch_gfactor(T, cfgT, n_cfg, U, G, Gmax, s);
+  launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
+
+  const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
+  void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
+  launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, A0, A1, s);
+  GramShape g{p.r_pad, p.k_pad, p.r_pad};
+  void *Gm = at<void>(ws, L, B_GM);
+  launch_gram(gram_prec(c.precision), g, A0, A1, Gm, at<void>(ws, L, B_PART), s);
+
+  AsmArgs a{};
+  a.rowO = at<int32_t>(ws, L, B_ROWO);
+  a.cfgT = cfgT;
+  a.sexp = sexp;
+  a.Gm = Gm;
+  a.ld_g = p.r_pad;
+  a.gm_f32 = c.precision != WLC_FP64;
+  a.Ps = Ps;
+  a.nmodes = at<double>(ws, L, B_NMODES);
+  a.ntri = tb->n_tri ? tb->n_tri : at<double>(ws, L, B_NTRI);
+  a.rR = rR;
+  a.dR = dR;
+  a.n_z = c.n_z;
+  a.n_ell = p.n_ell;
+  a.n = p.n_out;
+  a.omega = p.omega;
+  a.inv_omega = 1.0 / p.omega;
+  a.sigma_b2 = c.sigma_b2;
+  launch_rowexp(a, row_exp2, d, r, s);
+  launch_assemble(a, row_exp2, C, c.precision != WLC_FP64, s);
+  return hip_check(hipGetLastError(), "wlc_run launch");
+}
+
+int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws, double *snr2_host,
+             void *stream) {
+  if (!plan || !C || !row_exp2 || !d || !ws || !snr2_host) return fail(WLC_EINVAL, "null argument");
+  if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "workspace must be 256-byte aligned");
+  const Plan &p = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = p.n_out, ld = snr_ld(n);
+  char *base = static_cast<char *>(ws);
+  double *Wm = reinterpret_cast<double *>(base);
+  size_t o = align_up((size_t)(n + 1) * ld * 8, 256);
+  double *Linv = reinterpret_cast<double *>(base + o);
+  o += align_up(64 * 64 * 8, 256);
+  int32_t *flag = reinterpret_cast<int32_t *>(base + o);
+  o += 256;
+  double *out = reinterpret_cast<double *>(base + o);
+  launch_fill_i32(flag, 1, 0, s);
+  launch_chol_prep(C, p.cfg.precision != WLC_FP64, row_exp2, d, n, ld, Wm, s);
+  chol_factor(Wm, n, ld, Linv, flag, s);
+  launch_sumsq_row(Wm, n, ld, out, s);
+  int rc = hip_check(hipGetLastError(), "wlc_snr2 launch");
+  if (rc) return rc;
+  struct { int32_t flag; int32_t pad; double v; } h{};
+  rc = hip_check(hipMemcpyAsync(&h.flag, flag, 4, hipMemcpyDeviceToHost, s), "snr copy");
+  if (!rc) rc = hip_check(hipMemcpyAsync(&h.v, out, 8, hipMemcpyDeviceToHost, s), "snr copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "snr sync");
+  if (rc) return rc;
+  if (h.flag) return fail(WLC_ENOTPD, "covariance is not positive definite");
+  *snr2_host = h.v;
+  return WLC_OK;
+}
+
+}  // extern "C"

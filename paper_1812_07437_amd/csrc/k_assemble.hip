@@ -1,0 +1,150 @@
+// Assembly of the joint P+B covariance (Rizzato et al. 2019, eq. eq:SN2):
+//   C = C_Gauss + E (G / Omega) E^T + sigma_b^2 r r^T,
+// with E the map from data-vector rows to distinct rows, G the Gram product of
+// the one-halo factor, and the Gaussian blocks
+//   P-P: delta_{l l'} / N(l) [P^s_ii' P^s_jj' + P^s_ij' P^s_ji']       (eq. CovPPG)
+//   B-B: Omega / N_tri sum over the 6 maps sigma of primed onto unprimed legs of
+//        prod_a P^s_{i_a i'_sigma(a)}(l_a) delta_K(l_a, l'_sigma(a))     (App. B, Gauss term)
+//   P-B: none                                                          (eq. CovPBsynt)
+// The result is written scaled, C~[a][b] = 2^(t_a + t_b) C[a][b], with t
+// chosen so that every C~[a][a] lies in [1, 4).  Each unordered pair (a, b)
+// is evaluated once and written to both halves, so C~ is exactly symmetric.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace wlc {
+
+__device__ __forceinline__ double gauss_entry(const AsmArgs &A, const int32_t *ra, const int32_t *rb) {
+  if (ra[0] != rb[0]) return 0.0;  // different ell-configuration
+  const int nz = A.n_z;
+  const double *Ps = A.Ps;
+  const int kind = A.cfgT[4 * ra[0]];
+  if (kind == 2) {
+    const int b = ra[5];
+    const double *P = Ps + (size_t)b * nz * nz;
+    return (P[ra[2] * nz + rb[2]] * P[ra[3] * nz + rb[3]] + P[ra[2] * nz + rb[3]] * P[ra[3] * nz + rb[2]]) /
+           A.nmodes[b];
+  }
+  const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  double s = 0.0;
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    double term = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int sa = perm[p][a];
+      if (ra[5 + a] != rb[5 + sa]) { term = 0.0; break; }
+      term *= Ps[((size_t)ra[5 + a] * nz + ra[2 + a]) * nz + rb[2 + sa]];
+    }
+    s += term;
+  }
+  return A.omega / A.ntri[ra[0] - A.n_ell] * s;
+}
+
+__device__ __forceinline__ double gram_at(const AsmArgs &A, int64_t ea, int64_t eb) {
+  const int64_t hi = ea > eb ? ea : eb, lo = ea > eb ? eb : ea;
+  return A.gm_f32 ? (double)((const float *)A.Gm)[hi * A.ld_g + lo] : ((const double *)A.Gm)[hi * A.ld_g + lo];
+}
+
+// Diagonal first: row exponents t_a, and the expanded d, r.
+__global__ void k_rowexp(AsmArgs A, int32_t *row_exp2, double *d, double *r) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= A.n) return;
+  const int32_t *ra = A.rowO + 8 * a;
+  const int64_t e = ra[1];
+  const double g = gram_at(A, e, e);
+  const double rr = A.rR[e];
+  const double c = ldexp(g, -2 * A.sexp[e]) * A.inv_omega + gauss_entry(A, ra, ra) + A.sigma_b2 * rr * rr;
+  int t = 0;
+  if (c > 0.0 && isfinite(c)) {
+    const int E = exp2_of(c);
+    const int q = E - 1;
+    t = -(q >= 0 ? q / 2 : -((1 - q) / 2));  // -floor((E - 1) / 2)
+  }
+  row_exp2[a] = t;
+  d[a] = A.dR[e];
+  r[a] = rr;
+}
+
+void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowexp, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, row_exp2, d, r);
+}
+
+// 64 x 64 output tiles (I >= J); each thread computes 16 entries of one
+// column, the transposed copy goes through LDS so both halves are written
+// with contiguous rows.
+constexpr int AT = 64;
+
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__restrict__ row_exp2,
+                                                  OutT *__restrict__ C) {
+  __shared__ double tileT[AT][AT + 1];
+  __shared__ int32_t rowA[AT][8], rowB[AT][8];
+  __shared__ int32_t tA[AT], tB[AT], sA[AT], sB[AT];
+  __shared__ double rA[AT], rB[AT];
+  const int64_t t = blockIdx.x;
+  int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  const int64_t I = i, J = t - i * (i + 1) / 2;
+  const int64_t a0 = I * AT, b0 = J * AT;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < AT * 8; q += 256) {
+    const int r = q / 8, c = q % 8;
+    rowA[r][c] = a0 + r < A.n ? A.rowO[(a0 + r) * 8 + c] : 0;
+    rowB[r][c] = b0 + r < A.n ? A.rowO[(b0 + r) * 8 + c] : 0;
+  }
+  __syncthreads();
+  if (tid < AT) {
+    const int64_t a = a0 + tid;
+    tA[tid] = a < A.n ? row_exp2[a] : 0;
+    sA[tid] = a < A.n ? A.sexp[rowA[tid][1]] : 0;
+    rA[tid] = a < A.n ? A.rR[rowA[tid][1]] : 0.0;
+  } else if (tid < 2 * AT) {
+    const int q = tid - AT;
+    const int64_t b = b0 + q;
+    tB[q] = b < A.n ? row_exp2[b] : 0;
+    sB[q] = b < A.n ? A.sexp[rowB[q][1]] : 0;
+    rB[q] = b < A.n ? A.rR[rowB[q][1]] : 0.0;
+  }
+  __syncthreads();
+  const int cb = tid & 63;          // column within the tile
+  const int rbase = (tid >> 6) * 16;
+  const int64_t b = b0 + cb;
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int ra = rbase + q;
+    const int64_t a = a0 + ra;
+    double v = 0.0;
+    const bool live = a < A.n && b < A.n && a >= b;
+    if (live) {
+      const int tt = tA[ra] + tB[cb];
+      const double g = gram_at(A, rowA[ra][1], rowB[cb][1]);
+      const double rest = A.sigma_b2 * rA[ra] * rB[cb] + gauss_entry(A, rowA[ra], rowB[cb]);
+      v = ldexp(g * A.inv_omega, tt - sA[ra] - sB[cb]) + ldexp(rest, tt);
+      C[a * A.n + b] = (OutT)v;
+    }
+    tileT[ra][cb] = v;
+  }
+  __syncthreads();
+  // transposed half: C[b][a] for the same pairs, rows of the output contiguous
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int rb = rbase + q;  // row of the transposed tile (b index)
+    const int ca = cb;         // column (a index)
+    const int64_t bb = b0 + rb, aa = a0 + ca;
+    if (aa < A.n && bb < A.n && aa > bb) C[bb * A.n + aa] = (OutT)tileT[ca][rb];
+  }
+}
+
+void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s) {
+  const int64_t nt = (a.n + AT - 1) / AT;
+  const int64_t tiles = nt * (nt + 1) / 2;
+  if (c_f32)
+    hipLaunchKernelGGL(k_assemble<float>, dim3((unsigned)tiles), dim3(256), 0, s, a, row_exp2, (float *)C);
+  else
+    hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)tiles), dim3(256), 0, s, a, row_exp2, (double *)C);
+}
+
+}  // namespace wlc

@@ -1,0 +1,406 @@
+// Table staging, halo-model quadrature, Limber projection and the Gram factor.
+//
+// Rizzato et al. (2019), arXiv 1812.07437:
+//   halo mass integrals I_mu^beta ............ eq. ImunuHalos (Sec. 4.1)
+//   P_HM, B_HM ............................... eqs. PspHMtot2, B1halo, B2halos, B3halos (first line)
+//   responses to a long mode ................. eqs. PowerHMResp, BispHMResp, RespP, RespB (Sec. 4.3)
+//   Limber projection ........................ eq. nProjection (Sec. 3.1)
+//   one-halo n-point function ................ eq. General1h (Sec. 4.2)
+//   k_max cut of the line-of-sight integrand . Sec. 4.4
+// Tables are read by linear interpolation of ln X in ln k between the
+// bracketing nodes; d ln P / d ln k uses centred node differences (one-sided
+// at the ends) interpolated linearly in ln k.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace wlc {
+
+// ------------------------------------------------------------- validation
+__global__ void k_validate(DevTables T, const double *centres, int n_ell, int *flags) {
+  const int64_t nP = (int64_t)T.n_chi * T.n_k, nU = (int64_t)T.n_m_pts * T.n_k, nW = (int64_t)T.n_z * T.n_chi;
+  const int64_t nM = T.n_m_pts, nC = T.n_chi, nK = T.n_k, nCov = (int64_t)n_ell * T.n_chi;
+  const int64_t total = nP + nU + nW + nM + nC + nK + nCov;
+  int bad = 0, range = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = i;
+    if (q < nP) { double v = T.P[q]; bad |= !(isfinite(v) && v > 0.0); continue; }
+    q -= nP;
+    if (q < nU) { double v = T.u[q]; bad |= !(isfinite(v) && v > 0.0); continue; }
+    q -= nU;
+    if (q < nW) { double v = T.W[q]; bad |= !(isfinite(v) && v >= 0.0); continue; }
+    q -= nW;
+    if (q < nM) {
+      bad |= !(isfinite(T.n_m[q]) && T.n_m[q] > 0.0);
+      bad |= !(isfinite(T.m[q]) && T.m[q] > 0.0);
+      bad |= !(isfinite(T.w_m[q]) && T.w_m[q] >= 0.0);
+      if (T.b1) bad |= !isfinite(T.b1[q]);
+      if (T.b2) bad |= !isfinite(T.b2[q]);
+      continue;
+    }
+    q -= nM;
+    if (q < nC) {
+      bad |= !(isfinite(T.chi[q]) && T.chi[q] > 0.0 && isfinite(T.w_chi[q]) && T.w_chi[q] >= 0.0);
+      if (q > 0) bad |= !(T.chi[q] > T.chi[q - 1]);
+      continue;
+    }
+    q -= nC;
+    if (q < nK) {
+      bad |= !(isfinite(T.k[q]) && T.k[q] > 0.0);
+      if (q > 0) bad |= !(T.k[q] > T.k[q - 1]);
+      continue;
+    }
+    q -= nK;
+    {
+      const int b = (int)(q / T.n_chi), n = (int)(q % T.n_chi);
+      const double kk = centres[b] / T.chi[n];
+      if (kk <= T.k_max && !(kk >= T.k[0] && kk <= T.k[T.n_k - 1])) range = 1;
+    }
+  }
+  if (bad) atomicOr(&flags[0], 1);
+  if (range) atomicOr(&flags[1], 1);
+}
+
+void launch_validate(const DevTables &T, const double *centres, int n_ell, int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(512), dim3(256), 0, s, T, centres, n_ell, flags);
+}
+
+// ------------------------------------------------------------- staging
+// U[b][n][m] = u(m, c_b / chi_n) (0 above k_max); Pk, Ne [b][n] = P and its
+// logarithmic slope at c_b / chi_n.
+__global__ void k_stage_u(DevTables T, const double *centres, int n_ell, double *U) {
+  const int64_t total = (int64_t)n_ell * T.n_chi * T.n_m_pts;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int mi = (int)(i % T.n_m_pts);
+    const int64_t bn = i / T.n_m_pts;
+    const int n = (int)(bn % T.n_chi), b = (int)(bn / T.n_chi);
+    const double kk = centres[b] / T.chi[n];
+    double v = 0.0;
+    int j; double t;
+    if (kk <= T.k_max && bracket_lnk(T.k, T.n_k, kk, j, t)) {
+      const double *row = T.u + (int64_t)mi * T.n_k;
+      v = exp((1.0 - t) * log(row[j]) + t * log(row[j + 1]));
+    }
+    U[i] = v;
+  }
+}
+
+__device__ __forceinline__ double node_slope(const double *kg, const double *row, int nk, int j) {
+  const int a = j > 0 ? j - 1 : 0, b = j < nk - 1 ? j + 1 : nk - 1;
+  return (log(row[b]) - log(row[a])) / (log(kg[b]) - log(kg[a]));
+}
+
+__global__ void k_stage_p(DevTables T, const double *centres, int n_ell, double *Pk, double *Ne) {
+  const int64_t total = (int64_t)n_ell * T.n_chi;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(i % T.n_chi), b = (int)(i / T.n_chi);
+    const double kk = centres[b] / T.chi[n];
+    double pv = 0.0, nv = 0.0;
+    int j; double t;
+    if (kk <= T.k_max && bracket_lnk(T.k, T.n_k, kk, j, t)) {
+      const double *row = T.P + (int64_t)n * T.n_k;
+      pv = exp((1.0 - t) * log(row[j]) + t * log(row[j + 1]));
+      nv = (1.0 - t) * node_slope(T.k, row, T.n_k, j) + t * node_slope(T.k, row, T.n_k, j + 1);
+    }
+    Pk[i] = pv;
+    Ne[i] = nv;
+  }
+}
+
+void launch_stage(const DevTables &T, const double *centres, int n_ell, double *U, double *Pk, double *Ne,
+                  hipStream_t s) {
+  const int64_t tu = (int64_t)n_ell * T.n_chi * T.n_m_pts;
+  const int gu = (int)std::min<int64_t>((tu + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_stage_u, dim3(gu), dim3(256), 0, s, T, centres, n_ell, U);
+  const int64_t tp = (int64_t)n_ell * T.n_chi;
+  const int gp = (int)std::min<int64_t>((tp + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_stage_p, dim3(gp), dim3(256), 0, s, T, centres, n_ell, Pk, Ne);
+}
+
+// ------------------------------------------------------------- 3-D spectra
+// One wavefront per (configuration, chi node): lanes stride over the mass
+// nodes, then a wavefront reduction of every mass integral.
+__device__ __forceinline__ double cosine3(double ki, double kj, double kl) {
+  return (kl * kl - ki * ki - kj * kj) / (2.0 * ki * kj);
+}
+
+__global__ void k_spectra(DevTables T, const int32_t *cfgT, int n_cfg, const double *U, const double *Pk,
+                          const double *Ne, const double *centres, double *X, double *R) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (item >= (int64_t)n_cfg * T.n_chi) return;
+  const int c = (int)(item / T.n_chi), n = (int)(item % T.n_chi);
+  const int kind = cfgT[4 * c];
+  const int l0 = cfgT[4 * c + 1], l1 = cfgT[4 * c + 2], l2 = cfgT[4 * c + 3];
+  const double chi = T.chi[n];
+  double lmax = centres[l0];
+  if (kind == 3) lmax = fmax(lmax, fmax(centres[l1], centres[l2]));
+  const size_t out = (size_t)c * T.n_chi + n;
+  if (lmax / chi > T.k_max) {
+    if (lane == 0) { X[out] = 0.0; R[out] = 0.0; }
+    return;
+  }
+  const int nm = T.n_m_pts;
+  const double inv_rho = 1.0 / T.rho;
+  if (kind == 2) {
+    const double *Ub = U + ((size_t)l0 * T.n_chi + n) * nm;
+    double I11 = 0.0, I20 = 0.0, I21 = 0.0;
+    for (int mi = lane; mi < nm; mi += WAVE) {
+      const double x = T.m[mi] * inv_rho;
+      const double wn = T.w_m[mi] * T.n_m[mi];
+      const double b1 = T.b1 ? T.b1[mi] : 1.0;
+      const double uu = Ub[mi];
+      I11 += wn * b1 * x * uu;
+      I20 += wn * x * x * uu * uu;
+      I21 += wn * b1 * x * x * uu * uu;
+    }
+    I11 = wave_sum(I11); I20 = wave_sum(I20); I21 = wave_sum(I21);
+    if (lane == 0) {
+      const double P = Pk[(size_t)l0 * T.n_chi + n], ne = Ne[(size_t)l0 * T.n_chi + n];
+      const double Rlin = 47.0 / 21.0 * P - ne * P / 3.0;
+      X[out] = I20 + I11 * I11 * P;
+      R[out] = I11 * I11 * Rlin + I21;
+    }
+    return;
+  }
+  const int lg[3] = {l0, l1, l2};
+  const double *Ua = U + ((size_t)l0 * T.n_chi + n) * nm;
+  const double *Ub = U + ((size_t)l1 * T.n_chi + n) * nm;
+  const double *Uc = U + ((size_t)l2 * T.n_chi + n) * nm;
+  double I11[3] = {0, 0, 0}, I21[3] = {0, 0, 0}, I22[3] = {0, 0, 0}, I30 = 0.0, I31 = 0.0;
+  for (int mi = lane; mi < nm; mi += WAVE) {
+    const double x = T.m[mi] * inv_rho;
+    const double wn = T.w_m[mi] * T.n_m[mi];
+    const double b1 = T.b1 ? T.b1[mi] : 1.0;
+    const double b2 = T.b2 ? T.b2[mi] : 0.0;
+    const double u[3] = {Ua[mi], Ub[mi], Uc[mi]};
+    const double w1 = wn * x, w2 = wn * x * x, w3 = wn * x * x * x;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double ubc = u[(a + 1) % 3] * u[(a + 2) % 3];
+      I11[a] += w1 * b1 * u[a];
+      I21[a] += w2 * b1 * ubc;
+      I22[a] += w2 * b2 * ubc;
+    }
+    const double u3 = u[0] * u[1] * u[2];
+    I30 += w3 * u3;
+    I31 += w3 * b1 * u3;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) { I11[a] = wave_sum(I11[a]); I21[a] = wave_sum(I21[a]); I22[a] = wave_sum(I22[a]); }
+  I30 = wave_sum(I30);
+  I31 = wave_sum(I31);
+  if (lane == 0) {
+    double P[3], ne[3], kv[3], Rlin[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      P[a] = Pk[(size_t)lg[a] * T.n_chi + n];
+      ne[a] = Ne[(size_t)lg[a] * T.n_chi + n];
+      kv[a] = centres[lg[a]] / chi;
+      Rlin[a] = 47.0 / 21.0 * P[a] - ne[a] * P[a] / 3.0;
+    }
+    double two_halo = 0.0, resp_cyc = 0.0, Bpt = 0.0, Bg2 = 0.0, dil = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      two_halo += I11[a] * I21[a] * P[a];
+      resp_cyc += I11[a] * I22[a] * P[a] + I11[a] * I21[a] * Rlin[a];
+      const int i = a, j = (a + 1) % 3, l = (a + 2) % 3;
+      const double mu = cosine3(kv[i], kv[j], kv[l]);
+      const double F = 5.0 / 7.0 + 0.5 * mu * (kv[i] / kv[j] + kv[j] / kv[i]) + 2.0 / 7.0 * mu * mu;
+      Bpt += 2.0 * F * P[i] * P[j];
+      Bg2 += 2.0 * (mu * mu - 1.0) * P[i] * P[j];
+      dil += 2.0 * F * P[i] * P[j] * (ne[i] + ne[j]);
+    }
+    const double I111 = I11[0] * I11[1] * I11[2];
+    X[out] = I30 + two_halo + I111 * Bpt;
+    R[out] = I111 * (433.0 / 126.0 * Bpt + 5.0 / 126.0 * Bg2 - dil / 3.0) + resp_cyc + I31;
+  }
+}
+
+void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *Pk,
+                    const double *Ne, const double *centres, double *X, double *R, hipStream_t s) {
+  const int64_t items = (int64_t)n_cfg * T.n_chi;
+  const int g = (int)((items + 3) / 4);
+  hipLaunchKernelGGL(k_spectra, dim3(g), dim3(256), 0, s, T, cfgT, n_cfg, U, Pk, Ne, centres, X, R);
+}
+
+// ------------------------------------------------------------- projection
+// One wavefront per distinct row: lanes stride over chi, then reduce.
+__global__ void k_project(DevTables T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *X,
+                          const double *R, double *dR, double *rR) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (row >= n_R) return;
+  const int c = rowR[4 * row];
+  const int p = cfgT[4 * c];
+  int z[3] = {rowR[4 * row + 1], rowR[4 * row + 2], rowR[4 * row + 3]};
+  double sd = 0.0, sr = 0.0;
+  for (int n = lane; n < T.n_chi; n += WAVE) {
+    const double chi = T.chi[n];
+    double tw = T.w_chi[n] * pow(chi, 2.0 - 2.0 * p);
+    for (int q = 0; q < p; ++q) tw *= T.W[(size_t)z[q] * T.n_chi + n];
+    sd += tw * X[(size_t)c * T.n_chi + n];
+    sr += tw * R[(size_t)c * T.n_chi + n];
+  }
+  sd = wave_sum(sd);
+  sr = wave_sum(sr);
+  if (lane == 0) { dR[row] = sd; rR[row] = sr; }
+}
+
+void launch_project(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *X,
+                    const double *R, double *dR, double *rR, hipStream_t s) {
+  const int g = (int)((n_R + 3) / 4);
+  hipLaunchKernelGGL(k_project, dim3(g), dim3(256), 0, s, T, rowR, cfgT, n_R, X, R, dR, rR);
+}
+
+// Shot-noise power P^s_ij(l_b) = P_ij(l_b) + delta_ij sigma_eps^2 / n_i
+// (eq. ShotNoise); the power-spectrum rows lead the distinct rows.
+__global__ void k_ps(const double *dR, double *Ps, int n_ell, int n_z, double noise) {
+  const int total = n_ell * n_z * n_z;
+  const int npair = n_z * (n_z + 1) / 2;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
+    const int j = q % n_z, i = (q / n_z) % n_z, b = q / (n_z * n_z);
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const int rank = lo * n_z - lo * (lo - 1) / 2 + (hi - lo);
+    Ps[q] = dR[(size_t)b * npair + rank] + (i == j ? noise : 0.0);
+  }
+}
+
+void launch_ps(const double *dR, double *Ps, int n_ell, int n_z, double noise, hipStream_t s) {
+  const int total = n_ell * n_z * n_z;
+  hipLaunchKernelGGL(k_ps, dim3((total + 255) / 256), dim3(256), 0, s, dR, Ps, n_ell, n_z, noise);
+}
+
+// ------------------------------------------------------------- Gram factor
+// The one-halo (p_a + p_b)-point function factorises over the legs of each
+// row (eq. General1h), so
+//   A[row][(n, m)] = sqrt(w_n) chi_n^-(2p-1) prod_i W_i(chi_n)        (= T[row][n])
+//                  * sqrt(w_m n_m) (m/rho)^p prod_legs u(m, l/chi_n)   (= G[cfg][n][m])
+// and (1/Omega) A A^T is the one-halo covariance of eqs. CovPPNG, Ins5P, Ins6P.
+__global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, const double *U, double *G, double *Gmax) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (item >= (int64_t)n_cfg * T.n_chi) return;
+  const int c = (int)(item / T.n_chi), n = (int)(item % T.n_chi);
+  const int kind = cfgT[4 * c];
+  const int nm = T.n_m_pts;
+  const double *U0 = U + ((size_t)cfgT[4 * c + 1] * T.n_chi + n) * nm;
+  const double *U1 = kind == 3 ? U + ((size_t)cfgT[4 * c + 2] * T.n_chi + n) * nm : U0;
+  const double *U2 = kind == 3 ? U + ((size_t)cfgT[4 * c + 3] * T.n_chi + n) * nm : nullptr;
+  const double inv_rho = 1.0 / T.rho;
+  double mx = 0.0;
+  double *Gout = G + (size_t)item * nm;
+  for (int mi = lane; mi < nm; mi += WAVE) {
+    const double x = T.m[mi] * inv_rho;
+    double g = sqrt(T.w_m[mi] * T.n_m[mi]) * x * x * U0[mi] * U1[mi];
+    if (kind == 3) g *= x * U2[mi];
+    Gout[mi] = g;
+    mx = fmax(mx, fabs(g));
+  }
+  mx = wave_max(mx);
+  if (lane == 0) Gmax[item] = mx;
+}
+
+void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, double *G, double *Gmax,
+                    hipStream_t s) {
+  const int64_t items = (int64_t)n_cfg * T.n_chi;
+  hipLaunchKernelGGL(k_gfactor, dim3((int)((items + 3) / 4)), dim3(256), 0, s, T, cfgT, n_cfg, U, G, Gmax);
+}
+
+// Per distinct row: T[n] and the row exponent s = -e with
+// max_k |A[row][k]| = f 2^e, f in [0.5, 1); Ts[row][n] = 2^s T[n].
+__global__ void k_tfactor(DevTables T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *Gmax,
+                          double *Ts, int32_t *sexp) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (row >= n_R) return;
+  const int c = rowR[4 * row];
+  const int p = cfgT[4 * c];
+  const int z[3] = {rowR[4 * row + 1], rowR[4 * row + 2], rowR[4 * row + 3]};
+  double mx = 0.0;
+  for (int n = lane; n < T.n_chi; n += WAVE) {
+    const double chi = T.chi[n];
+    double t = sqrt(T.w_chi[n]) * pow(chi, 1.0 - 2.0 * p);
+    for (int q = 0; q < p; ++q) t *= T.W[(size_t)z[q] * T.n_chi + n];
+    mx = fmax(mx, fabs(t) * Gmax[(size_t)c * T.n_chi + n]);
+  }
+  mx = wave_max(mx);
+  const int s = -exp2_of(mx);
+  for (int n = lane; n < T.n_chi; n += WAVE) {
+    const double chi = T.chi[n];
+    double t = sqrt(T.w_chi[n]) * pow(chi, 1.0 - 2.0 * p);
+    for (int q = 0; q < p; ++q) t *= T.W[(size_t)z[q] * T.n_chi + n];
+    Ts[(size_t)row * T.n_chi + n] = ldexp(t, s);
+  }
+  if (lane == 0) sexp[row] = s;
+}
+
+void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *Gmax,
+                    double *Ts, int32_t *sexp, hipStream_t s) {
+  hipLaunchKernelGGL(k_tfactor, dim3((int)((n_R + 3) / 4)), dim3(256), 0, s, T, rowR, cfgT, n_R, Gmax, Ts, sexp);
+}
+
+// ------------------------------------------------------------- A build
+// A[row][k], k = n * n_m + m, row-major [r_pad][k_pad]; rows >= n_R and
+// k >= n_chi * n_m are zero.  Each thread writes 8 consecutive k.
+template <int FMT>
+__global__ void k_abuild(const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int n_chi, int n_m,
+                         int64_t k_pad, void *A0, void *A1) {
+  const int64_t row = blockIdx.y;
+  const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  if (k0 >= k_pad) return;
+  const int64_t k_len = (int64_t)n_chi * n_m;
+  double v[8];
+  if (row < n_R) {
+    const int c = rowR[4 * row];
+    const double *Tr = Ts + (size_t)row * n_chi;
+    const double *Gc = G + (size_t)c * n_chi * n_m;
+    int n = (int)(k0 / n_m), m = (int)(k0 % n_m);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t k = k0 + q;
+      v[q] = k < k_len ? Tr[n] * Gc[(size_t)n * n_m + m] : 0.0;
+      if (++m == n_m) { m = 0; ++n; }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = 0.0;
+  }
+  const size_t off = (size_t)row * k_pad + k0;
+  if constexpr (FMT == 0) {
+    double *o = (double *)A0 + off;
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) *(double2 *)(o + q) = make_double2(v[q], v[q + 1]);
+  } else if constexpr (FMT == 3) {
+    float *o = (float *)A0 + off;
+    *(float4 *)o = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    *(float4 *)(o + 4) = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+  } else {
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float x0 = (float)v[2 * q], x1 = (float)v[2 * q + 1];
+      const uint16_t h0 = f32_to_bf16_rne(x0), h1 = f32_to_bf16_rne(x1);
+      hi[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      if constexpr (FMT == 2) {
+        const uint16_t g0 = f32_to_bf16_rne(x0 - bf16_to_f32(h0)), g1 = f32_to_bf16_rne(x1 - bf16_to_f32(h1));
+        lo[q] = (uint32_t)g0 | ((uint32_t)g1 << 16);
+      }
+    }
+    *(u32x4 *)((uint16_t *)A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
+    if constexpr (FMT == 2) *(u32x4 *)((uint16_t *)A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+  }
+}
+
+void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
+                   int n_chi, int n_m, int64_t k_pad, void *A0, void *A1, hipStream_t s) {
+  const dim3 grid((unsigned)((k_pad / 8 + 255) / 256), (unsigned)r_pad);
+  switch (fmt) {
+    case 0: hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
+    case 1: hipLaunchKernelGGL(k_abuild<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
+    case 2: hipLaunchKernelGGL(k_abuild<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
+    default: hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
+  }
+}
+
+}  // namespace wlc

@@ -1,0 +1,71 @@
+// Launch wrappers for the HIP kernels (host side, called by the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dev.h"
+#include "wlcov.h"
+
+namespace wlc {
+
+// ---- tables and quadrature (k_tables.hip)
+void launch_validate(const DevTables &T, const double *centres, int n_ell, int *flags, hipStream_t s);
+void launch_stage(const DevTables &T, const double *centres, int n_ell, double *U, double *Pk, double *Ne,
+                  hipStream_t s);
+void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *Pk,
+                    const double *Ne, const double *centres, double *X, double *R, hipStream_t s);
+void launch_project(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *X,
+                    const double *R, double *dR, double *rR, hipStream_t s);
+void launch_ps(const double *dR, double *Ps, int n_ell, int n_z, double noise, hipStream_t s);
+void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, double *G, double *Gmax,
+                    hipStream_t s);
+void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *Gmax,
+                    double *Ts, int32_t *sexp, hipStream_t s);
+// fmt: 0 = f64, 1 = bf16 (hi only), 2 = bf16 hi + lo, 3 = f32
+void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
+                   int n_chi, int n_m, int64_t k_pad, void *A0, void *A1, hipStream_t s);
+
+// ---- Gram product (k_gram.hip): lower-triangle tiles of A A^T
+struct GramShape {
+  int64_t r_pad;   // padded rows (multiple of the tile)
+  int64_t k_pad;   // padded contraction length
+  int64_t ld_out;  // leading dimension of the output
+};
+size_t gram_partial_bytes(int prec, const GramShape &g);
+void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
+                 hipStream_t s);
+
+// ---- assembly (k_assemble.hip)
+struct AsmArgs {
+  const int32_t *rowO;    // [n][8]: cfg, e, z0, z1, z2, l0, l1, l2
+  const int32_t *cfgT;    // [n_cfg][4]: kind, l0, l1, l2
+  const int32_t *sexp;    // [n_R] row exponents of A
+  const void *Gm;         // [r_pad][r_pad] lower tiles, f64 or f32
+  int64_t ld_g;
+  int gm_f32;
+  const double *Ps;       // [n_ell][n_z][n_z]
+  const double *nmodes;   // [n_ell]
+  const double *ntri;     // [n_tri]
+  const double *rR, *dR;  // [n_R]
+  int n_z, n_ell;
+  int64_t n;              // output rows
+  double inv_omega, omega, sigma_b2;
+};
+void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hipStream_t s);
+void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s);
+
+// ---- signal-to-noise (k_chol.hip)
+void launch_chol_prep(const void *C, int c_f32, const int32_t *row_exp2, const double *d, int64_t n, int64_t ld,
+                      double *Wm, hipStream_t s);
+int chol_factor(double *Wm, int64_t n, int64_t ld, double *Linv, int *flag, hipStream_t s);
+void launch_sumsq_row(const double *Wm, int64_t n, int64_t ld, double *out, hipStream_t s);
+
+// ---- lattice counts (k_lattice.hip); thr_max = largest threshold used
+void launch_lattice(const int64_t *thr_dev, int64_t thr_max, int n_ell, const int32_t *tri, int n_tri,
+                    uint64_t *modes, uint64_t *tris, hipStream_t s);
+
+// ---- utilities (api.hip)
+void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
+
+}  // namespace wlc

@@ -1,0 +1,219 @@
+"""ctypes binding of libwlcov (include/wlcov.h), with the same entry-point names.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides device memory and streams.  Importing this module
+fails loudly when the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwlcov.so")
+
+WLC_OK, WLC_EINVAL, WLC_ERANGE, WLC_ENOMEM, WLC_ENOTPD, WLC_EDEVICE, WLC_EBUSY = 0, -1, -2, -3, -4, -5, -6
+WLC_TOMO_PAPER, WLC_TOMO_SORTED = 0, 1
+WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32 = 0, 1, 2, 3
+WLC_FLAG_NOCHECK = 1
+PRECISIONS = {"fp64": WLC_FP64, "bf16": WLC_BF16, "bf16x3": WLC_BF16X3, "fp32": WLC_FP32}
+
+
+class WlcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("wlcov error %d: %s" % (code, msg))
+        self.code = code
+
+
+class wlc_config(ct.Structure):
+    _fields_ = [("n_z", ct.c_int32), ("n_ell", ct.c_int32), ("n_chi", ct.c_int32), ("n_k", ct.c_int32),
+                ("n_m", ct.c_int32), ("tomo_mode", ct.c_int32), ("precision", ct.c_int32), ("flags", ct.c_int32),
+                ("ell_min", ct.c_double), ("ell_max", ct.c_double), ("ell_cut", ct.c_double),
+                ("f_sky", ct.c_double), ("sigma_eps", ct.c_double), ("n_gal_arcmin2", ct.c_double),
+                ("sigma_b2", ct.c_double), ("k_max", ct.c_double), ("rho_mean", ct.c_double)]
+
+
+class wlc_tables(ct.Structure):
+    _fields_ = [(n, ct.c_void_p) for n in ("chi", "w_chi", "k", "m", "w_m", "W", "P", "u", "n_m", "b1", "b2",
+                                           "n_tri")]
+
+
+class wlc_sizes(ct.Structure):
+    _fields_ = [("n_data", ct.c_int64), ("n_distinct", ct.c_int64), ("n_p", ct.c_int64), ("n_tri", ct.c_int64),
+                ("n_cfg", ct.c_int64), ("n_ell_used", ct.c_int64), ("k_len", ct.c_int64),
+                ("c_elem_bytes", ct.c_size_t), ("ws_run_bytes", ct.c_size_t), ("ws_snr_bytes", ct.c_size_t)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libwlcov.so is not built (run paper_1812_07437_amd.build.build())")
+    L = ct.CDLL(LIB_PATH)
+    vp = ct.c_void_p
+    L.wlc_last_error.restype = ct.c_char_p
+    L.wlc_plan_create.argtypes = [ct.POINTER(wlc_config), ct.POINTER(vp)]
+    L.wlc_plan_destroy.argtypes = [vp]
+    L.wlc_plan_destroy.restype = None
+    L.wlc_plan_sizes.argtypes = [vp, ct.POINTER(wlc_sizes)]
+    L.wlc_plan_index.argtypes = [vp, vp, vp, vp]
+    L.wlc_counts_closed.argtypes = [vp, vp, vp]
+    L.wlc_lattice_counts.argtypes = [vp, vp, vp, vp, vp]
+    L.wlc_run.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp, vp, vp, vp, vp]
+    L.wlc_snr2.argtypes = [vp, vp, vp, vp, vp, ct.POINTER(ct.c_double), vp]
+    return L
+
+
+lib = _load()
+
+EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_counts_closed",
+            "wlc_lattice_counts", "wlc_run", "wlc_snr2", "wlc_last_error"]
+
+
+def wlc_last_error():
+    return lib.wlc_last_error().decode()
+
+
+def _check(rc):
+    if rc != WLC_OK:
+        raise WlcError(rc, wlc_last_error())
+
+
+def wlc_plan_create(cfg: wlc_config):
+    h = ct.c_void_p()
+    _check(lib.wlc_plan_create(ct.byref(cfg), ct.byref(h)))
+    return h
+
+
+def wlc_plan_destroy(plan):
+    lib.wlc_plan_destroy(plan)
+
+
+def wlc_plan_sizes(plan) -> wlc_sizes:
+    s = wlc_sizes()
+    _check(lib.wlc_plan_sizes(plan, ct.byref(s)))
+    return s
+
+
+def wlc_plan_index(plan, tri, rows, distinct):
+    _check(lib.wlc_plan_index(plan, tri, rows, distinct))
+
+
+def wlc_counts_closed(plan, n_modes, n_tri):
+    _check(lib.wlc_counts_closed(plan, n_modes, n_tri))
+
+
+def wlc_lattice_counts(plan, ws, modes, tris, stream):
+    _check(lib.wlc_lattice_counts(plan, ws, modes, tris, stream))
+
+
+def wlc_run(plan, tables: wlc_tables, ws, d, r, C, row_exp2, stream):
+    _check(lib.wlc_run(plan, ct.byref(tables), ws, d, r, C, row_exp2, stream))
+
+
+def wlc_snr2(plan, C, row_exp2, d, ws, stream):
+    out = ct.c_double()
+    _check(lib.wlc_snr2(plan, C, row_exp2, d, ws, ct.byref(out), stream))
+    return out.value
+
+
+# ---------------------------------------------------------------- helpers
+def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False) -> wlc_config:
+    """wlc_config from a dict of scalars (n_z, n_ell, n_chi, n_k, n_m, ell_min,
+    ell_max, f_sky, sigma_eps, n_gal_arcmin2, sigma_b2, k_max, rho_mean and
+    optionally ell_cut)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return wlc_config(n_z=int(cfg["n_z"]), n_ell=int(cfg["n_ell"]), n_chi=int(cfg["n_chi"]), n_k=int(cfg["n_k"]),
+                      n_m=int(cfg["n_m"]), tomo_mode=WLC_TOMO_SORTED if tomo == "sorted" else WLC_TOMO_PAPER,
+                      precision=prec, flags=WLC_FLAG_NOCHECK if nocheck else 0,
+                      ell_min=float(cfg["ell_min"]), ell_max=float(cfg["ell_max"]),
+                      ell_cut=float(cfg.get("ell_cut", 0.0) or 0.0), f_sky=float(cfg["f_sky"]),
+                      sigma_eps=float(cfg["sigma_eps"]), n_gal_arcmin2=float(cfg["n_gal_arcmin2"]),
+                      sigma_b2=float(cfg["sigma_b2"]), k_max=float(cfg["k_max"]), rho_mean=float(cfg["rho_mean"]))
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(stream):
+    return ct.c_void_p(stream.cuda_stream) if stream is not None else None
+
+
+class Problem:
+    """One plan plus device-resident tables, workspace and outputs.
+
+    ``arrays`` maps the table names of wlc_tables (chi, w_chi, k, m, w_m, W, P,
+    u, n_m, optional b1, b2, n_tri) to float64 arrays (numpy or torch)."""
+
+    def __init__(self, cfg: dict, arrays: dict, precision="fp64", tomo="paper", device="cuda:0",
+                 nocheck=False):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.config = make_config(cfg, precision, tomo, nocheck)
+        self.plan = wlc_plan_create(self.config)
+        self.sizes = wlc_plan_sizes(self.plan)
+        self._tabs = {}
+        for name in ("chi", "w_chi", "k", "m", "w_m", "W", "P", "u", "n_m", "b1", "b2", "n_tri"):
+            a = arrays.get(name)
+            if a is None:
+                self._tabs[name] = None
+                continue
+            t = torch.as_tensor(a, dtype=torch.float64).contiguous().to(self.device)
+            self._tabs[name] = t
+        self.tables = wlc_tables(**{k: (_ptr(v) if v is not None else None) for k, v in self._tabs.items()})
+        n = self.sizes.n_data
+        cdt = torch.float64 if self.sizes.c_elem_bytes == 8 else torch.float32
+        self.d = torch.empty(n, dtype=torch.float64, device=self.device)
+        self.r = torch.empty(n, dtype=torch.float64, device=self.device)
+        self.C = torch.empty((n, n), dtype=cdt, device=self.device)
+        self.row_exp2 = torch.empty(n, dtype=torch.int32, device=self.device)
+        self.ws = torch.empty(int(self.sizes.ws_run_bytes), dtype=torch.uint8, device=self.device)
+        self.ws_snr = None
+
+    def close(self):
+        if self.plan:
+            wlc_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, stream=None):
+        wlc_run(self.plan, self.tables, _ptr(self.ws), _ptr(self.d), _ptr(self.r), _ptr(self.C),
+                _ptr(self.row_exp2), _stream_handle(stream))
+
+    def snr2(self, stream=None):
+        if self.ws_snr is None:
+            self.ws_snr = self.torch.empty(int(self.sizes.ws_snr_bytes), dtype=self.torch.uint8, device=self.device)
+        return wlc_snr2(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(self.ws_snr),
+                        _stream_handle(stream))
+
+    def free_snr_workspace(self):
+        self.ws_snr = None
+
+    def covariance_true(self):
+        """C_true = C * 2^-(t_a + t_b) in float64 (host numpy)."""
+        import numpy as np
+        C = self.C.double().cpu().numpy()
+        t = self.row_exp2.cpu().numpy().astype(np.int64)
+        return np.ldexp(C, -(t[:, None] + t[None, :]))
+
+    def index(self):
+        import numpy as np
+        s = self.sizes
+        tri = np.zeros((max(1, s.n_tri), 3), np.int32)
+        rows = np.zeros((s.n_data, 8), np.int32)
+        distinct = np.zeros(s.n_data, np.int32)
+        wlc_plan_index(self.plan, tri.ctypes.data_as(ct.c_void_p), rows.ctypes.data_as(ct.c_void_p),
+                       distinct.ctypes.data_as(ct.c_void_p))
+        return tri[:s.n_tri], rows, distinct
+
+    def lattice_counts(self, stream=None):
+        torch = self.torch
+        modes = torch.zeros(self.sizes.n_ell_used, dtype=torch.int64, device=self.device)
+        tris = torch.zeros(max(1, self.sizes.n_tri), dtype=torch.int64, device=self.device)
+        wlc_lattice_counts(self.plan, _ptr(self.ws), _ptr(modes), _ptr(tris), _stream_handle(stream))
+        return modes, tris[:self.sizes.n_tri]

@@ -1,0 +1,139 @@
+"""Host-side checks of libwlcov: exported symbols, planning and counts against
+the oracle's enumeration, argument validation.  No GPU needed."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+w = pytest.importorskip("paper_1812_07437_amd.wlcov", reason="libwlcov.so not built")
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(wlc_\w+)\s*\(", src, re.M))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert {"wlc_plan_create", "wlc_run", "wlc_snr2", "wlc_lattice_counts"} <= names
+    lib = ct.CDLL(w.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    for n in w.EXPORTED:
+        assert n in names
+
+
+def _plan(preset, tomo="paper", **over):
+    t = dict(synth.PRESETS[preset]) if isinstance(preset, str) else dict(preset)
+    t.update(synth.SURVEY_DEFAULTS)
+    t["rho_mean"] = 0.3 * synth.RHO_CRIT
+    t.update(over)
+    cfg = w.make_config(t, "fp64", tomo)
+    return t, w.wlc_plan_create(cfg)
+
+
+def _index(plan):
+    s = w.wlc_plan_sizes(plan)
+    tri = np.zeros((max(1, s.n_tri), 3), np.int32)
+    rows = np.zeros((s.n_data, 8), np.int32)
+    dist = np.zeros(s.n_data, np.int32)
+    w.wlc_plan_index(plan, tri.ctypes.data_as(ct.c_void_p), rows.ctypes.data_as(ct.c_void_p),
+                     dist.ctypes.data_as(ct.c_void_p))
+    return s, tri[:s.n_tri], rows, dist
+
+
+@pytest.mark.parametrize("preset,tomo", [("tiny", "paper"), ("tiny", "sorted"), ("mid", "paper"),
+                                         ("euclid5", "paper"), ("large10", "paper"), ("large10", "sorted")])
+def test_enumeration_bit_exact_vs_oracle(preset, tomo):
+    t, plan = _plan(preset, tomo)
+    s, tri, rows, dist = _index(plan)
+    _, cen, _ = oracle.ell_bins(t["ell_min"], t["ell_max"], t["n_ell"])
+    ref = oracle.enumerate_rows(t["n_z"], t["n_ell"], cen, tomo)
+    assert s.n_data == len(ref["kind"])
+    assert np.array_equal(tri, np.array([x[:3] for x in ref["triangles"]], np.int32).reshape(-1, 3))
+    assert np.array_equal(rows[:, 0], ref["kind"])
+    assert np.array_equal(rows[:, 1], ref["cfg"])
+    lb = ref["lbin"].copy()
+    lb[ref["kind"] == 2, 1] = lb[ref["kind"] == 2, 0]
+    assert np.array_equal(rows[:, 2:5], lb)
+    assert np.array_equal(rows[:, 5:8], ref["zbin"])
+    # distinct map: same class iff same canonical key, and the distinct
+    # vector is the sorted-tomography vector
+    canon, reps = oracle.canonical_rows(ref)
+    assert s.n_distinct == len(reps)
+    pairs = {}
+    for a, (c, e) in enumerate(zip(canon, dist)):
+        assert pairs.setdefault(int(c), int(e)) == int(e)
+    assert len(set(dist.tolist())) == len(reps)
+    w.wlc_plan_destroy(plan)
+
+
+def test_closed_counts_vs_oracle():
+    t, plan = _plan("euclid5")
+    s = w.wlc_plan_sizes(plan)
+    nm = np.zeros(s.n_ell_used); nt = np.zeros(s.n_tri)
+    w.wlc_counts_closed(plan, nm.ctypes.data_as(ct.c_void_p), nt.ctypes.data_as(ct.c_void_p))
+    _, cen, wid = oracle.ell_bins(t["ell_min"], t["ell_max"], t["n_ell"])
+    assert np.allclose(nm, oracle.n_modes(cen, wid, t["f_sky"]), rtol=1e-14)
+    want = [oracle.n_tri_closed(cen[i], cen[j], cen[k], wid[i], wid[j], wid[k], t["f_sky"])
+            for (i, j, k, _) in oracle.triangles(cen)]
+    # Lambda^2 cancels for near-flat triangles: allow the amplified rounding
+    assert np.allclose(nt, want, rtol=1e-11)
+    w.wlc_plan_destroy(plan)
+
+
+def test_ell_cut_plan():
+    t, plan = _plan("large10", ell_cut=1000.0)
+    s = w.wlc_plan_sizes(plan)
+    assert s.n_ell_used == 11
+    _, cen, _ = oracle.ell_bins(10.0, 5000.0, 15)
+    ref = oracle.enumerate_rows(10, 11, cen)
+    assert s.n_data == len(ref["kind"])
+    w.wlc_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("bad", [dict(n_z=0), dict(ell_min=-1.0), dict(f_sky=1.5), dict(k_max=0.0),
+                                 dict(ell_cut=5.0), dict(n_k=1)])
+def test_invalid_config_rejected(bad):
+    t = dict(synth.PRESETS["tiny"]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 1e11
+    t.update(bad)
+    cfg = w.make_config(t)
+    with pytest.raises(w.WlcError) as e:
+        w.wlc_plan_create(cfg)
+    assert e.value.code == w.WLC_EINVAL
+    assert w.wlc_last_error()
+
+
+def test_null_arguments_rejected():
+    _, plan = _plan("tiny")
+    tabs = w.wlc_tables()
+    with pytest.raises(w.WlcError) as e:
+        w.wlc_run(plan, tabs, None, None, None, None, None, None)
+    assert e.value.code == w.WLC_EINVAL
+    with pytest.raises(w.WlcError):
+        w.wlc_snr2(plan, None, None, None, None, None)
+    w.wlc_plan_destroy(plan)
+
+
+def test_workspace_sizes_cover_buffers():
+    for prec, el in (("fp64", 8), ("bf16x3", 4)):
+        t = dict(synth.PRESETS["large10"]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 1e11
+        p = w.wlc_plan_create(w.make_config(t, prec))
+        s = w.wlc_plan_sizes(p)
+        assert s.c_elem_bytes == el
+        r_pad = -(-s.n_distinct // 128) * 128
+        a_bytes = r_pad * s.k_len * (8 if prec == "fp64" else 4)
+        assert s.ws_run_bytes > a_bytes + r_pad * r_pad * el
+        assert s.ws_snr_bytes >= (s.n_data + 1) ** 2 * 8
+        w.wlc_plan_destroy(p)

@@ -1,0 +1,159 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_07437_amd import wlcov
+    return wlcov
+
+
+_ORACLE = {}
+
+
+def _oracle_full(preset, tomo="paper", **kw):
+    key = (preset, tomo, tuple(sorted(kw.items())))
+    if key not in _ORACLE:
+        t = synth.make_tables(preset, **kw)
+        o = oracle.Oracle(t, tomo=tomo)
+        _ORACLE[key] = (t, o, o.run())
+    return _ORACLE[key]
+
+
+def _run(wl, t, precision="fp64", tomo="paper", snr=True):
+    prob = wl.Problem(t.cfg, t.arrays(), precision=precision, tomo=tomo)
+    prob.run()
+    s = prob.snr2() if snr else None
+    torch.cuda.synchronize()
+    return prob, s
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b) / np.abs(b))
+
+
+@pytest.mark.parametrize("preset,tomo", [("tiny", "paper"), ("tiny", "sorted"), ("mid", "paper")])
+def test_fp64_full_parity(wl, preset, tomo):
+    _say("case fp64 full %s %s" % (preset, tomo))
+    t, o, ref = _oracle_full(preset, tomo)
+    prob, snr2 = _run(wl, t, "fp64", tomo)
+    d = prob.d.cpu().numpy(); r = prob.r.cpu().numpy()
+    assert _rel(d, ref["d"]) < 1e-10
+    assert _rel(r, o.data_vector()[1]) < 1e-10
+    C = prob.covariance_true()
+    assert _rel(C, ref["C"]) < 1e-10
+    Cs = prob.C.cpu().numpy()
+    assert np.array_equal(Cs, Cs.T)
+    dg = np.diag(Cs)
+    assert np.all((dg >= 1.0) & (dg < 4.0))
+    assert abs(snr2 - ref["snr2"]) / ref["snr2"] < 1e-10
+    prob.close()
+
+
+def test_fp64_deterministic(wl):
+    _say("case fp64 determinism mid")
+    t = synth.make_tables("mid")
+    a, sa = _run(wl, t, "fp64")
+    b, sb = _run(wl, t, "fp64")
+    assert torch.equal(a.C, b.C) and torch.equal(a.d, b.d) and sa == sb
+
+
+def test_fp64_euclid5_sampled(wl):
+    """Full-size 5-bin workload (N = 4550, K = 32768): data vector and response
+    entirely, covariance on seeded samples including the diagonal."""
+    _say("case fp64 euclid5 sampled")
+    t = synth.make_tables("euclid5")
+    o = oracle.Oracle(t)
+    prob, _ = _run(wl, t, "fp64", snr=False)
+    d_ref, r_ref = o.data_vector()
+    assert _rel(prob.d.cpu().numpy(), d_ref) < 1e-10
+    assert _rel(prob.r.cpu().numpy(), r_ref) < 1e-10
+    pairs = np.concatenate([synth.sample_pairs(o.N, 1500, seed=42),
+                            np.stack([np.arange(0, o.N, 7)] * 2, 1)])
+    want = o.cov_pairs(pairs)
+    C = prob.covariance_true()
+    got = C[pairs[:, 0], pairs[:, 1]]
+    assert _rel(got, want) < 1e-10
+    Cs = prob.C
+    assert torch.equal(Cs, Cs.T)
+    prob.close()
+
+
+@pytest.mark.parametrize("precision,tol_diag,tol_snr", [("bf16x3", 1e-5, 1e-4), ("fp32", 1e-5, 1e-4),
+                                                        ("bf16", 5e-3, 5e-2)])
+def test_mixed_precision_tiny_mid(wl, precision, tol_diag, tol_snr):
+    for preset in ("tiny", "mid"):
+        _say("case mixed %s %s" % (precision, preset))
+        t, o, ref = _oracle_full(preset)
+        prob, snr2 = _run(wl, t, precision)
+        C = prob.covariance_true()
+        dg = np.diag(C); dr = np.diag(ref["C"])
+        err_diag = _rel(dg, dr)
+        s = np.sqrt(np.outer(dr, dr))
+        err_off = np.max(np.abs(C - ref["C"]) / s)
+        err_snr = abs(snr2 - ref["snr2"]) / ref["snr2"]
+        _say("  %s %s: diag %.2e offdiag/sqrt(CaaCbb) %.2e snr %.2e" % (precision, preset, err_diag, err_off,
+                                                                      err_snr))
+        assert err_diag < tol_diag
+        assert err_snr < tol_snr
+        assert _rel(prob.d.cpu().numpy(), ref["d"]) < 1e-10
+        prob.close()
+
+
+def test_validation_errors(wl):
+    _say("case validation errors")
+    t = synth.make_tables("tiny")
+    arr = t.arrays()
+    bad = dict(arr); P = arr["P"].copy(); P[3, 7] = np.nan; bad["P"] = P
+    prob = wl.Problem(t.cfg, bad, "fp64")
+    with pytest.raises(wl.WlcError) as e:
+        prob.run()
+    assert e.value.code == wl.WLC_EINVAL
+    short = dict(arr); short["k"] = arr["k"] * 3.0
+    prob = wl.Problem(t.cfg, short, "fp64")
+    with pytest.raises(wl.WlcError) as e:
+        prob.run()
+    assert e.value.code == wl.WLC_ERANGE
+
+
+def test_lattice_counts_bruteforce(wl):
+    """Integer lattice counts bit-exact against pair-by-pair counting on a
+    coarse lattice (small sky fraction) and on the first triangles of the
+    tiny workload."""
+    _say("case lattice coarse")
+    t = synth.make_tables("tiny", f_sky=0.01)
+    prob = wl.Problem(t.cfg, t.arrays(), "fp64")
+    modes, tris = prob.lattice_counts()
+    torch.cuda.synchronize()
+    o = oracle.Oracle(t)
+    thr = oracle.lattice_thresholds(o.edges, 0.01)
+    assert [oracle.lattice_modes(thr, b) for b in range(o.n_ell)] == modes.cpu().tolist()
+    want = [oracle.lattice_triangles(thr, i, j, k) for (i, j, k, _) in o.tris]
+    assert tris.cpu().tolist() == want
+    _say("case lattice tiny")
+    t = synth.make_tables("tiny")
+    prob = wl.Problem(t.cfg, t.arrays(), "fp64")
+    modes, tris = prob.lattice_counts()
+    torch.cuda.synchronize()
+    o = oracle.Oracle(t)
+    thr = oracle.lattice_thresholds(o.edges, t.cfg["f_sky"])
+    assert [oracle.lattice_modes(thr, b) for b in range(o.n_ell)] == modes.cpu().tolist()
+    for q, (i, j, k, _) in enumerate(o.tris[:4]):
+        assert int(tris[q]) == oracle.lattice_triangles(thr, i, j, k)
