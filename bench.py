@@ -1,0 +1,220 @@
+"""Benchmark of the weak-lensing P+B covariance hot path on one MI355X.
+
+One step = one pass of the whole path over the synthetic workload: wlc_run
+(enumeration upload, table staging, halo-model quadrature and Limber
+projection, A-build, one-halo Gram product, covariance assembly) followed by
+wlc_snr2 (FP64 bordered Cholesky and S/N).  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload large10|euclid5]
+                  [--precision bf16x3|bf16|fp32|fp64] [--fp64-steps S] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large10")
+    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def gram_flops(n_r, k_len, precision):
+    """Useful flops of the one-halo Gram: each of the n_r (n_r + 1)/2 distinct
+    entries is a length-K dot product (2K flops); the split bf16 product does
+    three MFMA products per entry."""
+    f = n_r * (n_r + 1) * k_len
+    return f * (3 if precision == "bf16x3" else 1)
+
+
+def timed_steps(prob, steps, warmup, torch, wl):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        prob.run(stream)
+        prob.snr2(stream)
+    torch.cuda.synchronize()
+    wl.wlc_plan_set_timing(prob.plan, True)
+    phases = {p: 0.0 for p in wl.PHASES}
+    upd = dict(ms=0.0, launches=0, timed=0, flops=0.0)
+    t_snr = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.run(stream)
+        s = prob.snr2(stream)
+        t_snr.append(s)
+        ph = wl.wlc_plan_timings(prob.plan)
+        for k, v in ph.items():
+            phases[k] += v
+        ks = wl.wlc_plan_kernel_stats(prob.plan)
+        for k in upd:
+            upd[k] += ks[k]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    wl.wlc_plan_set_timing(prob.plan, False)
+    upd = {k: v / steps for k, v in upd.items()}
+    return dt, {k: v / steps for k, v in phases.items()}, t_snr, upd
+
+
+def cpu_baseline(tables, seconds, n_data):
+    """The oracle as it stands on the host cores: data vector for every row,
+    then covariance entries on seeded row pairs, as many as fit in the time
+    budget; entries/s from the pairs, with the data-vector time amortised the
+    way one step amortises it."""
+    import numpy as np
+    import oracle
+    import synth
+    o = oracle.Oracle(tables)
+    t0 = time.perf_counter()
+    o.data_vector()
+    o.u_table()
+    t_setup = time.perf_counter() - t0
+    n = 64
+    done, t_pairs = 0, 0.0
+    while t_pairs < seconds and done < 10 ** 7:
+        pairs = synth.sample_pairs(o.N, n, seed=100 + done)
+        t1 = time.perf_counter()
+        o.cov_pairs(pairs)
+        t_pairs += time.perf_counter() - t1
+        done += n
+        n = min(n * 2, 1 << 16)
+    per_entry = t_pairs / done
+    total = n_data * (n_data + 1) / 2
+    est_step = t_setup + per_entry * total
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=total / est_step, unit="cov entries/s", cores=cores, kind="oracle",
+                sample="data vector + %d seeded covariance entries (%.1f s); S/N Cholesky not included" %
+                (done, t_setup + t_pairs))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1812_07437_amd import wlcov as wl
+
+    log("building %s tables" % args.workload)
+    t = synth.make_tables(args.workload)
+    cfg = t.cfg
+    prob = wl.Problem(cfg, t.arrays(), precision=args.precision, device="cuda:0")
+    s = prob.sizes
+    N, NR, K = s.n_data, s.n_distinct, s.k_len
+    log("N=%d N_R=%d K=%d precision=%s" % (N, NR, K, args.precision))
+    dt, ph, snrs, upd = timed_steps(prob, args.steps, args.warmup, torch, wl)
+    ms_step = dt / args.steps * 1e3
+    entries = N * (N + 1) / 2
+    value = entries / (dt / args.steps)
+    log("mixed: %.1f ms/step  phases %s  snr2 %.6e" % (ms_step, {k: round(v, 2) for k, v in ph.items()}, snrs[-1]))
+
+    d_mixed = prob.C.diagonal().double().cpu().numpy()
+    t_mixed = prob.row_exp2.cpu().numpy().astype(np.int64)
+    diag_mixed = np.ldexp(d_mixed, -2 * t_mixed)
+    snr_mixed = snrs[-1]
+    del prob
+    torch.cuda.empty_cache()
+
+    # plain FP64 GPU path on the same workload (reference for accuracy and speedup)
+    fp64 = None
+    if args.fp64_steps > 0 and args.precision != "fp64":
+        log("fp64 path")
+        p64 = wl.Problem(cfg, t.arrays(), precision="fp64", device="cuda:0")
+        dt64, ph64, snr64, _ = timed_steps(p64, args.fp64_steps, 0, torch, wl)
+        d64 = p64.C.diagonal().cpu().numpy()
+        t64 = p64.row_exp2.cpu().numpy().astype(np.int64)
+        diag64 = np.ldexp(d64, -2 * t64)
+        err_diag = float(np.max(np.abs(diag_mixed - diag64) / diag64))
+        err_snr = float(abs(snr_mixed - snr64[-1]) / snr64[-1])
+        fp64 = dict(ms_per_step=dt64 / args.fp64_steps * 1e3, value=entries / (dt64 / args.fp64_steps),
+                    phases_ms=ph64, speedup_step=(dt64 / args.fp64_steps) / (dt / args.steps),
+                    speedup_gram=ph64["gram"] / max(ph["gram"], 1e-9),
+                    gram_tflops=gram_flops(NR, K, "fp64") / (ph64["gram"] * 1e-3) / 1e12,
+                    err_vs_fp64={"diag_max_rel": err_diag, "snr2_rel": err_snr})
+        log("fp64: %.1f ms/step  gram %.1f ms  diag err %.2e  snr err %.2e" % (fp64["ms_per_step"], ph64["gram"],
+                                                                           err_diag, err_snr))
+        del p64
+        torch.cuda.empty_cache()
+
+    # roofline of the dominant kernel of the step: the one-halo Gram (one
+    # launch per step) or the Cholesky block update (many launches per step,
+    # timed one by one with HIP events on the run's stream)
+    gram_tf = gram_flops(NR, K, args.precision) / (ph["gram"] * 1e-3) / 1e12
+    chol_flops = N ** 3 / 3.0
+    chol_tf = chol_flops / (ph["chol"] * 1e-3) / 1e12
+    upd_frac_timed = upd["timed"] / max(upd["launches"], 1)
+    upd_ms = upd["ms"] / max(upd_frac_timed, 1e-9)
+    upd_tf = upd["flops"] / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
+    if upd_ms >= ph["gram"]:
+        roof = dict(bound="mfma", kernel="k_update2 (FP64 Cholesky block update, incl. split-k reduce)",
+                    achieved=upd_tf, peak=PEAK_TFLOPS["fp64"], unit="TFLOP/s", frac=upd_tf / PEAK_TFLOPS["fp64"],
+                    traffic=None, launches=upd["launches"], avg_launch_ms=upd_ms / max(upd["launches"], 1),
+                    flops_per_step=upd["flops"])
+    else:
+        roof = dict(bound="mfma", kernel="k_gram_bf16<x3> (one-halo Gram)", achieved=gram_tf,
+                    peak=PEAK_TFLOPS[args.precision], unit="TFLOP/s", frac=gram_tf / PEAK_TFLOPS[args.precision],
+                    traffic=None, launches=1, avg_launch_ms=ph["gram"],
+                    flops_per_step=gram_flops(NR, K, args.precision))
+    a_bytes = NR * K * {"bf16": 2, "bf16x3": 4, "fp32": 4, "fp64": 8}[args.precision]
+    c_bytes = N * N * (8 if args.precision == "fp64" else 4)
+    kernels = dict(
+        gram=dict(ms=ph["gram"], tflops=gram_tf, frac_peak=gram_tf / PEAK_TFLOPS[args.precision]),
+        abuild=dict(ms=ph["abuild"], gbs=a_bytes / (ph["abuild"] * 1e-3) / 1e9,
+                    frac_hbm=a_bytes / (ph["abuild"] * 1e-3) / 1e9 / HBM_PEAK_GBS),
+        assemble=dict(ms=ph["assemble"], gbs=c_bytes / (ph["assemble"] * 1e-3) / 1e9,
+                      frac_hbm=c_bytes / (ph["assemble"] * 1e-3) / 1e9 / HBM_PEAK_GBS),
+        chol=dict(ms=ph["chol"], tflops=chol_tf, frac_peak=chol_tf / PEAK_TFLOPS["fp64"]),
+        chol_update=dict(ms=upd_ms, launches=upd["launches"], tflops=upd_tf, frac_peak=upd_tf / PEAK_TFLOPS["fp64"]),
+    )
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle, ~%.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(t, args.cpu_seconds, N)
+
+    out = {
+        "metric": "cov entries/s (joint P+B covariance incl. S/N) + %MFMA peak, mixed vs plain FP64",
+        "value": value, "unit": "cov entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": "%s: n_z=%d, %d ell-bins %g-%g, N_chi=%d, N_M=%d (K=%d), N=%d, N_R=%d" %
+                   (args.workload, cfg["n_z"], cfg["n_ell"], cfg["ell_min"], cfg["ell_max"], cfg["n_chi"],
+                    cfg["n_m"], K, N, NR), "precision": args.precision, "parallelism": "none (1 GPU)"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "phases_ms": ph,
+        "kernels": kernels,
+        "distinct_entries_per_s": NR * (NR + 1) / 2 / (dt / args.steps),
+        "snr": math.sqrt(snr_mixed) if snr_mixed > 0 else None,
+        "fp64_path": fp64,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

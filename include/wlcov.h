@@ -169,6 +169,30 @@ int wlc_run(wlc_plan plan, const wlc_tables *tables, void *ws, double *d, double
 int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
              double *snr2_host, void *stream);
 
+/* ---- phase timing (per-plan HIP events; not for plans shared by concurrent runs)
+ * With timing enabled, wlc_run and wlc_snr2 record a HIP event pair on their
+ * stream around each phase; wlc_plan_timings synchronises on them and writes
+ * the last recorded duration of every phase in milliseconds (0 if it did not
+ * run) into ms[WLC_PHASE_COUNT] (HOST). */
+enum {
+  WLC_PHASE_TABLES = 0,  /* validation, staging, spectra, projection, Gram factor */
+  WLC_PHASE_ABUILD = 1,  /* A rows in the Gram precision                           */
+  WLC_PHASE_GRAM = 2,    /* one-halo Gram product (and its split-K reduction)      */
+  WLC_PHASE_ASSEMBLE = 3,/* row exponents and covariance assembly                  */
+  WLC_PHASE_SNR_PREP = 4,/* bordered FP64 matrix from C and d                      */
+  WLC_PHASE_CHOL = 5,    /* blocked Cholesky and y^T y                             */
+  WLC_PHASE_COUNT = 6
+};
+int wlc_plan_set_timing(wlc_plan plan, int enable);
+int wlc_plan_timings(wlc_plan plan, float *ms);
+/* Launch statistics of the Cholesky block-update kernel (k_update2 and its
+ * split-k reduction) in the last timed wlc_snr2, into HOST scalars: summed
+ * event time of the timed launches, number of launches, number timed (event
+ * capacity permitting; the time covers only those), and the algorithmic
+ * flops of all launches (2 k per updated lower-triangle entry).  Synchronises
+ * on the events. */
+int wlc_plan_kernel_stats(wlc_plan plan, double *ms_total, int64_t *launches, int64_t *timed, double *flops);
+
 const char *wlc_last_error(void);
 
 #ifdef __cplusplus

@@ -6,13 +6,44 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "plan.h"
 
 struct wlc_plan_s {
   wlc::Plan p;
+  // phase timing (HIP events recorded on the run's stream)
+  bool timing = false;
+  bool events_ready = false;
+  bool recorded[WLC_PHASE_COUNT] = {};
+  hipEvent_t ev[2 * WLC_PHASE_COUNT] = {};
+  // per-launch events of the Cholesky trailing-update kernel
+  std::vector<hipEvent_t> upd_ev;
+  wlc::KernelProbe probe;
+  bool probe_valid = false;
+  ~wlc_plan_s() {
+    if (events_ready)
+      for (auto &e : ev) (void)hipEventDestroy(e);
+    for (auto &e : upd_ev) (void)hipEventDestroy(e);
+  }
 };
+
+namespace {
+struct PhaseTimer {
+  wlc_plan_s *h;
+  hipStream_t s;
+  void begin(int ph) {
+    if (h->timing && h->events_ready) (void)hipEventRecord(h->ev[2 * ph], s);
+  }
+  void end(int ph) {
+    if (h->timing && h->events_ready) {
+      (void)hipEventRecord(h->ev[2 * ph + 1], s);
+      h->recorded[ph] = true;
+    }
+  }
+};
+}  // namespace
 
 namespace wlc {
 
@@ -79,7 +110,7 @@ static int64_t snr_ld(int64_t n) { return round_up(n + 1, 8); }
 
 static size_t snr_bytes(const Plan &p) {
   const int64_t n = p.n_out, ld = snr_ld(n);
-  return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(64 * 64 * 8, 256) + 256 + 256;
+  return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(chol_scratch_bytes(), 256) + 256 + 256;
 }
 
 static void finish_sizes(Plan &p) {
@@ -138,6 +169,59 @@ using namespace wlc;
 extern "C" {
 
 const char *wlc_last_error(void) { return last_error(); }
+
+int wlc_plan_set_timing(wlc_plan plan, int enable) {
+  if (!plan) return fail(WLC_EINVAL, "null plan");
+  if (enable && !plan->events_ready) {
+    for (auto &e : plan->ev) {
+      int rc = hip_check(hipEventCreate(&e), "event create");
+      if (rc) return rc;
+    }
+    // two events per trailing-update launch: about 5 launches per 256 columns
+    const int64_t launches = 5 * ((plan->p.n_out + 255) / 256) + 16;
+    plan->upd_ev.resize((size_t)std::min<int64_t>(2 * launches, 16384));
+    for (auto &e : plan->upd_ev) {
+      int rc = hip_check(hipEventCreate(&e), "event create");
+      if (rc) return rc;
+    }
+    plan->events_ready = true;
+  }
+  plan->timing = enable != 0;
+  return WLC_OK;
+}
+
+int wlc_plan_kernel_stats(wlc_plan plan, double *ms_total, int64_t *launches, int64_t *timed, double *flops) {
+  if (!plan || !ms_total || !launches || !timed || !flops) return fail(WLC_EINVAL, "null argument");
+  *ms_total = 0.0;
+  *launches = 0;
+  *timed = 0;
+  *flops = 0.0;
+  if (!plan->probe_valid) return WLC_OK;
+  const KernelProbe &pr = plan->probe;
+  for (int q = 0; q < pr.count; ++q) {
+    float m = 0.0f;
+    int rc = hip_check(hipEventSynchronize(pr.ev[2 * q + 1]), "event sync");
+    if (!rc) rc = hip_check(hipEventElapsedTime(&m, pr.ev[2 * q], pr.ev[2 * q + 1]), "event time");
+    if (rc) return rc;
+    *ms_total += m;
+  }
+  *launches = pr.launches;
+  *timed = pr.count;
+  *flops = pr.flops;
+  return WLC_OK;
+}
+
+int wlc_plan_timings(wlc_plan plan, float *ms) {
+  if (!plan || !ms) return fail(WLC_EINVAL, "null argument");
+  for (int ph = 0; ph < WLC_PHASE_COUNT; ++ph) {
+    ms[ph] = 0.0f;
+    if (!plan->events_ready || !plan->recorded[ph]) continue;
+    int rc = hip_check(hipEventSynchronize(plan->ev[2 * ph + 1]), "event sync");
+    if (!rc) rc = hip_check(hipEventElapsedTime(&ms[ph], plan->ev[2 * ph], plan->ev[2 * ph + 1]), "event time");
+    if (rc) return rc;
+  }
+  return WLC_OK;
+}
 
 int wlc_plan_create(const wlc_config *cfg, wlc_plan *out) {
   if (!cfg || !out) return fail(WLC_EINVAL, "null argument");
@@ -233,6 +317,9 @@ int wlc_run(wlc_plan plan, const wlc_tables *tb, void *ws, double *d, double *r,
 
   DevTables T{tb->chi, tb->w_chi, tb->k, tb->m, tb->w_m, tb->W, tb->P, tb->u, tb->n_m, tb->b1, tb->b2,
               c.n_z, c.n_chi, c.n_k, c.n_m, c.rho_mean, c.k_max};
+  PhaseTimer tm{plan, s};
+  for (int ph = WLC_PHASE_TABLES; ph <= WLC_PHASE_ASSEMBLE; ++ph) plan->recorded[ph] = false;
+  tm.begin(WLC_PHASE_TABLES);
   const double *cent = at<double>(ws, L, B_CENT);
   int32_t *flags = at<int32_t>(ws, L, B_FLAGS);
   if (!(c.flags & WLC_FLAG_NOCHECK)) {
@@ -261,13 +348,18 @@ int wlc_run(wlc_plan plan, const wlc_tables *tb, void *ws, double *d, double *r,
   launch_ps(dR, Ps, p.n_ell, c.n_z, p.noise, s);
   launch_gfactor(T, cfgT, n_cfg, U, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
+  tm.end(WLC_PHASE_TABLES);
 
   const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
   void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
+  tm.begin(WLC_PHASE_ABUILD);
   launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, A0, A1, s);
+  tm.end(WLC_PHASE_ABUILD);
   GramShape g{p.r_pad, p.k_pad, p.r_pad};
   void *Gm = at<void>(ws, L, B_GM);
+  tm.begin(WLC_PHASE_GRAM);
   launch_gram(gram_prec(c.precision), g, A0, A1, Gm, at<void>(ws, L, B_PART), s);
+  tm.end(WLC_PHASE_GRAM);
 
   AsmArgs a{};
   a.rowO = at<int32_t>(ws, L, B_ROWO);
@@ -287,8 +379,10 @@ int wlc_run(wlc_plan plan, const wlc_tables *tb, void *ws, double *d, double *r,
   a.omega = p.omega;
   a.inv_omega = 1.0 / p.omega;
   a.sigma_b2 = c.sigma_b2;
+  tm.begin(WLC_PHASE_ASSEMBLE);
   launch_rowexp(a, row_exp2, d, r, s);
   launch_assemble(a, row_exp2, C, c.precision != WLC_FP64, s);
+  tm.end(WLC_PHASE_ASSEMBLE);
   return hip_check(hipGetLastError(), "wlc_run launch");
 }
 
@@ -302,15 +396,29 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
   char *base = static_cast<char *>(ws);
   double *Wm = reinterpret_cast<double *>(base);
   size_t o = align_up((size_t)(n + 1) * ld * 8, 256);
-  double *Linv = reinterpret_cast<double *>(base + o);
-  o += align_up(64 * 64 * 8, 256);
+  double *scratch = reinterpret_cast<double *>(base + o);
+  o += align_up(chol_scratch_bytes(), 256);
   int32_t *flag = reinterpret_cast<int32_t *>(base + o);
   o += 256;
   double *out = reinterpret_cast<double *>(base + o);
+  PhaseTimer tm{plan, s};
+  plan->recorded[WLC_PHASE_SNR_PREP] = plan->recorded[WLC_PHASE_CHOL] = false;
+  tm.begin(WLC_PHASE_SNR_PREP);
   launch_fill_i32(flag, 1, 0, s);
   launch_chol_prep(C, p.cfg.precision != WLC_FP64, row_exp2, d, n, ld, Wm, s);
-  chol_factor(Wm, n, ld, Linv, flag, s);
+  tm.end(WLC_PHASE_SNR_PREP);
+  tm.begin(WLC_PHASE_CHOL);
+  KernelProbe *probe = nullptr;
+  if (plan->timing && plan->events_ready) {
+    plan->probe = KernelProbe{};
+    plan->probe.ev = plan->upd_ev.data();
+    plan->probe.cap = (int)plan->upd_ev.size() / 2;
+    probe = &plan->probe;
+    plan->probe_valid = true;
+  }
+  chol_factor(Wm, n, ld, scratch, flag, s, probe);
   launch_sumsq_row(Wm, n, ld, out, s);
+  tm.end(WLC_PHASE_CHOL);
   int rc = hip_check(hipGetLastError(), "wlc_snr2 launch");
   if (rc) return rc;
   struct { int32_t flag; int32_t pad; double v; } h{};

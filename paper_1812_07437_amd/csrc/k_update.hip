@@ -1,0 +1,175 @@
+// Block update of the FP64 Cholesky factorisation:
+//   W[i][j] -= sum_{q in [k0, k1)} W[i][q] W[j][q],  i in [c0, r1), j in [c0, c1), i >= j,
+// on 128 x 128 tiles.  Four wavefronts of 64 x 64 each on v_mfma_f64_16x16x4
+// (lane l holds row l % 16, k l / 16 of each operand; the accumulator value v
+// of lane l is row l / 16 + 4 v, column l % 16).  Operand slices are staged
+// through LDS in 16-wide k steps with the next step prefetched into
+// registers.  A long k range may be split into slices whose partial products
+// go to a scratch buffer and are subtracted in a fixed order by a second
+// kernel, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace wlc {
+
+constexpr int UT2 = 128;
+constexpr int UBK = 16;
+constexpr int ULDR = UBK + 1;
+
+__device__ __forceinline__ void tile_of(int64_t t, int tri, int64_t tcols, int64_t &ti, int64_t &tj) {
+  if (tri) {
+    int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    ti = i;
+    tj = t - i * (i + 1) / 2;
+  } else {
+    ti = t / tcols;
+    tj = t % tcols;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_update2(double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1,
+                                                 int64_t c1, int64_t k0, int64_t k1, int tri_grid, int64_t tcols,
+                                                 int n_split, int64_t k_split, double *__restrict__ part) {
+  __shared__ double lds[2][UT2 * ULDR];
+  int64_t ti, tj;
+  tile_of(blockIdx.x / n_split, tri_grid, tcols, ti, tj);
+  const int split = blockIdx.x % n_split;
+  const int64_t i0 = c0 + ti * UT2, j0 = c0 + tj * UT2;
+  if (j0 > i0 + UT2 - 1) return;  // entirely above the diagonal
+  const int64_t kb = k0 + (int64_t)split * k_split;
+  const int64_t ke = min(k1, kb + k_split);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // 128 rows x 16 k per side = 1024 double2 chunks, 4 per thread
+  double2 pre[2][4];
+  auto gload = [&](int64_t kq) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int64_t base = side == 0 ? i0 : j0;
+      const int64_t lim = side == 0 ? r1 : c1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ch = tid + 256 * q;
+        const int r = ch >> 3, c = ch & 7;
+        const int64_t row = base + r, k = kq + 2 * c;
+        double2 v = make_double2(0.0, 0.0);
+        if (row < lim) {
+          const double *src = Wm + row * ld + k;
+          if (k + 1 < ke) v = *(const double2 *)src;
+          else if (k < ke) v.x = src[0];
+        }
+        pre[side][q] = v;
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ch = tid + 256 * q;
+        const int r = ch >> 3, c = ch & 7;
+        lds[side][r * ULDR + 2 * c] = pre[side][q].x;
+        lds[side][r * ULDR + 2 * c + 1] = pre[side][q].y;
+      }
+  };
+
+  if (kb < ke) gload(kb);
+  for (int64_t kq = kb; kq < ke; kq += UBK) {
+    __syncthreads();
+    lstore();
+    __syncthreads();
+    if (kq + UBK < ke) gload(kq + UBK);
+#pragma unroll
+    for (int kk = 0; kk < UBK; kk += 4) {
+      const int kc = kk + (lane >> 4);
+      double a[4], b[4];
+#pragma unroll
+      for (int blk = 0; blk < 4; ++blk) {
+        a[blk] = lds[0][(wr + blk * 16 + (lane & 15)) * ULDR + kc];
+        b[blk] = lds[1][(wc + blk * 16 + (lane & 15)) * ULDR + kc];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+  }
+  const int64_t pc = c1 - c0;
+  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pc : nullptr;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + wr + x * 16 + (lane >> 4) + 4 * v;
+        const int64_t j = j0 + wc + y * 16 + (lane & 15);
+        if (i < r1 && j < c1 && i >= j) {
+          if (pdst) pdst[(i - c0) * pc + (j - c0)] = acc[x][y][v];
+          else Wm[i * ld + j] -= acc[x][y][v];
+        }
+      }
+}
+
+// W[i][j] -= sum_s part[s][i - c0][j - c0] for the lower part of the block.
+__global__ void k_update_reduce(double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int n_split,
+                                const double *__restrict__ part) {
+  const int64_t pc = c1 - c0, rows = r1 - c0;
+  const int64_t total = rows * pc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = c0 + e / pc, j = c0 + e % pc;
+    if (i < j) continue;
+    double s = part[e];
+    for (int q = 1; q < n_split; ++q) s += part[q * total + e];
+    Wm[i * ld + j] -= s;
+  }
+}
+
+void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1,
+                    double *part, hipStream_t s, KernelProbe *probe) {
+  if (c0 >= c1 || c0 >= r1 || k0 >= k1) return;
+  const bool timed = probe && probe->ev && probe->count < probe->cap;
+  if (probe) {
+    const double cols = (double)(c1 - c0);
+    const double lower = cols * (double)r1 - (double)(c0 + c1 - 1) * cols / 2.0;  // entries with i >= j
+    probe->flops += 2.0 * lower * (double)(k1 - k0);
+    ++probe->launches;
+  }
+  if (timed) (void)hipEventRecord(probe->ev[2 * probe->count], s);
+  const int64_t tr = (r1 - c0 + UT2 - 1) / UT2, tc = (c1 - c0 + UT2 - 1) / UT2;
+  const int tri = tr == tc;
+  const int64_t tiles = tri ? tr * (tr + 1) / 2 : tr * tc;
+  // split the k range when the tiles alone cannot fill the chip, keeping at
+  // least 512 k per slice and the scratch (slices x rows x 256 doubles)
+  // within what chol_scratch_bytes() reserves
+  int ns = 1;
+  if (part && c1 - c0 <= 256) {
+    const int64_t ksteps = (k1 - k0 + UBK - 1) / UBK;
+    while (ns < 64 && tiles * ns < 1024 && ksteps / (2 * ns) >= 32 &&
+           (int64_t)(2 * ns) * (r1 - c0) <= chol_part_rows())
+      ns *= 2;
+  }
+  const int64_t ksplit = ((k1 - k0 + UBK - 1) / UBK + ns - 1) / ns * UBK;
+  hipLaunchKernelGGL(k_update2, dim3((unsigned)(tiles * ns)), dim3(256), 0, s, Wm, ld, c0, r1, c1, k0, k1, tri, tc, ns,
+                     ksplit, part);
+  if (ns > 1) {
+    const int64_t total = (r1 - c0) * (c1 - c0);
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_update_reduce, dim3(g), dim3(256), 0, s, Wm, ld, c0, r1, c1, ns, part);
+  }
+  if (timed) (void)hipEventRecord(probe->ev[2 * probe->count++ + 1], s);
+}
+
+}  // namespace wlc

@@ -58,7 +58,23 @@ void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f
 // ---- signal-to-noise (k_chol.hip)
 void launch_chol_prep(const void *C, int c_f32, const int32_t *row_exp2, const double *d, int64_t n, int64_t ld,
                       double *Wm, hipStream_t s);
-int chol_factor(double *Wm, int64_t n, int64_t ld, double *Linv, int *flag, hipStream_t s);
+// Optional per-launch timing of the trailing-update kernel: event pairs are
+// recorded around each launch while count < cap; flops accumulates the
+// algorithmic flops of every launch.
+struct KernelProbe {
+  hipEvent_t *ev = nullptr;
+  int cap = 0;
+  int count = 0;
+  int64_t launches = 0;
+  double flops = 0.0;
+};
+int chol_factor(double *Wm, int64_t n, int64_t ld, double *scratch, int *flag, hipStream_t s,
+                KernelProbe *probe = nullptr);
+size_t chol_scratch_bytes();
+int64_t chol_part_rows();
+// part: split-k scratch (NULL: no split)
+void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1,
+                    double *part, hipStream_t s, KernelProbe *probe = nullptr);
 void launch_sumsq_row(const double *Wm, int64_t n, int64_t ld, double *out, hipStream_t s);
 
 // ---- lattice counts (k_lattice.hip); thr_max = largest threshold used

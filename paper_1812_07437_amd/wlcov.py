@@ -59,13 +59,34 @@ def _load():
     L.wlc_lattice_counts.argtypes = [vp, vp, vp, vp, vp]
     L.wlc_run.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp, vp, vp, vp, vp]
     L.wlc_snr2.argtypes = [vp, vp, vp, vp, vp, ct.POINTER(ct.c_double), vp]
+    L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
+    L.wlc_plan_timings.argtypes = [vp, vp]
+    L.wlc_plan_kernel_stats.argtypes = [vp, vp, vp, vp, vp]
     return L
 
 
 lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_snr2", "wlc_last_error"]
+            "wlc_lattice_counts", "wlc_run", "wlc_snr2", "wlc_plan_set_timing", "wlc_plan_timings",
+            "wlc_plan_kernel_stats", "wlc_last_error"]
+PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
+
+
+def wlc_plan_set_timing(plan, enable):
+    _check(lib.wlc_plan_set_timing(plan, int(bool(enable))))
+
+
+def wlc_plan_timings(plan):
+    ms = (ct.c_float * len(PHASES))()
+    _check(lib.wlc_plan_timings(plan, ct.cast(ms, ct.c_void_p)))
+    return dict(zip(PHASES, [float(x) for x in ms]))
+
+
+def wlc_plan_kernel_stats(plan):
+    ms = ct.c_double(); n = ct.c_int64(); timed = ct.c_int64(); fl = ct.c_double()
+    _check(lib.wlc_plan_kernel_stats(plan, ct.byref(ms), ct.byref(n), ct.byref(timed), ct.byref(fl)))
+    return dict(ms=ms.value, launches=n.value, timed=timed.value, flops=fl.value)
 
 
 def wlc_last_error():

@@ -157,3 +157,34 @@ def test_lattice_counts_bruteforce(wl):
     assert [oracle.lattice_modes(thr, b) for b in range(o.n_ell)] == modes.cpu().tolist()
     for q, (i, j, k, _) in enumerate(o.tris[:4]):
         assert int(tris[q]) == oracle.lattice_triangles(thr, i, j, k)
+
+
+@pytest.mark.parametrize("preset", ["tiny", "mid", "euclid5"])
+def test_snr2_random_spd(wl, preset):
+    """wlc_snr2 on a seeded random SPD matrix of the plan's size (several
+    64-wide panels and a ragged last panel), against a LAPACK solve."""
+    _say("case snr2 random spd %s" % preset)
+    t = synth.make_tables(preset) if preset != "euclid5" else None
+    cfg = t.cfg if t is not None else dict(synth.PRESETS["euclid5"], **synth.SURVEY_DEFAULTS, rho_mean=8.3e10)
+    prob = wl.Problem(cfg, synth.make_tables("tiny").arrays(), precision="fp64")
+    n = prob.sizes.n_data
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((n, n)) / np.sqrt(n)
+    M = B @ B.T + 0.05 * np.eye(n)
+    d = rng.standard_normal(n)
+    e = rng.integers(-30, 30, n)
+    Ms = np.ldexp(M, e[:, None] + e[None, :])
+    prob.C.copy_(torch.from_numpy(Ms))
+    prob.row_exp2.copy_(torch.from_numpy(e.astype(np.int32)))
+    prob.d.copy_(torch.from_numpy(d))
+    got = prob.snr2()
+    want = float(d @ np.linalg.solve(M, d))
+    assert abs(got - want) / want < 1e-9
+    # not positive definite -> WLC_ENOTPD
+    bad = Ms.copy()
+    bad[n // 2, n // 2] = -1.0
+    prob.C.copy_(torch.from_numpy(bad))
+    with pytest.raises(wl.WlcError) as ex:
+        prob.snr2()
+    assert ex.value.code == wl.WLC_ENOTPD
+    prob.close()
