@@ -37,6 +37,11 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests of the serving stream (0: skip serving)")
+    ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-budget-gb", type=float, default=180.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
     return ap.parse_args()
 
 
@@ -108,6 +113,76 @@ def cpu_baseline(tables, seconds, n_data):
                 (done, t_setup + t_pairs))
 
 
+def serving(n_req, budget_gb, slots, precisions, torch):
+    """Continuous-batching server on a seeded Poisson stream of requests
+    (Omega_m, sigma_8, n_z, l_max drawn per request): closed-loop capacity
+    first, then an open loop at half of it; per-request latency is submit to
+    completion on the server clock."""
+    import numpy as np
+    import synth
+    from paper_1812_07437_amd import serve
+    fid = synth.serving_fiducial()
+    reqs = synth.serving_requests(n_req, seed=1234, qps=1.0, fid=fid)
+    out = {"requests": n_req, "slots": slots, "arena_gb": budget_gb,
+           "mix": {"n_z": [int(q["n_z"]) for q in reqs], "ell_max": [q["ell_max"] for q in reqs]}}
+    for prec in precisions:
+        srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=int(budget_gb * (1 << 30)), max_inflight=slots,
+                           precision=prec)
+
+        def submit(q):
+            return srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+
+        # closed loop: everything at once
+        # (a request holds its arena memory until released, and admission is
+        # in arrival order: release each one as soon as it is done)
+        t0 = time.perf_counter()
+        ts = [submit(q) for q in reqs]
+        for i, t in enumerate(ts):
+            r = srv.wait(t)
+            log("  closed loop %s: request %d/%d done at %.0f ms (n=%d)" % (prec, i + 1, n_req, r.t_done_ms,
+                                                                            r.n_data))
+            srv.release(t)
+        t_closed = time.perf_counter() - t0
+        cap = n_req / t_closed
+        # open loop: Poisson arrivals at half the capacity
+        qps = 0.5 * cap
+        gaps = np.random.default_rng(1234).exponential(1.0 / qps, size=n_req)
+        arrivals = np.cumsum(gaps)
+        t0 = time.perf_counter()
+        ts, res, released = [], [], 0
+        for q, ta in zip(reqs, arrivals):
+            while time.perf_counter() - t0 < ta:
+                # release finished requests in order while waiting for the next arrival
+                while released < len(ts):
+                    done, r = srv.poll(ts[released])
+                    if not done:
+                        break
+                    res.append(r)
+                    srv.release(ts[released])
+                    released += 1
+                time.sleep(0.0005)
+            ts.append(submit(q))
+        while released < len(ts):
+            r = srv.wait(ts[released])
+            res.append(r)
+            srv.release(ts[released])
+            released += 1
+            log("  open loop %s: request %d/%d done" % (prec, released, n_req))
+        t_open = time.perf_counter() - t0
+        lat = np.array([r.t_done_ms - r.t_submit_ms for r in res])
+        qwait = np.array([r.t_admit_ms - r.t_submit_ms for r in res])
+        st = srv.stats()
+        srv.close()
+        ok = all(r.status == 0 for r in res)
+        out[prec] = dict(closed_loop_req_per_s=cap, qps=qps, achieved_req_per_s=n_req / t_open,
+                         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                         mean_queue_ms=float(qwait.mean()), arena_peak_gb=st.arena_peak / 2 ** 30, all_ok=ok)
+        log("serve %s: capacity %.2f req/s, open loop at %.2f qps: p50 %.0f ms p99 %.0f ms" %
+            (prec, cap, qps, out[prec]["p50_ms"], out[prec]["p99_ms"]))
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -119,6 +194,12 @@ def main():
 
     import synth
     from paper_1812_07437_amd import wlcov as wl
+
+    if args.serve_only:
+        srv = serving(args.serve_requests or 24, args.serve_budget_gb, args.serve_slots, ["bf16x3", "fp64"], torch)
+        print(json.dumps({"metric": "serving p50/p99 latency (ms) and requests/s", "data": "synthetic",
+                          "serving": srv}), flush=True)
+        return
 
     log("building %s tables" % args.workload)
     t = synth.make_tables(args.workload)
@@ -192,6 +273,11 @@ def main():
         chol_update=dict(ms=upd_ms, launches=upd["launches"], tflops=upd_tf, frac_peak=upd_tf / PEAK_TFLOPS["fp64"]),
     )
 
+    srv = None
+    if args.serve_requests > 0:
+        log("serving stream (%d requests)" % args.serve_requests)
+        srv = serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, [args.precision], torch)
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle, ~%.0f s)" % args.cpu_seconds)
@@ -212,6 +298,7 @@ def main():
         "distinct_entries_per_s": NR * (NR + 1) / 2 / (dt / args.steps),
         "snr": math.sqrt(snr_mixed) if snr_mixed > 0 else None,
         "fp64_path": fp64,
+        "serving": srv,
     }
     print(json.dumps(out), flush=True)
 

@@ -8,8 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "kernels.h"
-#include "plan.h"
+#include "engine.h"
 
 struct wlc_plan_s {
   wlc::Plan p;
@@ -18,7 +17,7 @@ struct wlc_plan_s {
   bool events_ready = false;
   bool recorded[WLC_PHASE_COUNT] = {};
   hipEvent_t ev[2 * WLC_PHASE_COUNT] = {};
-  // per-launch events of the Cholesky trailing-update kernel
+  // per-launch events of the Cholesky block-update kernel
   std::vector<hipEvent_t> upd_ev;
   wlc::KernelProbe probe;
   bool probe_valid = false;
@@ -30,17 +29,14 @@ struct wlc_plan_s {
 };
 
 namespace {
-struct PhaseTimer {
+struct PlanTimer : wlc::PhaseHooks {
   wlc_plan_s *h;
   hipStream_t s;
-  void begin(int ph) {
-    if (h->timing && h->events_ready) (void)hipEventRecord(h->ev[2 * ph], s);
-  }
-  void end(int ph) {
-    if (h->timing && h->events_ready) {
-      (void)hipEventRecord(h->ev[2 * ph + 1], s);
-      h->recorded[ph] = true;
-    }
+  PlanTimer(wlc_plan_s *h_, hipStream_t s_) : h(h_), s(s_) {}
+  void begin(int ph) override { (void)hipEventRecord(h->ev[2 * ph], s); }
+  void end(int ph) override {
+    (void)hipEventRecord(h->ev[2 * ph + 1], s);
+    h->recorded[ph] = true;
   }
 };
 }  // namespace
@@ -63,8 +59,6 @@ struct Layout {
   size_t off[NBUF];
   size_t total;
 };
-
-static int gram_prec(int precision) { return precision; }
 
 static Layout run_layout(const Plan &p) {
   const auto &c = p.cfg;
@@ -95,7 +89,7 @@ static Layout run_layout(const Plan &p) {
   const size_t gel = c.precision == WLC_FP64 ? 8 : 4;
   sz[B_GM] = (size_t)p.r_pad * p.r_pad * gel;
   GramShape g{p.r_pad, p.k_pad, p.r_pad};
-  sz[B_PART] = gram_partial_bytes(gram_prec(c.precision), g);
+  sz[B_PART] = gram_partial_bytes(c.precision, g);
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < NBUF; ++b) {
@@ -108,20 +102,22 @@ static Layout run_layout(const Plan &p) {
 
 static int64_t snr_ld(int64_t n) { return round_up(n + 1, 8); }
 
-static size_t snr_bytes(const Plan &p) {
+size_t run_ws_bytes(const Plan &p) { return run_layout(p).total; }
+
+size_t snr_ws_bytes(const Plan &p) {
   const int64_t n = p.n_out, ld = snr_ld(n);
-  return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(chol_scratch_bytes(), 256) + 256 + 256;
+  return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(chol_scratch_bytes(n), 256) + 256 + 256;
 }
 
 static void finish_sizes(Plan &p) {
   p.k_len = (int64_t)p.cfg.n_chi * p.cfg.n_m;
   p.k_pad = round_up(p.k_len, K_ALIGN);
   p.r_pad = round_up(p.n_R, GRAM_TILE);
-  p.ws_run = run_layout(p).total;
-  p.ws_snr = snr_bytes(p);
+  p.ws_run = run_ws_bytes(p);
+  p.ws_snr = snr_ws_bytes(p);
 }
 
-static int hip_check(hipError_t e, const char *what) {
+int hip_check(hipError_t e, const char *what) {
   if (e == hipSuccess) return WLC_OK;
   return fail(WLC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -135,12 +131,23 @@ void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
 }
 
+__global__ void k_scale(const double *x, double *y, int64_t n, double a) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+void launch_scale(const double *x, double *y, int64_t n, double a, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_scale, dim3(g), dim3(256), 0, s, x, y, n, a);
+}
+
 template <typename T>
 static T *at(void *ws, const Layout &L, Buf b) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + L.off[b]);
 }
 
-// Copy the plan's index tables into the workspace.
+// Copy the plan's index tables into the workspace (the sources live in the
+// plan, which outlives every run using it).
 static int upload_index(const Plan &p, void *ws, const Layout &L, hipStream_t s) {
   struct Up { Buf b; const void *src; size_t bytes; } ups[] = {
       {B_ROWR, p.rowR.data(), p.rowR.size() * 4},
@@ -152,13 +159,139 @@ static int upload_index(const Plan &p, void *ws, const Layout &L, hipStream_t s)
       {B_THR, p.lattice_thr.data(), p.lattice_thr.size() * 8},
       {B_TRI, p.triT.data(), p.triT.size() * 4},
   };
-  // the sources live in the plan, which outlives every run using it
   for (const auto &u : ups) {
     if (!u.bytes) continue;
     int rc = hip_check(hipMemcpyAsync(at<char>(ws, L, u.b), u.src, u.bytes, hipMemcpyHostToDevice, s),
                        "index upload");
     if (rc) return rc;
   }
+  return WLC_OK;
+}
+
+static DevTables dev_tables(const Plan &p, const wlc_tables &tb, double rho = 0.0) {
+  const wlc_config &c = p.cfg;
+  return DevTables{tb.chi, tb.w_chi, tb.k, tb.m, tb.w_m, tb.W, tb.P, tb.u, tb.n_m, tb.b1, tb.b2,
+                   c.n_z, c.n_chi, c.n_k, c.n_m, rho > 0.0 ? rho : c.rho_mean, c.k_max};
+}
+
+static int check_tables_present(const wlc_tables &tb) {
+  if (!tb.chi || !tb.w_chi || !tb.k || !tb.m || !tb.w_m || !tb.W || !tb.P || !tb.u || !tb.n_m)
+    return fail(WLC_EINVAL, "missing table");
+  return WLC_OK;
+}
+
+int validate_tables(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s) {
+  int rc = check_tables_present(tb);
+  if (rc) return rc;
+  const Layout L = run_layout(p);
+  rc = upload_index(p, ws, L, s);
+  if (rc) return rc;
+  const DevTables T = dev_tables(p, tb);
+  int32_t *flags = at<int32_t>(ws, L, B_FLAGS);
+  launch_fill_i32(flags, 64, 0, s);
+  launch_validate(T, at<double>(ws, L, B_CENT), p.n_ell, flags, s);
+  int32_t hf[2] = {0, 0};
+  rc = hip_check(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s), "validation copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "validation sync");
+  if (rc) return rc;
+  if (hf[0]) return fail(WLC_EINVAL, "tables must be finite, positive where required, and grids increasing");
+  if (hf[1]) return fail(WLC_ERANGE, "the k table does not cover every ell/chi below k_max");
+  return WLC_OK;
+}
+
+int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
+                hipStream_t s, PhaseHooks *hooks, double rho) {
+  int rc = check_tables_present(tb);
+  if (rc) return rc;
+  const wlc_config &c = p.cfg;
+  const Layout L = run_layout(p);
+  rc = upload_index(p, ws, L, s);
+  if (rc) return rc;
+  const DevTables T = dev_tables(p, tb, rho);
+  const double *cent = at<double>(ws, L, B_CENT);
+  const int n_cfg = (int)p.cfgs.size();
+  const int32_t *cfgT = at<int32_t>(ws, L, B_CFGT);
+  const int32_t *rowR = at<int32_t>(ws, L, B_ROWR);
+  double *U = at<double>(ws, L, B_U), *Pk = at<double>(ws, L, B_PK), *Ne = at<double>(ws, L, B_NE);
+  double *X = at<double>(ws, L, B_X), *R = at<double>(ws, L, B_R);
+  double *dR = at<double>(ws, L, B_DR), *rR = at<double>(ws, L, B_RR);
+  double *Ps = at<double>(ws, L, B_PS);
+  double *G = at<double>(ws, L, B_G), *Gmax = at<double>(ws, L, B_GMAX), *Ts = at<double>(ws, L, B_TS);
+  int32_t *sexp = at<int32_t>(ws, L, B_SEXP);
+
+  if (hooks) hooks->begin(WLC_PHASE_TABLES);
+  launch_stage(T, cent, p.n_ell, U, Pk, Ne, s);
+  launch_spectra(T, cfgT, n_cfg, U, Pk, Ne, cent, X, R, s);
+  launch_project(T, rowR, cfgT, p.n_R, X, R, dR, rR, s);
+  launch_ps(dR, Ps, p.n_ell, c.n_z, p.noise, s);
+  launch_gfactor(T, cfgT, n_cfg, U, G, Gmax, s);
+  launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
+  if (hooks) hooks->end(WLC_PHASE_TABLES);
+
+  const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
+  void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
+  if (hooks) hooks->begin(WLC_PHASE_ABUILD);
+  launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, A0, A1, s);
+  if (hooks) hooks->end(WLC_PHASE_ABUILD);
+  GramShape g{p.r_pad, p.k_pad, p.r_pad};
+  void *Gm = at<void>(ws, L, B_GM);
+  if (hooks) hooks->begin(WLC_PHASE_GRAM);
+  launch_gram(c.precision, g, A0, A1, Gm, at<void>(ws, L, B_PART), s);
+  if (hooks) hooks->end(WLC_PHASE_GRAM);
+
+  AsmArgs a{};
+  a.rowO = at<int32_t>(ws, L, B_ROWO);
+  a.cfgT = cfgT;
+  a.sexp = sexp;
+  a.Gm = Gm;
+  a.ld_g = p.r_pad;
+  a.gm_f32 = c.precision != WLC_FP64;
+  a.Ps = Ps;
+  a.nmodes = at<double>(ws, L, B_NMODES);
+  a.ntri = tb.n_tri ? tb.n_tri : at<double>(ws, L, B_NTRI);
+  a.rR = rR;
+  a.dR = dR;
+  a.n_z = c.n_z;
+  a.n_ell = p.n_ell;
+  a.n = p.n_out;
+  a.omega = p.omega;
+  a.inv_omega = 1.0 / p.omega;
+  a.sigma_b2 = c.sigma_b2;
+  if (hooks) hooks->begin(WLC_PHASE_ASSEMBLE);
+  launch_rowexp(a, row_exp2, d, r, s);
+  launch_assemble(a, row_exp2, C, c.precision != WLC_FP64, s);
+  if (hooks) hooks->end(WLC_PHASE_ASSEMBLE);
+  return hip_check(hipGetLastError(), "run launch");
+}
+
+int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const double *d, void *ws, hipStream_t s,
+                PhaseHooks *hooks, KernelProbe *probe, int32_t **flag_dev, double **out_dev) {
+  const int64_t n = p.n_out, ld = snr_ld(n);
+  char *base = static_cast<char *>(ws);
+  double *Wm = reinterpret_cast<double *>(base);
+  size_t o = align_up((size_t)(n + 1) * ld * 8, 256);
+  double *scratch = reinterpret_cast<double *>(base + o);
+  o += align_up(chol_scratch_bytes(n), 256);
+  int32_t *flag = reinterpret_cast<int32_t *>(base + o);
+  o += 256;
+  double *out = reinterpret_cast<double *>(base + o);
+  if (hooks) hooks->begin(WLC_PHASE_SNR_PREP);
+  launch_fill_i32(flag, 1, 0, s);
+  launch_chol_prep(C, p.cfg.precision != WLC_FP64, row_exp2, d, n, ld, Wm, s);
+  if (hooks) hooks->end(WLC_PHASE_SNR_PREP);
+  if (hooks) hooks->begin(WLC_PHASE_CHOL);
+  chol_factor(Wm, n, ld, scratch, flag, s, probe);
+  launch_sumsq_row(Wm, n, ld, out, s);
+  if (hooks) hooks->end(WLC_PHASE_CHOL);
+  *flag_dev = flag;
+  *out_dev = out;
+  return hip_check(hipGetLastError(), "snr launch");
+}
+
+int plan_build(const wlc_config &cfg, Plan &p) {
+  int rc = build_plan(cfg, p);
+  if (rc) return rc;
+  finish_sizes(p);
   return WLC_OK;
 }
 
@@ -177,7 +310,7 @@ int wlc_plan_set_timing(wlc_plan plan, int enable) {
       int rc = hip_check(hipEventCreate(&e), "event create");
       if (rc) return rc;
     }
-    // two events per trailing-update launch: about 5 launches per 256 columns
+    // two events per block-update launch: about 5 launches per 256 columns
     const int64_t launches = 5 * ((plan->p.n_out + 255) / 256) + 16;
     plan->upd_ev.resize((size_t)std::min<int64_t>(2 * launches, 16384));
     for (auto &e : plan->upd_ev) {
@@ -228,12 +361,11 @@ int wlc_plan_create(const wlc_config *cfg, wlc_plan *out) {
   *out = nullptr;
   try {
     auto *h = new wlc_plan_s();
-    int rc = build_plan(*cfg, h->p);
+    int rc = plan_build(*cfg, h->p);
     if (rc) {
       delete h;
       return rc;
     }
-    finish_sizes(h->p);
     *out = h;
     return WLC_OK;
   } catch (const std::bad_alloc &) {
@@ -306,84 +438,16 @@ int wlc_run(wlc_plan plan, const wlc_tables *tb, void *ws, double *d, double *r,
             void *stream) {
   if (!plan || !tb || !ws || !d || !r || !C || !row_exp2) return fail(WLC_EINVAL, "null argument");
   if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "workspace must be 256-byte aligned");
-  if (!tb->chi || !tb->w_chi || !tb->k || !tb->m || !tb->w_m || !tb->W || !tb->P || !tb->u || !tb->n_m)
-    return fail(WLC_EINVAL, "missing table");
   const Plan &p = plan->p;
-  const wlc_config &c = p.cfg;
   hipStream_t s = (hipStream_t)stream;
-  const Layout L = run_layout(p);
-  int rc = upload_index(p, ws, L, s);
-  if (rc) return rc;
-
-  DevTables T{tb->chi, tb->w_chi, tb->k, tb->m, tb->w_m, tb->W, tb->P, tb->u, tb->n_m, tb->b1, tb->b2,
-              c.n_z, c.n_chi, c.n_k, c.n_m, c.rho_mean, c.k_max};
-  PhaseTimer tm{plan, s};
-  for (int ph = WLC_PHASE_TABLES; ph <= WLC_PHASE_ASSEMBLE; ++ph) plan->recorded[ph] = false;
-  tm.begin(WLC_PHASE_TABLES);
-  const double *cent = at<double>(ws, L, B_CENT);
-  int32_t *flags = at<int32_t>(ws, L, B_FLAGS);
-  if (!(c.flags & WLC_FLAG_NOCHECK)) {
-    launch_fill_i32(flags, 64, 0, s);
-    launch_validate(T, cent, p.n_ell, flags, s);
-    int32_t hf[2] = {0, 0};
-    rc = hip_check(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s), "validation copy");
-    if (!rc) rc = hip_check(hipStreamSynchronize(s), "validation sync");
+  if (!(p.cfg.flags & WLC_FLAG_NOCHECK)) {
+    int rc = validate_tables(p, *tb, ws, s);
     if (rc) return rc;
-    if (hf[0]) return fail(WLC_EINVAL, "tables must be finite, positive where required, and grids increasing");
-    if (hf[1]) return fail(WLC_ERANGE, "the k table does not cover every ell/chi below k_max");
   }
-  const int n_cfg = (int)p.cfgs.size();
-  const int32_t *cfgT = at<int32_t>(ws, L, B_CFGT);
-  const int32_t *rowR = at<int32_t>(ws, L, B_ROWR);
-  double *U = at<double>(ws, L, B_U), *Pk = at<double>(ws, L, B_PK), *Ne = at<double>(ws, L, B_NE);
-  double *X = at<double>(ws, L, B_X), *R = at<double>(ws, L, B_R);
-  double *dR = at<double>(ws, L, B_DR), *rR = at<double>(ws, L, B_RR);
-  double *Ps = at<double>(ws, L, B_PS);
-  double *G = at<double>(ws, L, B_G), *Gmax = at<double>(ws, L, B_GMAX), *Ts = at<double>(ws, L, B_TS);
-  int32_t *sexp = at<int32_t>(ws, L, B_SEXP);
-
-  launch_stage(T, cent, p.n_ell, U, Pk, Ne, s);
-  launch_spectra(T, cfgT, n_cfg, U, Pk, Ne, cent, X, R, s);
-  launch_project(T, rowR, cfgT, p.n_R, X, R, dR, rR, s);
-  launch_ps(dR, Ps, p.n_ell, c.n_z, p.noise, s);
-  launch_gfactor(T, cfgT, n_cfg, U, G, Gmax, s);
-  launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
-  tm.end(WLC_PHASE_TABLES);
-
-  const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
-  void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
-  tm.begin(WLC_PHASE_ABUILD);
-  launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, A0, A1, s);
-  tm.end(WLC_PHASE_ABUILD);
-  GramShape g{p.r_pad, p.k_pad, p.r_pad};
-  void *Gm = at<void>(ws, L, B_GM);
-  tm.begin(WLC_PHASE_GRAM);
-  launch_gram(gram_prec(c.precision), g, A0, A1, Gm, at<void>(ws, L, B_PART), s);
-  tm.end(WLC_PHASE_GRAM);
-
-  AsmArgs a{};
-  a.rowO = at<int32_t>(ws, L, B_ROWO);
-  a.cfgT = cfgT;
-  a.sexp = sexp;
-  a.Gm = Gm;
-  a.ld_g = p.r_pad;
-  a.gm_f32 = c.precision != WLC_FP64;
-  a.Ps = Ps;
-  a.nmodes = at<double>(ws, L, B_NMODES);
-  a.ntri = tb->n_tri ? tb->n_tri : at<double>(ws, L, B_NTRI);
-  a.rR = rR;
-  a.dR = dR;
-  a.n_z = c.n_z;
-  a.n_ell = p.n_ell;
-  a.n = p.n_out;
-  a.omega = p.omega;
-  a.inv_omega = 1.0 / p.omega;
-  a.sigma_b2 = c.sigma_b2;
-  tm.begin(WLC_PHASE_ASSEMBLE);
-  launch_rowexp(a, row_exp2, d, r, s);
-  launch_assemble(a, row_exp2, C, c.precision != WLC_FP64, s);
-  tm.end(WLC_PHASE_ASSEMBLE);
-  return hip_check(hipGetLastError(), "wlc_run launch");
+  for (int ph = WLC_PHASE_TABLES; ph <= WLC_PHASE_ASSEMBLE; ++ph) plan->recorded[ph] = false;
+  PlanTimer tm(plan, s);
+  const bool timed = plan->timing && plan->events_ready;
+  return run_enqueue(p, *tb, ws, d, r, C, row_exp2, s, timed ? &tm : nullptr);
 }
 
 int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws, double *snr2_host,
@@ -392,34 +456,20 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
   if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "workspace must be 256-byte aligned");
   const Plan &p = plan->p;
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = p.n_out, ld = snr_ld(n);
-  char *base = static_cast<char *>(ws);
-  double *Wm = reinterpret_cast<double *>(base);
-  size_t o = align_up((size_t)(n + 1) * ld * 8, 256);
-  double *scratch = reinterpret_cast<double *>(base + o);
-  o += align_up(chol_scratch_bytes(), 256);
-  int32_t *flag = reinterpret_cast<int32_t *>(base + o);
-  o += 256;
-  double *out = reinterpret_cast<double *>(base + o);
-  PhaseTimer tm{plan, s};
   plan->recorded[WLC_PHASE_SNR_PREP] = plan->recorded[WLC_PHASE_CHOL] = false;
-  tm.begin(WLC_PHASE_SNR_PREP);
-  launch_fill_i32(flag, 1, 0, s);
-  launch_chol_prep(C, p.cfg.precision != WLC_FP64, row_exp2, d, n, ld, Wm, s);
-  tm.end(WLC_PHASE_SNR_PREP);
-  tm.begin(WLC_PHASE_CHOL);
+  PlanTimer tm(plan, s);
+  const bool timed = plan->timing && plan->events_ready;
   KernelProbe *probe = nullptr;
-  if (plan->timing && plan->events_ready) {
+  if (timed) {
     plan->probe = KernelProbe{};
     plan->probe.ev = plan->upd_ev.data();
     plan->probe.cap = (int)plan->upd_ev.size() / 2;
     probe = &plan->probe;
     plan->probe_valid = true;
   }
-  chol_factor(Wm, n, ld, scratch, flag, s, probe);
-  launch_sumsq_row(Wm, n, ld, out, s);
-  tm.end(WLC_PHASE_CHOL);
-  int rc = hip_check(hipGetLastError(), "wlc_snr2 launch");
+  int32_t *flag = nullptr;
+  double *out = nullptr;
+  int rc = snr_enqueue(p, C, row_exp2, d, ws, s, timed ? &tm : nullptr, probe, &flag, &out);
   if (rc) return rc;
   struct { int32_t flag; int32_t pad; double v; } h{};
   rc = hip_check(hipMemcpyAsync(&h.flag, flag, 4, hipMemcpyDeviceToHost, s), "snr copy");

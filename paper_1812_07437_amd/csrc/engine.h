@@ -1,0 +1,46 @@
+// Asynchronous building blocks of the C ABI, shared by the entry points in
+// api.hip and the request server in server.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "plan.h"
+
+namespace wlc {
+
+// Hooks around the phases of a run (WLC_PHASE_*); may be null.
+struct PhaseHooks {
+  virtual void begin(int phase) = 0;
+  virtual void end(int phase) = 0;
+  virtual ~PhaseHooks() = default;
+};
+
+// Device workspace sizes of a plan.
+size_t run_ws_bytes(const Plan &p);
+size_t snr_ws_bytes(const Plan &p);
+
+// Validate the tables on the device and synchronise the stream
+// (WLC_EINVAL / WLC_ERANGE).  Uses the run workspace.
+int validate_tables(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s);
+
+// Enqueue the hot path (no synchronisation): index upload, staging,
+// quadrature, projection, A-build, Gram product, assembly.
+// rho > 0 replaces the plan's mean matter density.
+int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
+                hipStream_t s, PhaseHooks *hooks, double rho = 0.0);
+
+// Enqueue the S/N factorisation (no synchronisation).  On completion
+// *flag_dev != 0 marks a non-positive pivot and *out_dev holds (S/N)^2.
+int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const double *d, void *ws, hipStream_t s,
+                PhaseHooks *hooks, KernelProbe *probe, int32_t **flag_dev, double **out_dev);
+
+int hip_check(hipError_t e, const char *what);
+
+// Enumerate and size a plan.
+int plan_build(const wlc_config &cfg, Plan &p);
+
+// y[i] = a * x[i] (device), used to rescale shared tables per request.
+void launch_scale(const double *x, double *y, int64_t n, double a, hipStream_t s);
+
+}  // namespace wlc

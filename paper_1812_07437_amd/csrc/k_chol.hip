@@ -164,7 +164,7 @@ int chol_factor(double *Wm, int64_t n, int64_t ld, double *scratch, int *flag, h
   for (int64_t J0 = 0; J0 < n; J0 += NB_OUT) {
     const int64_t Jend = std::min<int64_t>(J0 + NB_OUT, n);
     // everything left of the panel, in one product over k = [0, J0)
-    launch_update2(Wm, ld, J0, rows, Jend, 0, J0, part, s, probe);
+    launch_update2(Wm, ld, J0, rows, Jend, 0, J0, part, chol_part_rows(n), s, probe);
     for (int64_t j0 = J0; j0 < Jend; j0 += NB) {
       const int jb = (int)std::min<int64_t>(NB, Jend - j0);
       hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, Wm, ld, j0, jb, Linv, flag);
@@ -174,14 +174,16 @@ int chol_factor(double *Wm, int64_t n, int64_t ld, double *scratch, int *flag, h
         hipLaunchKernelGGL(k_trsm, dim3((unsigned)nblk), dim3(256), 0, s, Wm, ld, j0, jb, r0, rows, Linv);
       }
       // the rest of this panel with the freshly solved columns
-      launch_update2(Wm, ld, j0 + jb, rows, Jend, j0, j0 + jb, nullptr, s, probe);
+      launch_update2(Wm, ld, j0 + jb, rows, Jend, j0, j0 + jb, nullptr, 0, s, probe);
     }
   }
   return 0;
 }
 
-size_t chol_scratch_bytes() { return (size_t)NB * NB * 8 + (size_t)PART_ROWS * NB_OUT * 8; }
-int64_t chol_part_rows() { return PART_ROWS; }
+// Split-k scratch rows for an n x n factorisation: slices never exceed 64 and
+// rows never exceed n + 1, so small matrices reserve little.
+int64_t chol_part_rows(int64_t n) { return std::min<int64_t>(PART_ROWS, 64 * (n + 1)); }
+size_t chol_scratch_bytes(int64_t n) { return (size_t)NB * NB * 8 + (size_t)chol_part_rows(n) * NB_OUT * 8; }
 
 // ------------------------------------------------------------- y^T y
 __global__ void k_sumsq_row(const double *__restrict__ Wm, int64_t n, int64_t ld, double *__restrict__ out) {

@@ -138,7 +138,7 @@ __global__ void k_update_reduce(double *__restrict__ Wm, int64_t ld, int64_t c0,
 }
 
 void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1,
-                    double *part, hipStream_t s, KernelProbe *probe) {
+                    double *part, int64_t part_rows, hipStream_t s, KernelProbe *probe) {
   if (c0 >= c1 || c0 >= r1 || k0 >= k1) return;
   const bool timed = probe && probe->ev && probe->count < probe->cap;
   if (probe) {
@@ -153,12 +153,11 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
   const int64_t tiles = tri ? tr * (tr + 1) / 2 : tr * tc;
   // split the k range when the tiles alone cannot fill the chip, keeping at
   // least 512 k per slice and the scratch (slices x rows x 256 doubles)
-  // within what chol_scratch_bytes() reserves
+  // within the part_rows x 256 doubles the caller reserved
   int ns = 1;
   if (part && c1 - c0 <= 256) {
     const int64_t ksteps = (k1 - k0 + UBK - 1) / UBK;
-    while (ns < 64 && tiles * ns < 1024 && ksteps / (2 * ns) >= 32 &&
-           (int64_t)(2 * ns) * (r1 - c0) <= chol_part_rows())
+    while (ns < 64 && tiles * ns < 1024 && ksteps / (2 * ns) >= 32 && (int64_t)(2 * ns) * (r1 - c0) <= part_rows)
       ns *= 2;
   }
   const int64_t ksplit = ((k1 - k0 + UBK - 1) / UBK + ns - 1) / ns * UBK;

@@ -70,11 +70,11 @@ struct KernelProbe {
 };
 int chol_factor(double *Wm, int64_t n, int64_t ld, double *scratch, int *flag, hipStream_t s,
                 KernelProbe *probe = nullptr);
-size_t chol_scratch_bytes();
-int64_t chol_part_rows();
-// part: split-k scratch (NULL: no split)
+size_t chol_scratch_bytes(int64_t n);
+int64_t chol_part_rows(int64_t n);
+// part: split-k scratch of part_rows x 256 doubles (NULL: no split)
 void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1,
-                    double *part, hipStream_t s, KernelProbe *probe = nullptr);
+                    double *part, int64_t part_rows, hipStream_t s, KernelProbe *probe = nullptr);
 void launch_sumsq_row(const double *Wm, int64_t n, int64_t ld, double *out, hipStream_t s);
 
 // ---- lattice counts (k_lattice.hip); thr_max = largest threshold used

@@ -9,6 +9,11 @@ from __future__ import annotations
 import ctypes as ct
 import os
 
+# torch ships its own HIP runtime with the same soname as the system one;
+# loading it first makes libwlcov bind to that single runtime, which owns
+# the device memory of every tensor passed in.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwlcov.so")
 

@@ -239,3 +239,50 @@ def sample_pairs(n, count, seed=42):
     lo = np.minimum(a, b)
     hi = np.maximum(a, b)
     return np.stack([hi, lo], axis=1).astype(np.int64)
+
+
+# ---------------------------------------------------------- serving stream
+SERVE_GRID_OM = 0.28       # chi grid: midpoints of [0, chi(2.5; Omega_m = 0.28)]
+SERVE_FID = dict(omega_m=0.3, sigma8=0.8)
+PRESETS["serve"] = dict(n_z=10, n_ell=15, ell_min=10.0, ell_max=5000.0, n_chi=256, n_m=128, n_k=512)
+
+
+def serving_fiducial() -> Tables:
+    """Fiducial device-resident tables of the serving workload: the 15 ell-bins
+    over 10-5000, 256 x 128 (chi, M) grid shared by every request."""
+    return make_tables("serve", chi_grid_om=SERVE_GRID_OM, **SERVE_FID)
+
+
+def serving_requests(n, seed=1234, qps=1.0, fid: Tables | None = None):
+    """A seeded Poisson stream of likelihood-style requests.  Each draws
+    Omega_m ~ U[0.28, 0.32], sigma_8 ~ U[0.78, 0.86], n_z in {3, 5, 7, 10} and
+    l_max in {1000, 3000, 5000}; it rescales P by (sigma_8/0.8)^2 and n(M) by
+    Omega_m/0.3 (with rho = Omega_m rho_crit) and carries its own lensing
+    kernels on the shared chi grid.  Arrival times are exponential gaps at
+    rate qps."""
+    fid = fid or serving_fiducial()
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(n):
+        om = float(rng.uniform(0.28, 0.32))
+        s8 = float(rng.uniform(0.78, 0.86))
+        nz = int(rng.choice([3, 5, 7, 10]))
+        lmax = float(rng.choice([1000.0, 3000.0, 5000.0]))
+        t += float(rng.exponential(1.0 / qps))
+        W = lensing_kernels(fid.chi, om, equipopulated_edges(nz))
+        out.append(dict(t_arrival=t, omega_m=om, sigma8=s8, n_z=nz, ell_max=lmax, W=W,
+                        p_scale=(s8 / SERVE_FID["sigma8"]) ** 2, n_scale=om / SERVE_FID["omega_m"],
+                        rho_mean=om * RHO_CRIT))
+    return out
+
+
+def request_tables(fid: Tables, req: dict) -> Tables:
+    """The complete tables of one request (fiducial tables rescaled), for
+    running it alone or through the oracle."""
+    cfg = dict(fid.cfg)
+    cfg["n_z"] = req["n_z"]
+    cfg["rho_mean"] = req["rho_mean"]
+    cfg["ell_cut"] = req["ell_max"]
+    return Tables(cfg=cfg, chi=fid.chi, w_chi=fid.w_chi, k=fid.k, m=fid.m, w_m=fid.w_m, W=req["W"],
+                  P=fid.P * req["p_scale"], u=fid.u, n_m=fid.n_m * req["n_scale"])

@@ -1,0 +1,111 @@
+"""Request server: every request's result is the same alone and in a mix of
+concurrent requests, equals the direct path, and matches the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_07437_amd import serve, wlcov
+    fid = synth.serving_fiducial()
+    reqs = synth.serving_requests(14, seed=1234, qps=10.0, fid=fid)
+    small = [r for r in reqs if r["n_z"] <= 5 and r["ell_max"] <= 3000.0][:5]
+    # one request of each remaining kind keeps sizes mixed
+    small += [dict(reqs[0], n_z=3, W=synth.lensing_kernels(fid.chi, reqs[0]["omega_m"],
+                                                            synth.equipopulated_edges(3)), ell_max=1000.0)]
+    return serve, wlcov, fid, small
+
+
+def _run_alone(srv, reqs):
+    out = []
+    for q in reqs:
+        t = srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+        res, d, r, C, tt = srv.fetch(t)
+        assert res.status == 0
+        out.append((res.snr2, d.cpu(), C.cpu(), tt.cpu()))
+        srv.release(t)
+    return out
+
+
+def test_alone_equals_mix(env):
+    serve, wl, fid, reqs = env
+    _say("case serve alone vs mix (%d requests)" % len(reqs))
+    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=24 << 30, max_inflight=4, precision="bf16x3")
+    alone = _run_alone(srv, reqs)
+    tickets = [srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+               for q in reqs]
+    overlapped = 0
+    for q, t, (s_a, d_a, C_a, t_a) in zip(reqs, tickets, alone):
+        res, d, r, C, tt = srv.fetch(t)
+        assert res.status == 0
+        assert res.snr2 == s_a
+        assert torch.equal(d.cpu(), d_a) and torch.equal(C.cpu(), C_a) and torch.equal(tt.cpu(), t_a)
+        srv.release(t)
+    # the mix really ran requests side by side
+    st = srv.stats()
+    assert st.completed_total == 2 * len(reqs)
+    srv.close()
+
+
+def test_server_matches_direct_path_and_oracle(env):
+    serve, wl, fid, reqs = env
+    q = reqs[-1]
+    _say("case serve vs direct vs oracle n_z=%d l_max=%g" % (q["n_z"], q["ell_max"]))
+    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=8 << 30, max_inflight=2, precision="bf16x3")
+    t = srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+    res, d, r, C, tt = srv.fetch(t)
+    tab = synth.request_tables(fid, q)
+    prob = wl.Problem(tab.cfg, tab.arrays(), precision="bf16x3")
+    prob.run()
+    s_direct = prob.snr2()
+    torch.cuda.synchronize()
+    assert s_direct == res.snr2
+    assert torch.equal(prob.d, d) and torch.equal(prob.C, C)
+    o = oracle.Oracle(tab)
+    ref = o.run()
+    assert np.max(np.abs(d.cpu().numpy() - ref["d"]) / ref["d"]) < 1e-10
+    assert abs(res.snr2 - ref["snr2"]) / ref["snr2"] < 1e-4
+    srv.release(t)
+    srv.close()
+
+
+def test_memory_admission(env):
+    serve, wl, fid, reqs = env
+    _say("case serve admission")
+    q = reqs[0]
+    # an arena too small for the request: refused at submission
+    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=8 << 20, max_inflight=2)
+    with pytest.raises(wl.WlcError) as e:
+        srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+    assert e.value.code == wl.WLC_EBUSY
+    srv.close()
+    # an arena that holds one request at a time: all complete, in order
+    tab = synth.request_tables(fid, q)
+    p = wl.Problem(tab.cfg, tab.arrays(), precision="bf16x3")
+    foot = p.sizes.ws_run_bytes + p.sizes.ws_snr_bytes + p.sizes.n_data ** 2 * 4 + (8 << 20)
+    p.close()
+    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=int(foot * 1.5), max_inflight=4)
+    ts = [srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"]) for _ in range(3)]
+    snrs = []
+    for t in ts:
+        res = srv.wait(t)
+        assert res.status == 0
+        snrs.append(res.snr2)
+        srv.release(t)
+    assert snrs[0] == snrs[1] == snrs[2]
+    srv.close()
