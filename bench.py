@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=180.0)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB device copy (to scale HBM byte counters)")
     return ap.parse_args()
 
 
@@ -200,6 +202,14 @@ def main():
         print(json.dumps({"metric": "serving p50/p99 latency (ms) and requests/s", "data": "synthetic",
                           "serving": srv}), flush=True)
         return
+
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
 
     log("building %s tables" % args.workload)
     t = synth.make_tables(args.workload)
