@@ -46,7 +46,7 @@ namespace wlc {
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 static inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-constexpr int64_t GRAM_TILE = 128;
+constexpr int64_t GRAM_TILE = 256;  // rows of A padded to the bf16 Gram tile
 constexpr int64_t K_ALIGN = 64;
 
 enum Buf {
@@ -88,7 +88,7 @@ static Layout run_layout(const Plan &p) {
   sz[B_A1] = c.precision == WLC_BF16X3 ? sz[B_A0] : 0;
   const size_t gel = c.precision == WLC_FP64 ? 8 : 4;
   sz[B_GM] = (size_t)p.r_pad * p.r_pad * gel;
-  GramShape g{p.r_pad, p.k_pad, p.r_pad};
+  GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
   sz[B_PART] = gram_partial_bytes(c.precision, g);
   Layout L{};
   size_t o = 0;
@@ -233,7 +233,7 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   if (hooks) hooks->begin(WLC_PHASE_ABUILD);
   launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, A0, A1, s);
   if (hooks) hooks->end(WLC_PHASE_ABUILD);
-  GramShape g{p.r_pad, p.k_pad, p.r_pad};
+  GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
   void *Gm = at<void>(ws, L, B_GM);
   if (hooks) hooks->begin(WLC_PHASE_GRAM);
   launch_gram(c.precision, g, A0, A1, Gm, at<void>(ws, L, B_PART), s);

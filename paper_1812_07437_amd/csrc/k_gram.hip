@@ -11,11 +11,21 @@
 // Rows of A carry a power-of-two scale so that their largest entry lies in
 // [0.5, 1); the caller undoes it exactly.
 //
-// Work decomposition: a workgroup of 4 wavefronts owns one 128 x 128 output
-// tile (I >= J) and one contiguous slice of K; wavefronts split the tile 2 x 2.
-// Operands are staged through LDS with the next slice prefetched into
-// registers.  Slices of K (split-K) are reduced in a fixed order by a second
-// kernel, so results are deterministic.
+// Work decomposition: a workgroup owns one output tile (I >= J) of the lower
+// triangle and one contiguous slice of K: 256 x 256 for the bf16 variants
+// (8 wavefronts), 128 x 128 for f32 / f64 (4 wavefronts, 2 x 2).  Operands
+// are staged through LDS with the next slice prefetched into registers.
+// Slices of K (split-K) are reduced in a fixed order by a second kernel, so
+// results are deterministic.  A 256-row tile halves the operand bytes per
+// flop against a 128-row one, which matters because tiles that share a panel
+// rarely run in step closely enough to share it through L2.
+//
+// Tile schedule: the hardware hands workgroup b to XCD b mod 8, and each XCD
+// has its own L2.  Work items are therefore renumbered so that every XCD
+// walks a contiguous run of a super-block order (8 x 8 tiles per block): the
+// workgroups resident on one XCD at a time cover one or two super-blocks and
+// stream the same 16 operand panels through that XCD's L2, instead of every
+// tile fetching its own panels from HBM.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -24,7 +34,7 @@ namespace wlc {
 
 constexpr int TILE = 128;
 
-// Lower-triangle tile t -> (I, J), I >= J.
+// Lower-triangle tile t -> (I, J), I >= J (row-major over the triangle).
 __device__ __forceinline__ void tri_tile(int64_t t, int &I, int &J) {
   int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while ((i + 1) * (i + 2) / 2 <= t) ++i;
@@ -33,40 +43,93 @@ __device__ __forceinline__ void tri_tile(int64_t t, int &I, int &J) {
   J = (int)(t - i * (i + 1) / 2);
 }
 
-// ===================================================================== bf16
-// LDS tile: [128 rows][64 bf16] = 128 B per row, in 16-byte chunks; chunk c of
-// row r is stored at slot c ^ (r & 7) so that the 8 rows read together by an
-// MFMA operand load hit distinct banks.
-constexpr int BK16 = 64;
+constexpr int SB = 8;     // tiles per super-block side
+constexpr int N_XCD = 8;  // XCDs per device; workgroup b runs on XCD b mod 8
 
-template <bool X3>
-__global__ __launch_bounds__(256) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
-                                                  int64_t k_pad, int64_t k_split, int n_split, float *__restrict__ out,
-                                                  int64_t ld, int64_t part_stride) {
+// Lower-triangle tile t -> (I, J) in super-block order for nt tiles per side:
+// strips of SB tile rows, each strip's super-blocks left to right, the tiles
+// of a super-block row-major (the diagonal block holds its lower triangle).
+// All strips but the last are full, and strip P starts at tile
+// 32 P^2 + 4 P (= sum over p < P of 64 p + 36).
+__device__ __forceinline__ void sb_tile(int64_t t, int nt, int &I, int &J) {
+  const int64_t full = nt / SB;
+  int64_t P = (int64_t)((sqrt(16.0 + 128.0 * (double)t) - 4.0) / 64.0);
+  if (P > full) P = full;
+  while (P < full && 32 * (P + 1) * (P + 1) + 4 * (P + 1) <= t) ++P;
+  while (P > 0 && 32 * P * P + 4 * P > t) --P;
+  const int64_t u = t - (32 * P * P + 4 * P);
+  const int64_t rr = P < full ? SB : nt - SB * P;  // tile rows in this strip
+  const int64_t off = rr * SB * P;                  // tiles left of the diagonal block
+  if (u < off) {
+    const int64_t Q = u / (rr * SB), v = u % (rr * SB);
+    I = (int)(SB * P + v / SB);
+    J = (int)(SB * Q + v % SB);
+  } else {
+    int i, j;
+    tri_tile(u - off, i, j);
+    I = (int)(SB * P + i);
+    J = (int)(SB * P + j);
+  }
+}
+
+// Workgroup -> (tile, split) for a grid padded to a multiple of N_XCD: XCD x
+// takes work items [x per, (x + 1) per).  Returns false for padding.
+__device__ __forceinline__ bool gram_work(int64_t n_work, int n_split, int nt, int &I, int &J, int &split) {
+  const int64_t per = (int64_t)gridDim.x / N_XCD;
+  const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
+  if (w >= n_work) return false;
+  split = (int)(w % n_split);
+  sb_tile(w / n_split, nt, I, J);
+  return true;
+}
+
+// ===================================================================== bf16
+// 256 x 256 output tile per workgroup of NW wavefronts on a 2 x (NW/2) grid:
+// NW = 4 gives 128 x 128 per wavefront (4 x 4 blocks of
+// v_mfma_f32_32x32x16_bf16, one wavefront per SIMD); NW = 8 gives 128 x 64
+// (two per SIMD).  Larger wavefront tiles read fewer LDS bytes per MFMA.  K advances
+// in stages of 32 through a double-buffered LDS tile ([256 rows][32 bf16] =
+// 64 B per row and operand); stage s + 2 is fetched into registers while
+// stage s is multiplied.  Chunk c (16 B) of row r sits at slot c ^ ((r/2)&3),
+// which keeps the 8 rows that one MFMA operand read touches at a time on
+// distinct banks.
+constexpr int T2 = 256;
+constexpr int BK2 = 32;
+constexpr int GRAM_NW = 8;  // measured faster than 4 at both precisions
+
+__device__ __forceinline__ int swz2(int r, int c) { return r * BK2 + ((c ^ ((r >> 1) & 3)) << 3); }
+
+template <bool X3, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
+                                                  int64_t k_pad, int64_t lda, int64_t k_split, int n_split,
+                                                  int nt, int64_t n_work, float *__restrict__ out, int64_t ld,
+                                                  int64_t part_stride) {
   constexpr int NOPS = X3 ? 2 : 1;  // hi (and lo)
-  __shared__ __attribute__((aligned(16))) uint16_t lds[NOPS][2][TILE * BK16];  // [op][I/J][...]
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2][NOPS][2][T2 * BK2];  // [buffer][op][I/J side]
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t tile = blockIdx.x / n_split;
-  const int split = blockIdx.x % n_split;
-  int I, J;
-  tri_tile(tile, I, J);
-  const int64_t row0 = (int64_t)I * TILE, col0 = (int64_t)J * TILE;
+  int I, J, split;
+  if (!gram_work(n_work, n_split, nt, I, J, split)) return;
+  const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
   const int64_t kb = (int64_t)split * k_split;
   const int64_t ke = min(k_pad, kb + k_split);
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;  // wave sub-tile origin
+  constexpr int NT = 64 * NW;          // threads
+  constexpr int WCOLS = 512 / NW;      // wavefront tile columns
+  constexpr int BJ = WCOLS / 32;       // 32-column blocks per wavefront
+  constexpr int PER = 1024 / NT;       // 16-byte chunks per thread, operand side and stage
+  const int wr = (wave / (NW / 2)) * 128, wc = (wave % (NW / 2)) * WCOLS;  // wavefront sub-tile origin
 
-  f32x16 acc[2][2];
+  f32x16 acc[4][BJ];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BJ; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
 
-  // global -> register prefetch: 1024 chunks of 16 B per operand tile,
-  // 4 per thread; chunk q: row q >> 3, chunk q & 7.
-  u32x4 pre[NOPS][2][4];
+  // one stage of one operand side: 256 rows x 4 chunks = 1024 chunks, PER
+  // per thread; chunk q: row q >> 2, chunk q & 3
+  u32x4 pre[NOPS][2][PER];
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int op = 0; op < NOPS; ++op) {
@@ -75,65 +138,74 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const uint16_t *__restrict__ 
       for (int side = 0; side < 2; ++side) {
         const int64_t r0 = side == 0 ? row0 : col0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int ch = tid + 256 * q;
-          const int r = ch >> 3, c = ch & 7;
-          pre[op][side][q] = *(const u32x4 *)(src + (r0 + r) * k_pad + k0 + 8 * c);
+        for (int q = 0; q < PER; ++q) {
+          const int ch = tid + NT * q;
+          pre[op][side][q] = *(const u32x4 *)(src + (r0 + (ch >> 2)) * lda + k0 + 8 * (ch & 3));
         }
       }
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int buf) {
 #pragma unroll
     for (int op = 0; op < NOPS; ++op)
 #pragma unroll
       for (int side = 0; side < 2; ++side)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int ch = tid + 256 * q;
-          const int r = ch >> 3, c = ch & 7;
-          *(u32x4 *)(&lds[op][side][r * BK16 + ((c ^ (r & 7)) << 3)]) = pre[op][side][q];
+        for (int q = 0; q < PER; ++q) {
+          const int ch = tid + NT * q;
+          *(u32x4 *)(&lds[buf][op][side][swz2(ch >> 2, ch & 3)]) = pre[op][side][q];
         }
   };
-
-  if (kb < ke) gload(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += BK16) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (k0 + BK16 < ke) gload(k0 + BK16);
+  auto compute = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < BK16; kk += 16) {
+    for (int kk = 0; kk < BK2; kk += 16) {
       // lane holds 8 consecutive k of row (lane & 31), k offset 8 * (lane >> 5)
       const int cidx = (kk >> 3) + (lane >> 5);
-      bf16x8 a[NOPS][2], b[NOPS][2];
+      bf16x8 a[NOPS][4], b[NOPS][BJ];
 #pragma unroll
-      for (int op = 0; op < NOPS; ++op)
+      for (int op = 0; op < NOPS; ++op) {
 #pragma unroll
-        for (int blk = 0; blk < 2; ++blk) {
-          const int ra = wr + blk * 32 + (lane & 31);
-          const int rb = wc + blk * 32 + (lane & 31);
-          a[op][blk] = *(const bf16x8 *)(&lds[op][0][ra * BK16 + ((cidx ^ (ra & 7)) << 3)]);
-          b[op][blk] = *(const bf16x8 *)(&lds[op][1][rb * BK16 + ((cidx ^ (rb & 7)) << 3)]);
-        }
+        for (int blk = 0; blk < 4; ++blk)
+          a[op][blk] = *(const bf16x8 *)(&lds[buf][op][0][swz2(wr + blk * 32 + (lane & 31), cidx)]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int blk = 0; blk < BJ; ++blk)
+          b[op][blk] = *(const bf16x8 *)(&lds[buf][op][1][swz2(wc + blk * 32 + (lane & 31), cidx)]);
+      }
+      // products outermost, so consecutive MFMAs use different accumulators
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-          if constexpr (X3) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-          }
-        }
+      for (int p = 0; p < (X3 ? 3 : 1); ++p)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < BJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[p == 2 ? 1 : 0][i], b[p == 1 ? 1 : 0][j], acc[i][j],
+                                                                0, 0, 0);
     }
+  };
+
+  // stage s is fetched into registers two stages ahead, copied to LDS buffer
+  // s % 2 one stage ahead, and multiplied from there
+  const int64_t n_st = (ke - kb) / BK2;
+  if (n_st > 0) {
+    gload(kb);
+    lstore(0);
+    if (n_st > 1) gload(kb + BK2);
+    __syncthreads();
+  }
+  for (int64_t st = 0; st < n_st; ++st) {
+    compute((int)(st & 1));
+    if (st + 1 < n_st) {
+      lstore((int)((st + 1) & 1));  // that buffer was last read before the previous barrier
+      if (st + 2 < n_st) gload(kb + (st + 2) * BK2);
+    }
+    __syncthreads();
   }
   // 32x32 accumulator layout: value v of lane l is row 8 (v/4) + 4 (l/32) + v%4, column l % 32
   float *dst = out + (int64_t)split * part_stride;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t r = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -159,8 +231,9 @@ __device__ __forceinline__ void mfma16x16x4<float>(float a, float b, f32x4 &c) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_t k_pad, int64_t k_split, int n_split,
-                                                 T *__restrict__ out, int64_t ld, int64_t part_stride) {
+__global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_t k_pad, int64_t lda, int64_t k_split,
+                                                 int n_split, int nt, int64_t n_work, T *__restrict__ out, int64_t ld,
+                                                 int64_t part_stride) {
   using acc_t = typename std::conditional<sizeof(T) == 8, f64x4, f32x4>::type;
   constexpr int BK = 128 / sizeof(T);  // 128 bytes of k per row
   constexpr int LDR = BK + 1;          // padded row length
@@ -170,10 +243,8 @@ __global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_
   __shared__ T lds[2][TILE * LDR];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t tile = blockIdx.x / n_split;
-  const int split = blockIdx.x % n_split;
-  int I, J;
-  tri_tile(tile, I, J);
+  int I, J, split;
+  if (!gram_work(n_work, n_split, nt, I, J, split)) return;
   const int64_t row0 = (int64_t)I * TILE, col0 = (int64_t)J * TILE;
   const int64_t kb = (int64_t)split * k_split;
   const int64_t ke = min(k_pad, kb + k_split);
@@ -197,7 +268,7 @@ __global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_
       for (int q = 0; q < PER; ++q) {
         const int ch = tid + 256 * q;
         const int r = ch / (BK / CH), c = ch % (BK / CH);
-        pre[side][q] = *(const vec_t *)(A + (r0 + r) * k_pad + k0 + CH * c);
+        pre[side][q] = *(const vec_t *)(A + (r0 + r) * lda + k0 + CH * c);
       }
     }
   };
@@ -274,10 +345,12 @@ static int pick_split(int64_t n_tiles, int64_t k_pad, int bk) {
   return (int)s;
 }
 
-static int gram_bk(int prec) { return prec == WLC_FP64 ? 16 : (prec == WLC_FP32 ? 32 : BK16); }
+static bool is_bf16(int prec) { return prec == WLC_BF16 || prec == WLC_BF16X3; }
+static int gram_tile(int prec) { return is_bf16(prec) ? T2 : TILE; }
+static int gram_bk(int prec) { return prec == WLC_FP64 ? 16 : (prec == WLC_FP32 ? 32 : BK2); }
 
 size_t gram_partial_bytes(int prec, const GramShape &g) {
-  const int64_t nt = g.r_pad / TILE;
+  const int64_t nt = g.r_pad / gram_tile(prec);
   const int64_t tiles = nt * (nt + 1) / 2;
   const int s = pick_split(tiles, g.k_pad, gram_bk(prec));
   if (s <= 1) return 0;
@@ -287,39 +360,45 @@ size_t gram_partial_bytes(int prec, const GramShape &g) {
 
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
                  hipStream_t s) {
-  const int64_t nt = g.r_pad / TILE;
+  const int64_t nt = g.r_pad / gram_tile(prec);
   const int64_t tiles = nt * (nt + 1) / 2;
   const int bk = gram_bk(prec);
   const int ns = pick_split(tiles, g.k_pad, bk);
   int64_t ksplit = (g.k_pad / bk + ns - 1) / ns * bk;
   void *dst = ns > 1 ? partial : out;
   const int64_t pstride = ns > 1 ? g.r_pad * g.ld_out : 0;
-  const dim3 grid((unsigned)(tiles * ns));
+  const int64_t n_work = tiles * ns;
+  const dim3 grid((unsigned)((n_work + N_XCD - 1) / N_XCD * N_XCD));
+  const int nti = (int)nt;
   switch (prec) {
     case WLC_BF16:
-      hipLaunchKernelGGL(k_gram_bf16<false>, grid, dim3(256), 0, s, (const uint16_t *)A0, (const uint16_t *)A1, g.k_pad,
-                         ksplit, ns, (float *)dst, g.ld_out, pstride);
+      hipLaunchKernelGGL((k_gram_bf16<false, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0, (const uint16_t *)A1, g.k_pad,
+                         g.lda, ksplit, ns, nti, n_work, (float *)dst, g.ld_out, pstride);
       break;
     case WLC_BF16X3:
-      hipLaunchKernelGGL(k_gram_bf16<true>, grid, dim3(256), 0, s, (const uint16_t *)A0, (const uint16_t *)A1, g.k_pad,
-                         ksplit, ns, (float *)dst, g.ld_out, pstride);
+      hipLaunchKernelGGL((k_gram_bf16<true, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0, (const uint16_t *)A1, g.k_pad,
+                         g.lda, ksplit, ns, nti, n_work, (float *)dst, g.ld_out, pstride);
       break;
     case WLC_FP32:
-      hipLaunchKernelGGL(k_gram_x4<float>, grid, dim3(256), 0, s, (const float *)A0, g.k_pad, ksplit, ns, (float *)dst,
-                         g.ld_out, pstride);
+      hipLaunchKernelGGL(k_gram_x4<float>, grid, dim3(256), 0, s, (const float *)A0, g.k_pad, g.lda, ksplit, ns, nti,
+                         n_work, (float *)dst, g.ld_out, pstride);
       break;
     default:
-      hipLaunchKernelGGL(k_gram_x4<double>, grid, dim3(256), 0, s, (const double *)A0, g.k_pad, ksplit, ns,
-                         (double *)dst, g.ld_out, pstride);
+      hipLaunchKernelGGL(k_gram_x4<double>, grid, dim3(256), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, nti,
+                         n_work, (double *)dst, g.ld_out, pstride);
       break;
   }
   if (ns > 1) {
+    // the reduction walks the lower triangle in 128 x 128 tiles, which the
+    // 256 x 256 tiles cover exactly
+    const int64_t nr = g.r_pad / TILE;
+    const unsigned rt = (unsigned)(nr * (nr + 1) / 2);
     if (prec == WLC_FP64)
-      hipLaunchKernelGGL(k_gram_reduce<double>, dim3((unsigned)tiles), dim3(256), 0, s, (const double *)partial, ns,
-                         pstride, (double *)out, g.ld_out);
+      hipLaunchKernelGGL(k_gram_reduce<double>, dim3(rt), dim3(256), 0, s, (const double *)partial, ns, pstride,
+                         (double *)out, g.ld_out);
     else
-      hipLaunchKernelGGL(k_gram_reduce<float>, dim3((unsigned)tiles), dim3(256), 0, s, (const float *)partial, ns,
-                         pstride, (float *)out, g.ld_out);
+      hipLaunchKernelGGL(k_gram_reduce<float>, dim3(rt), dim3(256), 0, s, (const float *)partial, ns, pstride,
+                         (float *)out, g.ld_out);
   }
 }
 

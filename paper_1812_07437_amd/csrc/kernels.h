@@ -31,6 +31,7 @@ struct GramShape {
   int64_t r_pad;   // padded rows (multiple of the tile)
   int64_t k_pad;   // padded contraction length
   int64_t ld_out;  // leading dimension of the output
+  int64_t lda;     // row pitch of A in elements (>= k_pad)
 };
 size_t gram_partial_bytes(int prec, const GramShape &g);
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
