@@ -3,8 +3,10 @@
 // on 128 x 128 tiles.  Four wavefronts of 64 x 64 each on v_mfma_f64_16x16x4
 // (lane l holds row l % 16, k l / 16 of each operand; the accumulator value v
 // of lane l is row l / 16 + 4 v, column l % 16).  Operand slices are staged
-// through LDS in 16-wide k steps with the next step prefetched into
-// registers.  A long k range may be split into slices whose partial products
+// through a double-buffered LDS tile in 16-wide k steps: step s + 2 is
+// fetched into registers and step s + 1 copied to LDS while step s is
+// multiplied, with one barrier per step.  The register budget is capped so
+// that two workgroups share a CU and cover each other's barrier waits.  A long k range may be split into slices whose partial products
 // go to a scratch buffer and are subtracted in a fixed order by a second
 // kernel, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -32,10 +34,10 @@ __device__ __forceinline__ void tile_of(int64_t t, int tri, int64_t tcols, int64
   }
 }
 
-__global__ __launch_bounds__(256) void k_update2(double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1,
-                                                 int64_t c1, int64_t k0, int64_t k1, int tri_grid, int64_t tcols,
-                                                 int n_split, int64_t k_split, double *__restrict__ part) {
-  __shared__ double lds[2][UT2 * ULDR];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update2(
+    double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1, int tri_grid,
+    int64_t tcols, int n_split, int64_t k_split, double *__restrict__ part) {
+  __shared__ double lds[2][2][UT2 * ULDR];  // [buffer][I/J side]
   int64_t ti, tj;
   tile_of(blockIdx.x / n_split, tri_grid, tcols, ti, tj);
   const int split = blockIdx.x % n_split;
@@ -73,38 +75,49 @@ __global__ __launch_bounds__(256) void k_update2(double *__restrict__ Wm, int64_
       }
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int buf) {
 #pragma unroll
     for (int side = 0; side < 2; ++side)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int ch = tid + 256 * q;
         const int r = ch >> 3, c = ch & 7;
-        lds[side][r * ULDR + 2 * c] = pre[side][q].x;
-        lds[side][r * ULDR + 2 * c + 1] = pre[side][q].y;
+        lds[buf][side][r * ULDR + 2 * c] = pre[side][q].x;
+        lds[buf][side][r * ULDR + 2 * c + 1] = pre[side][q].y;
       }
   };
-
-  if (kb < ke) gload(kb);
-  for (int64_t kq = kb; kq < ke; kq += UBK) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (kq + UBK < ke) gload(kq + UBK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < UBK; kk += 4) {
       const int kc = kk + (lane >> 4);
       double a[4], b[4];
 #pragma unroll
       for (int blk = 0; blk < 4; ++blk) {
-        a[blk] = lds[0][(wr + blk * 16 + (lane & 15)) * ULDR + kc];
-        b[blk] = lds[1][(wc + blk * 16 + (lane & 15)) * ULDR + kc];
+        a[blk] = lds[buf][0][(wr + blk * 16 + (lane & 15)) * ULDR + kc];
+        b[blk] = lds[buf][1][(wc + blk * 16 + (lane & 15)) * ULDR + kc];
       }
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
+  };
+
+  // the last step may be partial: gload zero-fills k >= ke
+  const int64_t n_st = (ke - kb + UBK - 1) / UBK;
+  if (n_st > 0) {
+    gload(kb);
+    lstore(0);
+    if (n_st > 1) gload(kb + UBK);
+    __syncthreads();
+  }
+  for (int64_t st = 0; st < n_st; ++st) {
+    compute((int)(st & 1));
+    if (st + 1 < n_st) {
+      lstore((int)((st + 1) & 1));  // that buffer was last read before the previous barrier
+      if (st + 2 < n_st) gload(kb + (st + 2) * UBK);
+    }
+    __syncthreads();
   }
   const int64_t pc = c1 - c0;
   double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pc : nullptr;
