@@ -231,7 +231,7 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
   void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
   if (hooks) hooks->begin(WLC_PHASE_ABUILD);
-  launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, A0, A1, s);
+  launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, p.k_pad, A0, A1, s);
   if (hooks) hooks->end(WLC_PHASE_ABUILD);
   GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
   void *Gm = at<void>(ws, L, B_GM);
@@ -258,6 +258,7 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   a.inv_omega = 1.0 / p.omega;
   a.sigma_b2 = c.sigma_b2;
   if (hooks) hooks->begin(WLC_PHASE_ASSEMBLE);
+  launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
   launch_rowexp(a, row_exp2, d, r, s);
   launch_assemble(a, row_exp2, C, c.precision != WLC_FP64, s);
   if (hooks) hooks->end(WLC_PHASE_ASSEMBLE);

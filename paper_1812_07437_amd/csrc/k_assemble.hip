@@ -42,9 +42,11 @@ __device__ __forceinline__ double gauss_entry(const AsmArgs &A, const int32_t *r
   return A.omega / A.ntri[ra[0] - A.n_ell] * s;
 }
 
+// G has been mirrored to exact symmetry, so it is read along rows: for the
+// 64 consecutive data rows b of a wavefront the distinct rows e(b) are
+// clustered, and the reads touch few cache lines.
 __device__ __forceinline__ double gram_at(const AsmArgs &A, int64_t ea, int64_t eb) {
-  const int64_t hi = ea > eb ? ea : eb, lo = ea > eb ? eb : ea;
-  return A.gm_f32 ? (double)((const float *)A.Gm)[hi * A.ld_g + lo] : ((const double *)A.Gm)[hi * A.ld_g + lo];
+  return A.gm_f32 ? (double)((const float *)A.Gm)[ea * A.ld_g + eb] : ((const double *)A.Gm)[ea * A.ld_g + eb];
 }
 
 // Diagonal first: row exponents t_a, and the expanded d, r.

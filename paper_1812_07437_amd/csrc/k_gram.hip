@@ -335,6 +335,36 @@ __global__ void k_gram_reduce(const T *__restrict__ part, int n_split, int64_t p
   }
 }
 
+// Mirror of the lower triangle onto the upper one in 64 x 64 tiles (I >= J):
+// tile (I, J) is read row by row, transposed through LDS and written as tile
+// (J, I), so both sides stay coalesced.  On a diagonal tile only the entries
+// above the diagonal are written, after the whole tile has been read.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_mirror(T *__restrict__ G, int64_t ld) {
+  __shared__ T tile[64][65];
+  int I, J;
+  tri_tile(blockIdx.x, I, J);
+  const int c = threadIdx.x & 63, rb = (threadIdx.x >> 6) * 16;
+  const int64_t i0 = (int64_t)I * 64, j0 = (int64_t)J * 64;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tile[rb + q][c] = G[(i0 + rb + q) * ld + j0 + c];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = rb + q;  // upper entry (j0 + r, i0 + c) = lower entry (i0 + c, j0 + r)
+    if (I != J || c > r) G[(j0 + r) * ld + i0 + c] = tile[c][r];
+  }
+}
+
+void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s) {
+  const int64_t nt = (n + 63) / 64;  // nt * 64 <= ld: rows and columns are padded to the Gram tile
+  const unsigned tiles = (unsigned)(nt * (nt + 1) / 2);
+  if (f32)
+    hipLaunchKernelGGL(k_gram_mirror<float>, dim3(tiles), dim3(256), 0, s, (float *)G, ld);
+  else
+    hipLaunchKernelGGL(k_gram_mirror<double>, dim3(tiles), dim3(256), 0, s, (double *)G, ld);
+}
+
 static int pick_split(int64_t n_tiles, int64_t k_pad, int bk) {
   const int64_t target = 2048;  // workgroups to cover 256 CUs several times
   int64_t s = (target + n_tiles - 1) / n_tiles;

@@ -341,65 +341,96 @@ void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT
 }
 
 // ------------------------------------------------------------- A build
-// A[row][k], k = n * n_m + m, row-major [r_pad][k_pad]; rows >= n_R and
-// k >= n_chi * n_m are zero.  Each thread writes 8 consecutive k.
+// A[row][k], k = n * n_m + m, row-major [r_pad][lda]; rows >= n_R and
+// k >= n_chi * n_m are zero.  A row of A is T_row(chi_n) G_cfg(chi_n, M_m),
+// and consecutive rows mostly share their configuration, so each block holds
+// 8 consecutive k of G_cfg per thread in registers and writes them, times
+// T_row, for AB_ROWS consecutive rows, reloading G only where the
+// configuration changes.  The write traffic is the kernel's whole HBM cost.
+constexpr int AB_ROWS = 16;
+
 template <int FMT>
-__global__ void k_abuild(const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int n_chi, int n_m,
-                         int64_t k_pad, void *A0, void *A1) {
-  const int64_t row = blockIdx.y;
+__global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
+                                               const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
+                                               int64_t k_pad, int64_t lda, void *A0, void *A1) {
   const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
   if (k0 >= k_pad) return;
   const int64_t k_len = (int64_t)n_chi * n_m;
-  double v[8];
-  if (row < n_R) {
-    const int c = rowR[4 * row];
-    const double *Tr = Ts + (size_t)row * n_chi;
-    const double *Gc = G + (size_t)c * n_chi * n_m;
+  int nq[8];
+  {
     int n = (int)(k0 / n_m), m = (int)(k0 % n_m);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int64_t k = k0 + q;
-      v[q] = k < k_len ? Tr[n] * Gc[(size_t)n * n_m + m] : 0.0;
+      nq[q] = k0 + q < k_len ? n : -1;
       if (++m == n_m) { m = 0; ++n; }
     }
-  } else {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = 0.0;
   }
-  const size_t off = (size_t)row * k_pad + k0;
-  if constexpr (FMT == 0) {
-    double *o = (double *)A0 + off;
+  double g[8];
+  int cc = -1;
+  const int64_t r0 = (int64_t)blockIdx.y * AB_ROWS;
+  for (int rr = 0; rr < AB_ROWS; ++rr) {
+    const int64_t row = r0 + rr;
+    double v[8];
+    if (row < n_R) {
+      const int c = rowR[4 * row];
+      if (c != cc) {
+        cc = c;
+        const double *Gc = G + (size_t)c * k_len + k0;
+        if (k0 + 8 <= k_len) {
 #pragma unroll
-    for (int q = 0; q < 8; q += 2) *(double2 *)(o + q) = make_double2(v[q], v[q + 1]);
-  } else if constexpr (FMT == 3) {
-    float *o = (float *)A0 + off;
-    *(float4 *)o = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
-    *(float4 *)(o + 4) = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
-  } else {
-    uint32_t hi[4], lo[4];
+          for (int q = 0; q < 8; q += 2) {
+            const double2 t = *(const double2 *)(Gc + q);
+            g[q] = t.x;
+            g[q + 1] = t.y;
+          }
+        } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float x0 = (float)v[2 * q], x1 = (float)v[2 * q + 1];
-      const uint16_t h0 = f32_to_bf16_rne(x0), h1 = f32_to_bf16_rne(x1);
-      hi[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-      if constexpr (FMT == 2) {
-        const uint16_t g0 = f32_to_bf16_rne(x0 - bf16_to_f32(h0)), g1 = f32_to_bf16_rne(x1 - bf16_to_f32(h1));
-        lo[q] = (uint32_t)g0 | ((uint32_t)g1 << 16);
+          for (int q = 0; q < 8; ++q) g[q] = nq[q] >= 0 ? Gc[q] : 0.0;
+        }
       }
+      const double *Tr = Ts + (size_t)row * n_chi;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = nq[q] >= 0 ? Tr[nq[q]] * g[q] : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = 0.0;
     }
-    *(u32x4 *)((uint16_t *)A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
-    if constexpr (FMT == 2) *(u32x4 *)((uint16_t *)A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+    const size_t off = (size_t)row * lda + k0;
+    if constexpr (FMT == 0) {
+      double *o = (double *)A0 + off;
+#pragma unroll
+      for (int q = 0; q < 8; q += 2) *(double2 *)(o + q) = make_double2(v[q], v[q + 1]);
+    } else if constexpr (FMT == 3) {
+      float *o = (float *)A0 + off;
+      *(float4 *)o = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+      *(float4 *)(o + 4) = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+    } else {
+      uint32_t hi[4], lo[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float x0 = (float)v[2 * q], x1 = (float)v[2 * q + 1];
+        const uint16_t h0 = f32_to_bf16_rne(x0), h1 = f32_to_bf16_rne(x1);
+        hi[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        if constexpr (FMT == 2) {
+          const uint16_t g0 = f32_to_bf16_rne(x0 - bf16_to_f32(h0)), g1 = f32_to_bf16_rne(x1 - bf16_to_f32(h1));
+          lo[q] = (uint32_t)g0 | ((uint32_t)g1 << 16);
+        }
+      }
+      *(u32x4 *)((uint16_t *)A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
+      if constexpr (FMT == 2) *(u32x4 *)((uint16_t *)A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+    }
   }
 }
 
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
-                   int n_chi, int n_m, int64_t k_pad, void *A0, void *A1, hipStream_t s) {
-  const dim3 grid((unsigned)((k_pad / 8 + 255) / 256), (unsigned)r_pad);
+                   int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s) {
+  // r_pad is a multiple of AB_ROWS (rows are padded to the Gram tile)
+  const dim3 grid((unsigned)((k_pad / 8 + 255) / 256), (unsigned)((r_pad + AB_ROWS - 1) / AB_ROWS));
   switch (fmt) {
-    case 0: hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
-    case 1: hipLaunchKernelGGL(k_abuild<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
-    case 2: hipLaunchKernelGGL(k_abuild<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
-    default: hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, A0, A1); break;
+    case 0: hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
+    case 1: hipLaunchKernelGGL(k_abuild<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
+    case 2: hipLaunchKernelGGL(k_abuild<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
+    default: hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
   }
 }
 

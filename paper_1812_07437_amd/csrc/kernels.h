@@ -24,7 +24,7 @@ void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT
                     double *Ts, int32_t *sexp, hipStream_t s);
 // fmt: 0 = f64, 1 = bf16 (hi only), 2 = bf16 hi + lo, 3 = f32
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
-                   int n_chi, int n_m, int64_t k_pad, void *A0, void *A1, hipStream_t s);
+                   int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s);
 
 // ---- Gram product (k_gram.hip): lower-triangle tiles of A A^T
 struct GramShape {
@@ -36,13 +36,16 @@ struct GramShape {
 size_t gram_partial_bytes(int prec, const GramShape &g);
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
                  hipStream_t s);
+// Copy the lower triangle of the first n rows/columns of G (row pitch ld,
+// f32 or f64) onto the upper one, so that G is exactly symmetric.
+void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s);
 
 // ---- assembly (k_assemble.hip)
 struct AsmArgs {
   const int32_t *rowO;    // [n][8]: cfg, e, z0, z1, z2, l0, l1, l2
   const int32_t *cfgT;    // [n_cfg][4]: kind, l0, l1, l2
   const int32_t *sexp;    // [n_R] row exponents of A
-  const void *Gm;         // [r_pad][r_pad] lower tiles, f64 or f32
+  const void *Gm;         // [r_pad][r_pad], f64 or f32, symmetric on the first n_R rows
   int64_t ld_g;
   int gm_f32;
   const double *Ps;       // [n_ell][n_z][n_z]
