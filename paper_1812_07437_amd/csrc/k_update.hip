@@ -164,14 +164,26 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
   const int64_t tr = (r1 - c0 + UT2 - 1) / UT2, tc = (c1 - c0 + UT2 - 1) / UT2;
   const int tri = tr == tc;
   const int64_t tiles = tri ? tr * (tr + 1) / 2 : tr * tc;
-  // split the k range when the tiles alone cannot fill the chip, keeping at
-  // least 512 k per slice and the scratch (slices x rows x 256 doubles)
-  // within the part_rows x 256 doubles the caller reserved
+  // Split the k range so that the workgroups fill whole rounds of the chip's
+  // resident slots (two per CU): a launch takes about
+  // ceil(tiles ns / slots) rounds of (ksteps / ns + 3) k-steps, the 3 being
+  // a slice's pipeline fill and partial-tile traffic.  Each slice keeps at
+  // least 32 k-steps, and the scratch (slices x rows x 256 doubles) stays
+  // within the part_rows x 256 doubles the caller reserved.  The choice
+  // depends only on the shape, so results stay deterministic.
   int ns = 1;
   if (part && c1 - c0 <= 256) {
     const int64_t ksteps = (k1 - k0 + UBK - 1) / UBK;
-    while (ns < 64 && tiles * ns < 1024 && ksteps / (2 * ns) >= 32 && (int64_t)(2 * ns) * (r1 - c0) <= part_rows)
-      ns *= 2;
+    const int64_t slots = 2 * 256;
+    double best = (double)((tiles + slots - 1) / slots) * (double)(ksteps + 3);
+    for (int q = 2; q <= 64; ++q) {
+      if (ksteps / q < 32 || (int64_t)q * (r1 - c0) > part_rows) break;
+      const double cost = (double)((tiles * q + slots - 1) / slots) * ((double)ksteps / q + 3.0);
+      if (cost < best) {
+        best = cost;
+        ns = q;
+      }
+    }
   }
   const int64_t ksplit = ((k1 - k0 + UBK - 1) / UBK + ns - 1) / ns * UBK;
   hipLaunchKernelGGL(k_update2, dim3((unsigned)(tiles * ns)), dim3(256), 0, s, Wm, ld, c0, r1, c1, k0, k1, tri, tc, ns,
