@@ -48,61 +48,117 @@ void launch_chol_prep(const void *C, int c_f32, const int32_t *row_exp2, const d
 }
 
 // ------------------------------------------------------------- diagonal block
-// One wavefront, lane r owning row r of the jb x jb diagonal block at j0
-// (rows beyond jb padded with the identity):
-//   L[r][k] = (A[r][k] - sum_{q<k} L[r][q] L[k][q]) / L[k][k]    (column by column)
-//   X = L^-1, lane c solving column c of L X = I by forward substitution.
-// Writes L back and X to Linv (row-major, NB columns).
-__device__ __forceinline__ double dot_lds(const double *a, const double *b, int n) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int q = 0;
-  for (; q + 4 <= n; q += 4) {
-    s0 += a[q] * b[q];
-    s1 += a[q + 1] * b[q + 1];
-    s2 += a[q + 2] * b[q + 2];
-    s3 += a[q + 3] * b[q + 3];
-  }
-  for (; q < n; ++q) s0 += a[q] * b[q];
-  return (s0 + s1) + (s2 + s3);
+// One workgroup of 256 threads on the jb x jb diagonal block at j0 (rows
+// beyond jb padded with the identity), held in registers: thread
+// t = 16 tj + ti owns rows 4 ti .. 4 ti + 3 and columns 4 tj .. 4 tj + 3.
+// The factorisation runs square-root free, as A = U D U^T with U unit lower:
+// at step k the owners of column k publish it in LDS as it stands (the
+// Schur complement column, d_k = its diagonal entry), and after one barrier
+// every thread applies -a[i][k] a[j][k] / d_k to its block.  Then
+// L = U D^1/2, i.e. L[i][k] = a[i][k] / sqrt(d_k), in one parallel pass.
+// X = L^-1 follows by forward substitution in the same order: the owners of
+// row q scale it by 1 / L[q][q] and publish it, and the rows below subtract
+// L[i][q] X[q][:].  Each step is a chain of dependent instructions, so it
+// holds no square root and one division, and the updates mask the
+// broadcast factors rather than each product; entries above the diagonal
+// of a thread's block take harmless updates and are never read.  The
+// published vectors alternate between two LDS buffers, so one barrier per
+// step suffices.  Writes L back and X to Linv (row-major, NB columns).
+__device__ __forceinline__ double pick4(const double (&v)[4], int c) {
+  return c == 0 ? v[0] : c == 1 ? v[1] : c == 2 ? v[2] : v[3];
 }
 
-__global__ __launch_bounds__(64) void k_potrf_diag(double *__restrict__ Wm, int64_t ld, int64_t j0, int jb,
-                                                   double *__restrict__ Linv, int *__restrict__ flag) {
-  __shared__ double A[NB][NB + 1];
-  __shared__ double Xt[NB][NB + 1];  // Xt[c][r] = X[r][c]
-  const int r = threadIdx.x;
-  for (int q = r; q < NB * NB; q += NB) {
-    const int i = q / NB, c = q % NB;
-    double v = 0.0;
-    if (i < jb && c <= i) v = Wm[(j0 + i) * ld + j0 + c];
-    else if (i >= jb && i == c) v = 1.0;
-    A[i][c] = v;
-  }
-  __syncthreads();
-  bool bad = false;
+__global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ Wm, int64_t ld, int64_t j0, int jb,
+                                                    double *__restrict__ Linv, int *__restrict__ flag) {
+  __shared__ double vec[2][NB];
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double dsq[NB], dinv[NB];  // sqrt(d_k) and its reciprocal
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int ti = tid & 15, tj = tid >> 4;
+  const int i0 = 4 * ti, c0 = 4 * tj;
+  double a[4][4], x[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + r, j = c0 + c;
+      double v = 0.0;
+      if (i < jb && j <= i) v = Wm[(j0 + i) * ld + j0 + j];
+      else if (i >= jb && i == j) v = 1.0;
+      a[r][c] = v;
+      x[r][c] = i == j ? 1.0 : 0.0;
+    }
+  if (tid == 0) bad = 0;
   for (int k = 0; k < NB; ++k) {
-    const double v = A[r][k] - dot_lds(A[r], A[k], k);
-    if (r == k) {
-      bad |= !(v > 0.0);
-      A[k][k] = sqrt(v > 0.0 ? v : 1.0);
+    const int kb = k >> 2, kc = k & 3, buf = k & 1;
+    if (tj == kb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) vec[buf][i0 + r] = pick4(a[r], kc);
     }
     __syncthreads();
-    if (r > k) A[r][k] = v / A[k][k];
-    __syncthreads();
-  }
-  // column r of X = L^-1 (lane r), stored transposed so the solve reads a row
-  for (int i = 0; i < NB; ++i) {
-    double s = (i == r) ? 1.0 : 0.0;
-    if (i > r) s -= dot_lds(&A[i][r], &Xt[r][r], i - r);
-    Xt[r][i] = i >= r ? s / A[i][i] : 0.0;
+    const double dk = vec[buf][k];
+    const double rd = dk > 0.0 ? 1.0 / dk : 0.0;
+    double li[4], lj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      li[q] = i0 + q > k ? vec[buf][i0 + q] : 0.0;
+      lj[q] = c0 + q > k ? vec[buf][c0 + q] * rd : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[r][c] -= li[r] * lj[c];
+    if (tid == k) {
+      if (!(dk > 0.0)) bad = 1;
+      const double sq = sqrt(dk > 0.0 ? dk : 1.0);
+      dsq[k] = sq;
+      dinv[k] = 1.0 / sq;
+    }
   }
   __syncthreads();
-  for (int q = r; q < NB * NB; q += NB) {
-    const int i = q / NB, c = q % NB;
-    if (i < jb && c <= i) Wm[(j0 + i) * ld + j0 + c] = A[i][c];
-    Linv[q] = Xt[c][i];
+  // L = U D^1/2 to LDS (and back to the matrix), then the inverse
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + r, j = c0 + c;
+      const double l = j < i ? a[r][c] * dinv[j] : (j == i ? dsq[j] : 0.0);
+      Ls[i][j] = l;
+      if (i < jb && j <= i) Wm[(j0 + i) * ld + j0 + j] = l;
+    }
+  __syncthreads();
+  for (int q = 0; q < NB; ++q) {
+    const int qb = q >> 2, qc = q & 3, buf = q & 1;
+    if (ti == qb) {
+      const double rq = dinv[q];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r == qc) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            x[r][c] *= rq;
+            vec[buf][c0 + c] = x[r][c];
+          }
+        }
+    }
+    __syncthreads();
+    double xq[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xq[c] = vec[buf][c0 + c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double liq = i0 + r > q ? Ls[i0 + r][q] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[r][c] -= liq * xq[c];
+    }
   }
-  if (bad) atomicOr(flag, 1);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Linv[(i0 + r) * NB + c0 + c] = x[r][c];
+  __syncthreads();
+  if (tid == 0 && bad) atomicOr(flag, 1);
 }
 
 // ------------------------------------------------------------- panel solve
@@ -167,7 +223,7 @@ int chol_factor(double *Wm, int64_t n, int64_t ld, double *scratch, int *flag, h
     launch_update2(Wm, ld, J0, rows, Jend, 0, J0, part, chol_part_rows(n), s, probe);
     for (int64_t j0 = J0; j0 < Jend; j0 += NB) {
       const int jb = (int)std::min<int64_t>(NB, Jend - j0);
-      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, Wm, ld, j0, jb, Linv, flag);
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, Wm, ld, j0, jb, Linv, flag);
       const int64_t r0 = j0 + jb;
       if (r0 < rows) {
         const int64_t nblk = (rows - r0 + NB - 1) / NB;
