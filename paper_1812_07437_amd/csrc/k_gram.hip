@@ -90,14 +90,16 @@ __device__ __forceinline__ bool gram_work(int64_t n_work, int n_split, int nt, i
 // (two per SIMD).  Larger wavefront tiles read fewer LDS bytes per MFMA.  K advances
 // in stages of 32 through a double-buffered LDS tile ([256 rows][32 bf16] =
 // 64 B per row and operand); stage s + 2 is fetched into registers while
-// stage s is multiplied.  Chunk c (16 B) of row r sits at slot c ^ ((r/2)&3),
-// which keeps the 8 rows that one MFMA operand read touches at a time on
-// distinct banks.
+// stage s is multiplied.  Chunk c (16 B) of row r sits at slot
+// c ^ (((r >> 1) ^ (r >> 3)) & 3): the 16 consecutive rows that one MFMA
+// operand read touches at a time then fall on 16 distinct 16-byte bank
+// groups (and any 8 consecutive rows on 8), so operand reads and staging
+// writes are free of bank conflicts.
 constexpr int T2 = 256;
 constexpr int BK2 = 32;
 constexpr int GRAM_NW = 8;  // measured faster than 4 at both precisions
 
-__device__ __forceinline__ int swz2(int r, int c) { return r * BK2 + ((c ^ ((r >> 1) & 3)) << 3); }
+__device__ __forceinline__ int swz2(int r, int c) { return r * BK2 + ((c ^ (((r >> 1) ^ (r >> 3)) & 3)) << 3); }
 
 template <bool X3, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
