@@ -1,14 +1,17 @@
 // Block update of the FP64 Cholesky factorisation:
 //   W[i][j] -= sum_{q in [k0, k1)} W[i][q] W[j][q],  i in [c0, r1), j in [c0, c1), i >= j,
-// on 128 x 128 tiles.  Four wavefronts of 64 x 64 each on v_mfma_f64_16x16x4
+// on tiles of 128 rows by TC = 32 NW columns: NW = 4 wavefronts for 128 x 128
+// tiles, NW = 8 for 128 x 256 tiles that span a whole 256-wide panel, so that
+// each row slice is read once per launch (21.3 instead of 16 flops per
+// operand byte).  Each wavefront computes 64 x 64 on v_mfma_f64_16x16x4
 // (lane l holds row l % 16, k l / 16 of each operand; the accumulator value v
 // of lane l is row l / 16 + 4 v, column l % 16).  Operand slices are staged
 // through a double-buffered LDS tile in 16-wide k steps: step s + 2 is
 // fetched into registers and step s + 1 copied to LDS while step s is
-// multiplied, with one barrier per step.  The register budget is capped so
-// that two workgroups share a CU and cover each other's barrier waits.  A long k range may be split into slices whose partial products
-// go to a scratch buffer and are subtracted in a fixed order by a second
-// kernel, so results do not depend on scheduling.
+// multiplied, with one barrier per step.  The register budget is capped at
+// two wavefronts per SIMD.  A long k range may be split into slices whose
+// partial products go to a scratch buffer and are subtracted in a fixed order
+// by a second kernel, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,57 +37,65 @@ __device__ __forceinline__ void tile_of(int64_t t, int tri, int64_t tcols, int64
   }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update2(
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update2(
     double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1, int tri_grid,
     int64_t tcols, int n_split, int64_t k_split, double *__restrict__ part) {
-  __shared__ double lds[2][2][UT2 * ULDR];  // [buffer][I/J side]
+  constexpr int NT = 64 * NW;                // threads
+  constexpr int TC = 32 * NW;                // tile columns
+  constexpr int PR = UT2 * (UBK / 2) / NT;   // double2 chunks per thread, row side
+  constexpr int PC = TC * (UBK / 2) / NT;    // double2 chunks per thread, column side
+  __shared__ double lds[2][(UT2 + TC) * ULDR];  // [buffer][rows, then columns]
   int64_t ti, tj;
   tile_of(blockIdx.x / n_split, tri_grid, tcols, ti, tj);
   const int split = blockIdx.x % n_split;
-  const int64_t i0 = c0 + ti * UT2, j0 = c0 + tj * UT2;
+  const int64_t i0 = c0 + ti * UT2, j0 = c0 + tj * TC;
   if (j0 > i0 + UT2 - 1) return;  // entirely above the diagonal
   const int64_t kb = k0 + (int64_t)split * k_split;
   const int64_t ke = min(k1, kb + k_split);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave / (NW / 2)) * 64, wc = (wave % (NW / 2)) * 64;
   f64x4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  // 128 rows x 16 k per side = 1024 double2 chunks, 4 per thread
-  double2 pre[2][4];
-  auto gload = [&](int64_t kq) {
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int64_t base = side == 0 ? i0 : j0;
-      const int64_t lim = side == 0 ? r1 : c1;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int ch = tid + 256 * q;
-        const int r = ch >> 3, c = ch & 7;
-        const int64_t row = base + r, k = kq + 2 * c;
-        double2 v = make_double2(0.0, 0.0);
-        if (row < lim) {
-          const double *src = Wm + row * ld + k;
-          if (k + 1 < ke) v = *(const double2 *)src;
-          else if (k < ke) v.x = src[0];
-        }
-        pre[side][q] = v;
+  // each side: rows x 16 k as double2 chunks; chunk q is row q >> 3, pair q & 7
+  double2 pr[PR], pc[PC];
+  auto load_side = [&](double2 *dst, int per, int64_t base, int64_t lim, int64_t kq) {
+    for (int q = 0; q < per; ++q) {
+      const int ch = tid + NT * q;
+      const int r = ch >> 3, c = ch & 7;
+      const int64_t row = base + r, k = kq + 2 * c;
+      double2 v = make_double2(0.0, 0.0);
+      if (row < lim) {
+        const double *src = Wm + row * ld + k;
+        if (k + 1 < ke) v = *(const double2 *)src;
+        else if (k < ke) v.x = src[0];
       }
+      dst[q] = v;
     }
+  };
+  auto gload = [&](int64_t kq) {
+    load_side(pr, PR, i0, r1, kq);
+    load_side(pc, PC, j0, c1, kq);
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int side = 0; side < 2; ++side)
+    for (int q = 0; q < PR; ++q) {
+      const int ch = tid + NT * q;
+      const int r = ch >> 3, c = ch & 7;
+      lds[buf][r * ULDR + 2 * c] = pr[q].x;
+      lds[buf][r * ULDR + 2 * c + 1] = pr[q].y;
+    }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int ch = tid + 256 * q;
-        const int r = ch >> 3, c = ch & 7;
-        lds[buf][side][r * ULDR + 2 * c] = pre[side][q].x;
-        lds[buf][side][r * ULDR + 2 * c + 1] = pre[side][q].y;
-      }
+    for (int q = 0; q < PC; ++q) {
+      const int ch = tid + NT * q;
+      const int r = ch >> 3, c = ch & 7;
+      lds[buf][(UT2 + r) * ULDR + 2 * c] = pc[q].x;
+      lds[buf][(UT2 + r) * ULDR + 2 * c + 1] = pc[q].y;
+    }
   };
   auto compute = [&](int buf) {
 #pragma unroll
@@ -93,8 +104,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       double a[4], b[4];
 #pragma unroll
       for (int blk = 0; blk < 4; ++blk) {
-        a[blk] = lds[buf][0][(wr + blk * 16 + (lane & 15)) * ULDR + kc];
-        b[blk] = lds[buf][1][(wc + blk * 16 + (lane & 15)) * ULDR + kc];
+        a[blk] = lds[buf][(wr + blk * 16 + (lane & 15)) * ULDR + kc];
+        b[blk] = lds[buf][(UT2 + wc + blk * 16 + (lane & 15)) * ULDR + kc];
       }
 #pragma unroll
       for (int x = 0; x < 4; ++x)
@@ -119,8 +130,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
     __syncthreads();
   }
-  const int64_t pc = c1 - c0;
-  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pc : nullptr;
+  const int64_t pcols = c1 - c0;
+  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pcols : nullptr;
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -130,7 +141,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const int64_t i = i0 + wr + x * 16 + (lane >> 4) + 4 * v;
         const int64_t j = j0 + wc + y * 16 + (lane & 15);
         if (i < r1 && j < c1 && i >= j) {
-          if (pdst) pdst[(i - c0) * pc + (j - c0)] = acc[x][y][v];
+          if (pdst) pdst[(i - c0) * pcols + (j - c0)] = acc[x][y][v];
           else Wm[i * ld + j] -= acc[x][y][v];
         }
       }
@@ -161,20 +172,24 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
     ++probe->launches;
   }
   if (timed) (void)hipEventRecord(probe->ev[2 * probe->count], s);
-  const int64_t tr = (r1 - c0 + UT2 - 1) / UT2, tc = (c1 - c0 + UT2 - 1) / UT2;
-  const int tri = tr == tc;
+  // a whole 256-wide panel below its diagonal block goes on 128 x 256 tiles
+  const bool wide = c1 - c0 > UT2 && c1 - c0 <= 2 * UT2 && r1 - c0 > 2 * UT2;
+  const int64_t tcw = wide ? 2 * UT2 : UT2;
+  const int64_t tr = (r1 - c0 + UT2 - 1) / UT2, tc = (c1 - c0 + tcw - 1) / tcw;
+  const int tri = !wide && tr == tc;
   const int64_t tiles = tri ? tr * (tr + 1) / 2 : tr * tc;
   // Split the k range so that the workgroups fill whole rounds of the chip's
-  // resident slots (two per CU): a launch takes about
-  // ceil(tiles ns / slots) rounds of (ksteps / ns + 3) k-steps, the 3 being
-  // a slice's pipeline fill and partial-tile traffic.  Each slice keeps at
-  // least 32 k-steps, and the scratch (slices x rows x 256 doubles) stays
-  // within the part_rows x 256 doubles the caller reserved.  The choice
-  // depends only on the shape, so results stay deterministic.
+  // resident slots (two 4-wavefront or one 8-wavefront workgroup per CU): a
+  // launch takes about ceil(tiles ns / slots) rounds of (ksteps / ns + 3)
+  // k-steps, the 3 being a slice's pipeline fill and partial-tile traffic.
+  // Each slice keeps at least 32 k-steps, and the scratch (slices x rows x
+  // 256 doubles) stays within the part_rows x 256 doubles the caller
+  // reserved.  The choice depends only on the shape, so results stay
+  // deterministic.
   int ns = 1;
   if (part && c1 - c0 <= 256) {
     const int64_t ksteps = (k1 - k0 + UBK - 1) / UBK;
-    const int64_t slots = 2 * 256;
+    const int64_t slots = wide ? 256 : 2 * 256;
     double best = (double)((tiles + slots - 1) / slots) * (double)(ksteps + 3);
     for (int q = 2; q <= 64; ++q) {
       if (ksteps / q < 32 || (int64_t)q * (r1 - c0) > part_rows) break;
@@ -186,8 +201,12 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
     }
   }
   const int64_t ksplit = ((k1 - k0 + UBK - 1) / UBK + ns - 1) / ns * UBK;
-  hipLaunchKernelGGL(k_update2, dim3((unsigned)(tiles * ns)), dim3(256), 0, s, Wm, ld, c0, r1, c1, k0, k1, tri, tc, ns,
-                     ksplit, part);
+  if (wide)
+    hipLaunchKernelGGL(k_update2<8>, dim3((unsigned)(tiles * ns)), dim3(512), 0, s, Wm, ld, c0, r1, c1, k0, k1, tri,
+                       tc, ns, ksplit, part);
+  else
+    hipLaunchKernelGGL(k_update2<4>, dim3((unsigned)(tiles * ns)), dim3(256), 0, s, Wm, ld, c0, r1, c1, k0, k1, tri,
+                       tc, ns, ksplit, part);
   if (ns > 1) {
     const int64_t total = (r1 - c0) * (c1 - c0);
     const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
