@@ -47,6 +47,31 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(*names):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    runs (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the record
+    is missing or the kernel's source has changed since the counters were
+    taken.  Several names are summed over their launches and divided by the
+    launches of the first (a kernel and its helper timed as one launch)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    total, launches = 0.0, None
+    for n in names:
+        r = rec.get(n)
+        if r is None or r.get("fetch_bytes_per_launch") is None or r.get("write_bytes_per_launch") is None:
+            return None
+        with open(os.path.join(ROOT, r["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != r["source_sha256"]:
+                return None
+        total += (r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"]) * r["launches"]
+        launches = launches or r["launches"]
+    return dict(bytes_per_launch=total / launches, summary=rec[names[0]]["summary"])
+
+
 def gram_flops(n_r, k_len, precision):
     """Useful flops of the one-halo Gram: each of the n_r (n_r + 1)/2 distinct
     entries is a length-K dot product (2K flops); the split bf16 product does
@@ -262,15 +287,19 @@ def main():
     upd_ms = upd["ms"] / max(upd_frac_timed, 1e-9)
     upd_tf = upd["flops"] / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
     if upd_ms >= ph["gram"]:
+        tr = measured_traffic("k_update2", "k_update_reduce")
         roof = dict(bound="mfma", kernel="k_update2 (FP64 Cholesky block update, incl. split-k reduce)",
                     achieved=upd_tf, peak=PEAK_TFLOPS["fp64"], unit="TFLOP/s", frac=upd_tf / PEAK_TFLOPS["fp64"],
-                    traffic=None, launches=upd["launches"], avg_launch_ms=upd_ms / max(upd["launches"], 1),
-                    flops_per_step=upd["flops"])
+                    traffic=tr["bytes_per_launch"] / 1e9 if tr else None, launches=upd["launches"],
+                    avg_launch_ms=upd_ms / max(upd["launches"], 1), flops_per_step=upd["flops"])
     else:
+        tr = measured_traffic("k_gram_bf16")
         roof = dict(bound="mfma", kernel="k_gram_bf16<x3> (one-halo Gram)", achieved=gram_tf,
                     peak=PEAK_TFLOPS[args.precision], unit="TFLOP/s", frac=gram_tf / PEAK_TFLOPS[args.precision],
-                    traffic=None, launches=1, avg_launch_ms=ph["gram"],
+                    traffic=tr["bytes_per_launch"] / 1e9 if tr else None, launches=1, avg_launch_ms=ph["gram"],
                     flops_per_step=gram_flops(NR, K, args.precision))
+    roof["traffic_unit"] = "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["traffic_source"] = tr["summary"] if tr else None
     a_bytes = NR * K * {"bf16": 2, "bf16x3": 4, "fp32": 4, "fp64": 8}[args.precision]
     c_bytes = N * N * (8 if args.precision == "fp64" else 4)
     kernels = dict(
