@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--workload", default="large10")
     ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--chi-steps", type=int, default=1,
+                    help="steps of the FP64 path with the one-halo term factorised along chi (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=12,
@@ -274,7 +276,27 @@ def main():
                     err_vs_fp64={"diag_max_rel": err_diag, "snr2_rel": err_snr})
         log("fp64: %.1f ms/step  gram %.1f ms  diag err %.2e  snr err %.2e" % (fp64["ms_per_step"], ph64["gram"],
                                                                            err_diag, err_snr))
+        fp64["snr2"] = snr64[-1]
         del p64
+        torch.cuda.empty_cache()
+
+    # FP64 path with the one-halo sum taken over M first and chi second
+    # (exact; N_M times fewer one-halo operations than the flattened Gram)
+    chi = None
+    if args.chi_steps > 0:
+        log("fp64 chi-factorised path")
+        pc = wl.Problem(cfg, t.arrays(), precision="fp64_chi", device="cuda:0")
+        dtc, phc, snrc, _ = timed_steps(pc, args.chi_steps, 1, torch, wl)
+        n_cfg = int(pc.sizes.n_cfg)
+        chi_flops = NR * (NR + 1) * cfg["n_chi"] + 2.0 * n_cfg * n_cfg * cfg["n_chi"] * cfg["n_m"]
+        ref_snr = fp64["snr2"] if fp64 else snr_mixed
+        chi = dict(ms_per_step=dtc / args.chi_steps * 1e3, value=entries / (dtc / args.chi_steps), phases_ms=phc,
+                   one_halo_ms=phc["gram"], one_halo_tflops=chi_flops / (phc["gram"] * 1e-3) / 1e12,
+                   one_halo_speedup_vs_mixed_gram=ph["gram"] / max(phc["gram"], 1e-9),
+                   snr2_rel_vs=("fp64" if fp64 else args.precision), snr2_rel=abs(snrc[-1] - ref_snr) / ref_snr)
+        log("fp64 chi: %.1f ms/step  one-halo %.2f ms  snr rel %.2e" % (chi["ms_per_step"], phc["gram"],
+                                                                      chi["snr2_rel"]))
+        del pc
         torch.cuda.empty_cache()
 
     # roofline of the dominant kernel of the step: the one-halo Gram (one
@@ -337,6 +359,7 @@ def main():
         "distinct_entries_per_s": NR * (NR + 1) / 2 / (dt / args.steps),
         "snr": math.sqrt(snr_mixed) if snr_mixed > 0 else None,
         "fp64_path": fp64,
+        "fp64_chi_path": chi,
         "serving": srv,
     }
     print(json.dumps(out), flush=True)

@@ -47,12 +47,15 @@ enum {
 enum { WLC_TOMO_PAPER = 0, WLC_TOMO_SORTED = 1 };
 
 /* ---- arithmetic of the one-halo Gram product (everything else is FP64)
- * FP64   : f64 MFMA, FP64 covariance output;
- * BF16   : bf16 MFMA with FP32 accumulation, FP32 covariance output;
- * BF16X3 : split bf16 (hi + lo) compensated product hi.hi + hi.lo + lo.hi;
- * FP32   : f32 MFMA;
+ * FP64     : f64 MFMA on the flattened (chi, M) axis, FP64 covariance output;
+ * BF16     : bf16 MFMA with FP32 accumulation, FP32 covariance output;
+ * BF16X3   : split bf16 (hi + lo) compensated product hi.hi + hi.lo + lo.hi;
+ * FP32     : f32 MFMA;
+ * FP64_CHI : FP64, the same sum taken over M first and then over chi (the
+ *            factorisation of eq. General1h along the line of sight),
+ *            N_M times fewer operations; FP64 covariance output.
  * BF16X3 and FP32 also return an FP32 covariance. */
-enum { WLC_FP64 = 0, WLC_BF16 = 1, WLC_BF16X3 = 2, WLC_FP32 = 3 };
+enum { WLC_FP64 = 0, WLC_BF16 = 1, WLC_BF16X3 = 2, WLC_FP32 = 3, WLC_FP64_CHI = 4 };
 
 /* ---- flags */
 enum {

@@ -52,7 +52,7 @@ constexpr int64_t K_ALIGN = 64;
 enum Buf {
   B_ROWR, B_ROWO, B_CFGT, B_CENT, B_NMODES, B_NTRI, B_THR, B_TRI, B_FLAGS,
   B_U, B_PK, B_NE, B_X, B_R, B_DR, B_RR, B_PS, B_G, B_GMAX, B_TS, B_SEXP,
-  B_A0, B_A1, B_GM, B_PART, NBUF
+  B_A0, B_A1, B_GM, B_PART, B_H, NBUF
 };
 
 struct Layout {
@@ -83,13 +83,15 @@ static Layout run_layout(const Plan &p) {
   sz[B_GMAX] = (size_t)n_cfg * c.n_chi * 8;
   sz[B_TS] = (size_t)p.n_R * c.n_chi * 8;
   sz[B_SEXP] = (size_t)p.n_R * 4;
+  const bool chi = c.precision == WLC_FP64_CHI;
   const size_t ael = c.precision == WLC_FP64 ? 8 : (c.precision == WLC_FP32 ? 4 : 2);
-  sz[B_A0] = (size_t)p.r_pad * p.k_pad * ael;
+  sz[B_A0] = chi ? 0 : (size_t)p.r_pad * p.k_pad * ael;
   sz[B_A1] = c.precision == WLC_BF16X3 ? sz[B_A0] : 0;
-  const size_t gel = c.precision == WLC_FP64 ? 8 : 4;
+  const size_t gel = prec_f64(c.precision) ? 8 : 4;
   sz[B_GM] = (size_t)p.r_pad * p.r_pad * gel;
   GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
-  sz[B_PART] = gram_partial_bytes(c.precision, g);
+  sz[B_PART] = chi ? 0 : gram_partial_bytes(c.precision, g);
+  sz[B_H] = chi ? (size_t)n_cfg * n_cfg * c.n_chi * 8 : 0;
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < NBUF; ++b) {
@@ -228,16 +230,27 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
   if (hooks) hooks->end(WLC_PHASE_TABLES);
 
-  const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
-  void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
-  if (hooks) hooks->begin(WLC_PHASE_ABUILD);
-  launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, p.k_pad, A0, A1, s);
-  if (hooks) hooks->end(WLC_PHASE_ABUILD);
-  GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
   void *Gm = at<void>(ws, L, B_GM);
-  if (hooks) hooks->begin(WLC_PHASE_GRAM);
-  launch_gram(c.precision, g, A0, A1, Gm, at<void>(ws, L, B_PART), s);
-  if (hooks) hooks->end(WLC_PHASE_GRAM);
+  if (c.precision == WLC_FP64_CHI) {
+    // no flattened factor: the one-halo product from T and G directly
+    if (hooks) hooks->begin(WLC_PHASE_ABUILD);
+    if (hooks) hooks->end(WLC_PHASE_ABUILD);
+    if (hooks) hooks->begin(WLC_PHASE_GRAM);
+    const int nz = c.n_z;
+    launch_chifact(Ts, G, at<double>(ws, L, B_H), n_cfg, c.n_chi, c.n_m, p.n_ell, nz * (nz + 1) / 2,
+                   nz * (nz + 1) * (nz + 2) / 6, p.n_tri, (double *)Gm, p.r_pad, s);
+    if (hooks) hooks->end(WLC_PHASE_GRAM);
+  } else {
+    const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
+    void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
+    if (hooks) hooks->begin(WLC_PHASE_ABUILD);
+    launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, p.k_pad, A0, A1, s);
+    if (hooks) hooks->end(WLC_PHASE_ABUILD);
+    GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
+    if (hooks) hooks->begin(WLC_PHASE_GRAM);
+    launch_gram(c.precision, g, A0, A1, Gm, at<void>(ws, L, B_PART), s);
+    if (hooks) hooks->end(WLC_PHASE_GRAM);
+  }
 
   AsmArgs a{};
   a.rowO = at<int32_t>(ws, L, B_ROWO);
@@ -245,7 +258,7 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   a.sexp = sexp;
   a.Gm = Gm;
   a.ld_g = p.r_pad;
-  a.gm_f32 = c.precision != WLC_FP64;
+  a.gm_f32 = !prec_f64(c.precision);
   a.Ps = Ps;
   a.nmodes = at<double>(ws, L, B_NMODES);
   a.ntri = tb.n_tri ? tb.n_tri : at<double>(ws, L, B_NTRI);
@@ -260,7 +273,7 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   if (hooks) hooks->begin(WLC_PHASE_ASSEMBLE);
   launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
   launch_rowexp(a, row_exp2, d, r, s);
-  launch_assemble(a, row_exp2, C, c.precision != WLC_FP64, s);
+  launch_assemble(a, row_exp2, C, !prec_f64(c.precision), s);
   if (hooks) hooks->end(WLC_PHASE_ASSEMBLE);
   return hip_check(hipGetLastError(), "run launch");
 }
@@ -278,7 +291,7 @@ int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const dou
   double *out = reinterpret_cast<double *>(base + o);
   if (hooks) hooks->begin(WLC_PHASE_SNR_PREP);
   launch_fill_i32(flag, 1, 0, s);
-  launch_chol_prep(C, p.cfg.precision != WLC_FP64, row_exp2, d, n, ld, Wm, s);
+  launch_chol_prep(C, !prec_f64(p.cfg.precision), row_exp2, d, n, ld, Wm, s);
   if (hooks) hooks->end(WLC_PHASE_SNR_PREP);
   if (hooks) hooks->begin(WLC_PHASE_CHOL);
   chol_factor(Wm, n, ld, scratch, flag, s, probe);
@@ -388,7 +401,7 @@ int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out) {
   out->n_cfg = (int64_t)p.cfgs.size();
   out->n_ell_used = p.n_ell;
   out->k_len = p.k_len;
-  out->c_elem_bytes = p.cfg.precision == WLC_FP64 ? 8 : 4;
+  out->c_elem_bytes = prec_f64(p.cfg.precision) ? 8 : 4;
   out->ws_run_bytes = p.ws_run;
   out->ws_snr_bytes = p.ws_snr;
   return WLC_OK;

@@ -36,6 +36,13 @@ struct GramShape {
 size_t gram_partial_bytes(int prec, const GramShape &g);
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
                  hipStream_t s);
+// One-halo product through the chi factorisation (k_chifact.hip): H (scratch,
+// n_cfg^2 n_chi doubles) from the configuration factors G, then the lower
+// triangle of out[e][f] = sum_n Ts[e][n] Ts[f][n] H[c(e)][c(f)][n] over the
+// distinct rows, grouped by configuration in blocks of sp (power spectrum)
+// and sb (bispectrum) rows.
+void launch_chifact(const double *Ts, const double *G, double *H, int n_cfg, int n_chi, int n_m, int nl, int sp,
+                    int sb, int n_tri, double *out, int64_t ld, hipStream_t s);
 // Copy the lower triangle of the first n rows/columns of G (row pitch ld,
 // f32 or f64) onto the upper one, so that G is exactly symmetric.
 void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s);

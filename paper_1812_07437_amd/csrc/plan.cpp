@@ -43,7 +43,7 @@ int build_plan(const wlc_config &c, Plan &p) {
     return fail(WLC_EINVAL, "survey scalars must be finite and positive");
   if (c.tomo_mode != WLC_TOMO_PAPER && c.tomo_mode != WLC_TOMO_SORTED)
     return fail(WLC_EINVAL, "unknown tomo_mode");
-  if (c.precision < WLC_FP64 || c.precision > WLC_FP32) return fail(WLC_EINVAL, "unknown precision");
+  if (!prec_valid(c.precision)) return fail(WLC_EINVAL, "unknown precision");
   p.cfg = c;
   const int nz = c.n_z;
 

@@ -38,6 +38,11 @@ struct Plan {
   size_t ws_run = 0, ws_snr = 0;
 };
 
+// Precision modes: valid range, and whether the covariance (and the Gram
+// output) is FP64.
+inline bool prec_valid(int p) { return p >= WLC_FP64 && p <= WLC_FP64_CHI; }
+inline bool prec_f64(int p) { return p == WLC_FP64 || p == WLC_FP64_CHI; }
+
 void set_error(const std::string &msg);
 const char *last_error();
 int fail(int code, const std::string &msg);

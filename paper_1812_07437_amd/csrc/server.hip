@@ -147,7 +147,7 @@ struct wlc_server_s {
     R.d = (double *)take(n * 8);
     R.r = (double *)take(n * 8);
     R.t = (int32_t *)take(n * 4);
-    R.C = take((size_t)n * n * (p.cfg.precision == WLC_FP64 ? 8 : 4));
+    R.C = take((size_t)n * n * (prec_f64(p.cfg.precision) ? 8 : 4));
     R.P = (double *)take((size_t)base_cfg().n_chi * base_cfg().n_k * 8);
     R.nm = (double *)take((size_t)base_cfg().n_m * 8);
     R.Wd = (double *)take(R.W.size() * 8);
@@ -245,7 +245,7 @@ struct wlc_server_s {
 static void fill_result(const Request &R, wlc_result *res) {
   res->status = R.status;
   res->n_data = R.plan->n_out;
-  res->c_elem_bytes = R.plan->cfg.precision == WLC_FP64 ? 8 : 4;
+  res->c_elem_bytes = prec_f64(R.plan->cfg.precision) ? 8 : 4;
   res->snr2 = R.snr2;
   res->t_submit_ms = R.t_submit;
   res->t_admit_ms = R.t_admit;
@@ -299,7 +299,7 @@ int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t
 int wlc_server_submit(wlc_server srv, const wlc_request *q, uint64_t *ticket) {
   if (!srv || !q || !ticket || !q->W) return fail(WLC_EINVAL, "null argument");
   if (q->n_z < 1 || q->n_z > 64 || !(q->p_scale > 0.0) || !(q->n_scale > 0.0) || !(q->rho_mean > 0.0) ||
-      q->precision < WLC_FP64 || q->precision > WLC_FP32)
+      !prec_valid(q->precision))
     return fail(WLC_EINVAL, "bad request");
   wlc_config cfg = srv->base;
   cfg.n_z = q->n_z;
@@ -321,7 +321,7 @@ int wlc_server_submit(wlc_server srv, const wlc_request *q, uint64_t *ticket) {
   }
   const int64_t n = plan->n_out;
   const size_t foot = a256(plan->ws_run) + a256(plan->ws_snr) + 2 * a256(n * 8) + a256(n * 4) +
-                      a256((size_t)n * n * (q->precision == WLC_FP64 ? 8 : 4)) +
+                      a256((size_t)n * n * (prec_f64(q->precision) ? 8 : 4)) +
                       a256((size_t)cfg.n_chi * cfg.n_k * 8) + a256((size_t)cfg.n_m * 8) +
                       a256((size_t)q->n_z * cfg.n_chi * 8);
   if (foot > srv->arena->size()) return fail(WLC_EBUSY, "request footprint exceeds the server arena");
@@ -374,7 +374,7 @@ int wlc_server_copy(wlc_server srv, uint64_t ticket, double *d, double *r, void 
   }
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = R->plan->n_out;
-  const size_t ce = R->plan->cfg.precision == WLC_FP64 ? 8 : 4;
+  const size_t ce = prec_f64(R->plan->cfg.precision) ? 8 : 4;
   int rc = WLC_OK;
   if (d && !rc) rc = hip_check(hipMemcpyAsync(d, R->d, n * 8, hipMemcpyDeviceToDevice, s), "copy d");
   if (r && !rc) rc = hip_check(hipMemcpyAsync(r, R->r, n * 8, hipMemcpyDeviceToDevice, s), "copy r");

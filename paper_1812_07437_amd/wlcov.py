@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libwlcov.so")
 
 WLC_OK, WLC_EINVAL, WLC_ERANGE, WLC_ENOMEM, WLC_ENOTPD, WLC_EDEVICE, WLC_EBUSY = 0, -1, -2, -3, -4, -5, -6
 WLC_TOMO_PAPER, WLC_TOMO_SORTED = 0, 1
-WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32 = 0, 1, 2, 3
+WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32, WLC_FP64_CHI = 0, 1, 2, 3, 4
 WLC_FLAG_NOCHECK = 1
-PRECISIONS = {"fp64": WLC_FP64, "bf16": WLC_BF16, "bf16x3": WLC_BF16X3, "fp32": WLC_FP32}
+PRECISIONS = {"fp64": WLC_FP64, "bf16": WLC_BF16, "bf16x3": WLC_BF16X3, "fp32": WLC_FP32,
+              "fp64_chi": WLC_FP64_CHI}
 
 
 class WlcError(RuntimeError):

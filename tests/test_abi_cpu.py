@@ -115,6 +115,18 @@ def test_invalid_config_rejected(bad):
     assert w.wlc_last_error()
 
 
+def test_precision_modes():
+    t = dict(synth.PRESETS["tiny"]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 1e11
+    for name, code in w.PRECISIONS.items():
+        plan = w.wlc_plan_create(w.make_config(t, name))
+        s = w.wlc_plan_sizes(plan)
+        assert s.c_elem_bytes == (8 if name in ("fp64", "fp64_chi") else 4)
+        w.wlc_plan_destroy(plan)
+    with pytest.raises(w.WlcError) as e:
+        w.wlc_plan_create(w.make_config(t, 5))
+    assert e.value.code == w.WLC_EINVAL
+
+
 def test_null_arguments_rejected():
     _, plan = _plan("tiny")
     tabs = w.wlc_tables()

@@ -77,7 +77,7 @@ def _check(prob, ref, tol_diag, tol_off):
     assert err_o < tol_off
 
 
-def test_large10_fp64_and_bf16x3(wl, ref):
+def test_large10_fp64_chi_and_bf16x3(wl, ref):
     t = ref["t"]
     _say("case large10 fp64")
     p64 = wl.Problem(t.cfg, t.arrays(), precision="fp64")
@@ -88,6 +88,18 @@ def test_large10_fp64_and_bf16x3(wl, ref):
     _check(p64, ref, 1e-10, 1e-10)
     p64.close()
     del p64
+    torch.cuda.empty_cache()
+
+    _say("case large10 fp64_chi")
+    pc = wl.Problem(t.cfg, t.arrays(), precision="fp64_chi")
+    pc.run()
+    snr_chi = pc.snr2()
+    torch.cuda.synchronize()
+    _check(pc, ref, 1e-10, 1e-10)
+    _say("  (S/N)^2 fp64_chi %.12e fp64 %.12e" % (snr_chi, snr64))
+    assert abs(snr_chi - snr64) / snr64 < 1e-9
+    pc.close()
+    del pc
     torch.cuda.empty_cache()
 
     _say("case large10 bf16x3")

@@ -49,11 +49,14 @@ def _rel(a, b):
     return np.max(np.abs(a - b) / np.abs(b))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp64_chi"])
 @pytest.mark.parametrize("preset,tomo", [("tiny", "paper"), ("tiny", "sorted"), ("mid", "paper")])
-def test_fp64_full_parity(wl, preset, tomo):
-    _say("case fp64 full %s %s" % (preset, tomo))
+def test_fp64_full_parity(wl, preset, tomo, precision):
+    """Both FP64 one-halo forms: the flattened Gram, and the sum over M
+    first and chi second (factorisation along the line of sight)."""
+    _say("case %s full %s %s" % (precision, preset, tomo))
     t, o, ref = _oracle_full(preset, tomo)
-    prob, snr2 = _run(wl, t, "fp64", tomo)
+    prob, snr2 = _run(wl, t, precision, tomo)
     d = prob.d.cpu().numpy(); r = prob.r.cpu().numpy()
     assert _rel(d, ref["d"]) < 1e-10
     assert _rel(r, o.data_vector()[1]) < 1e-10
@@ -75,13 +78,14 @@ def test_fp64_deterministic(wl):
     assert torch.equal(a.C, b.C) and torch.equal(a.d, b.d) and sa == sb
 
 
-def test_fp64_euclid5_sampled(wl):
+@pytest.mark.parametrize("precision", ["fp64", "fp64_chi"])
+def test_fp64_euclid5_sampled(wl, precision):
     """Full-size 5-bin workload (N = 4550, K = 32768): data vector and response
     entirely, covariance on seeded samples including the diagonal."""
-    _say("case fp64 euclid5 sampled")
+    _say("case %s euclid5 sampled" % precision)
     t = synth.make_tables("euclid5")
     o = oracle.Oracle(t)
-    prob, _ = _run(wl, t, "fp64", snr=False)
+    prob, _ = _run(wl, t, precision, snr=False)
     d_ref, r_ref = o.data_vector()
     assert _rel(prob.d.cpu().numpy(), d_ref) < 1e-10
     assert _rel(prob.r.cpu().numpy(), r_ref) < 1e-10
