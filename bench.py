@@ -82,11 +82,14 @@ def gram_flops(n_r, k_len, precision):
     return f * (3 if precision == "bf16x3" else 1)
 
 
-def timed_steps(prob, steps, warmup, torch, wl):
+def timed_steps(prob, steps, warmup, torch, wl, structured=False):
+    """Time whole steps (run + S/N); structured=True takes the S/N through
+    the distinct rows instead of the Cholesky of the whole covariance."""
     stream = torch.cuda.current_stream()
+    snr = prob.snr2_structured if structured else prob.snr2
     for _ in range(warmup):
         prob.run(stream)
-        prob.snr2(stream)
+        snr(stream)
     torch.cuda.synchronize()
     wl.wlc_plan_set_timing(prob.plan, True)
     phases = {p: 0.0 for p in wl.PHASES}
@@ -96,7 +99,7 @@ def timed_steps(prob, steps, warmup, torch, wl):
     t0 = time.perf_counter()
     for _ in range(steps):
         prob.run(stream)
-        s = prob.snr2(stream)
+        s = snr(stream)
         t_snr.append(s)
         ph = wl.wlc_plan_timings(prob.plan)
         for k, v in ph.items():
@@ -296,6 +299,14 @@ def main():
                    snr2_rel_vs=("fp64" if fp64 else args.precision), snr2_rel=abs(snrc[-1] - ref_snr) / ref_snr)
         log("fp64 chi: %.1f ms/step  one-halo %.2f ms  snr rel %.2e" % (chi["ms_per_step"], phc["gram"],
                                                                       chi["snr2_rel"]))
+        # the same step with the S/N through the distinct rows
+        pc.free_snr_workspace()
+        dts, phs, snrs_, _ = timed_steps(pc, args.chi_steps, 1, torch, wl, structured=True)
+        chi["structured"] = dict(ms_per_step=dts / args.chi_steps * 1e3, value=entries / (dts / args.chi_steps),
+                                 phases_ms=phs, snr2_rel=abs(snrs_[-1] - ref_snr) / ref_snr,
+                                 speedup_vs_headline_step=(dt / args.steps) / (dts / args.chi_steps))
+        log("fp64 chi + structured S/N: %.1f ms/step  phases %s  snr rel %.2e" % (
+            chi["structured"]["ms_per_step"], {k: round(v, 2) for k, v in phs.items()}, chi["structured"]["snr2_rel"]))
         del pc
         torch.cuda.empty_cache()
 

@@ -110,6 +110,8 @@ typedef struct {
   size_t c_elem_bytes; /* 8 (FP64) or 4 (mixed precisions)                    */
   size_t ws_run_bytes; /* device workspace needed by wlc_run                  */
   size_t ws_snr_bytes; /* device workspace needed by wlc_snr2                 */
+  size_t ws_snr_structured_bytes; /* ... by wlc_snr2_structured (0: not available
+                                     for this plan: SORTED tomography or n_z > 32) */
 } wlc_sizes;
 
 typedef struct wlc_plan_s *wlc_plan;
@@ -171,6 +173,24 @@ int wlc_run(wlc_plan plan, const wlc_tables *tables, void *ws, double *d, double
  * WLC_ENOTPD if a pivot is not positive. */
 int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
              double *snr2_host, void *stream);
+
+/* The same (S/N)^2 through the distinct rows, for PAPER tomography.
+ * With C = C_G + E M E^T (C_G the Gaussian term, block-diagonal over
+ * ell-configurations; E the map from data-vector rows to their distinct
+ * rows; M the one-halo plus super-sample term on distinct rows) and d = E d_R:
+ *   (S/N)^2 = u^T (I + L^T M L)^-1 u,  u = L^T d_R,  L L^T = E^T C_G^-1 E,
+ * where E^T C_G^-1 E is block-diagonal with closed-form blocks (symmetrised
+ * products of (P^s)^-1 per ell-bin).  The one large factorisation is an FP64
+ * Cholesky on n_distinct rows instead of n_data (eqs. SNprim, eq:SN2, with
+ * the Gaussian term of eq. CovPPG and App. B).
+ * ws_run: the DEVICE workspace of a completed wlc_run with this plan (its
+ *         Gram product, spectra, counts and row exponents are read; any
+ *         precision, the result carries the Gram's precision);
+ * ws:     DEVICE workspace of at least ws_snr_structured_bytes.
+ * Synchronises the stream.  WLC_EINVAL for SORTED tomography (there
+ * n_data = n_distinct and wlc_snr2 is the same computation) or n_z > 32;
+ * WLC_ENOTPD if a pivot is not positive. */
+int wlc_snr2_structured(wlc_plan plan, const void *ws_run, void *ws, double *snr2_host, void *stream);
 
 /* ---- phase timing (per-plan HIP events; not for plans shared by concurrent runs)
  * With timing enabled, wlc_run and wlc_snr2 record a HIP event pair on their

@@ -111,12 +111,82 @@ size_t snr_ws_bytes(const Plan &p) {
   return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(chol_scratch_bytes(n), 256) + 256 + 256;
 }
 
+size_t snr_structured_ws_bytes(const Plan &p) {
+  if (p.cfg.tomo_mode != WLC_TOMO_PAPER || p.cfg.n_z > WOOD_NZ_MAX) return 0;
+  const int64_t n = p.n_R, ldw = snr_ld(n), ldt = round_up(n, 8);
+  const int nz = p.cfg.n_z, sp = nz * (nz + 1) / 2, sb = nz * (nz + 1) * (nz + 2) / 6;
+  const size_t blocks = (size_t)p.n_ell * sp * sp + (size_t)p.n_tri * sb * sb;
+  return align_up((size_t)(n + 1) * ldw * 8, 256) + align_up((size_t)n * ldt * 8, 256) + align_up(blocks * 8, 256) +
+         align_up((size_t)p.n_ell * nz * nz * 8, 256) + align_up((size_t)n * 4, 256) + align_up((size_t)n * 8, 256) +
+         align_up(chol_scratch_bytes(n), 256) + 256 + 256;
+}
+
 static void finish_sizes(Plan &p) {
   p.k_len = (int64_t)p.cfg.n_chi * p.cfg.n_m;
   p.k_pad = round_up(p.k_len, K_ALIGN);
   p.r_pad = round_up(p.n_R, GRAM_TILE);
   p.ws_run = run_ws_bytes(p);
   p.ws_snr = snr_ws_bytes(p);
+}
+
+int snr_structured_enqueue(const Plan &p, const void *ws_run, void *ws, hipStream_t s, PhaseHooks *hooks,
+                           KernelProbe *probe, int32_t **flag_dev, double **out_dev) {
+  if (p.cfg.tomo_mode != WLC_TOMO_PAPER)
+    return fail(WLC_EINVAL, "the structured S/N needs PAPER tomography (with SORTED rows use wlc_snr2)");
+  if (p.cfg.n_z > WOOD_NZ_MAX) return fail(WLC_EINVAL, "the structured S/N supports at most 32 redshift bins");
+  const Layout L = run_layout(p);
+  const wlc_config &c = p.cfg;
+  const int64_t n = p.n_R, ldw = snr_ld(n), ldt = round_up(n, 8);
+  const int nz = c.n_z, sp = nz * (nz + 1) / 2, sb = nz * (nz + 1) * (nz + 2) / 6;
+  const size_t blocks = (size_t)p.n_ell * sp * sp + (size_t)p.n_tri * sb * sb;
+  char *base = static_cast<char *>(ws);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char *q = base + o;
+    o += align_up(bytes, 256);
+    return q;
+  };
+  WoodArgs w{};
+  w.W = reinterpret_cast<double *>(take((size_t)(n + 1) * ldw * 8));
+  w.ld_w = ldw;
+  w.T = reinterpret_cast<double *>(take((size_t)n * ldt * 8));
+  w.ld_t = ldt;
+  w.Gb = reinterpret_cast<double *>(take(blocks * 8));
+  w.Q = reinterpret_cast<double *>(take((size_t)p.n_ell * nz * nz * 8));
+  w.tau = reinterpret_cast<int32_t *>(take((size_t)n * 4));
+  w.rhat = reinterpret_cast<double *>(take((size_t)n * 8));
+  double *scratch = reinterpret_cast<double *>(take(chol_scratch_bytes(n)));
+  int32_t *flag = reinterpret_cast<int32_t *>(take(256));
+  double *out = reinterpret_cast<double *>(take(256));
+  w.B = BlockMap{p.n_ell, p.n_tri, sp, sb, n};
+  w.n_ell = p.n_ell;
+  w.nz = nz;
+  const void *wr = ws_run;
+  auto run_at = [&](Buf b) { return static_cast<const char *>(wr) + L.off[b]; };
+  w.Ps = reinterpret_cast<const double *>(run_at(B_PS));
+  w.nmodes = reinterpret_cast<const double *>(run_at(B_NMODES));
+  w.ntri = reinterpret_cast<const double *>(run_at(B_NTRI));
+  w.dR = reinterpret_cast<const double *>(run_at(B_DR));
+  w.rR = reinterpret_cast<const double *>(run_at(B_RR));
+  w.cfgT = reinterpret_cast<const int32_t *>(run_at(B_CFGT));
+  w.sexp = reinterpret_cast<const int32_t *>(run_at(B_SEXP));
+  w.Gm = run_at(B_GM);
+  w.gm_f32 = !prec_f64(c.precision);
+  w.ld_g = p.r_pad;
+  w.omega = p.omega;
+  w.sigma_b2 = c.sigma_b2;
+  w.flag = flag;
+  if (hooks) hooks->begin(WLC_PHASE_SNR_PREP);
+  launch_fill_i32(flag, 1, 0, s);
+  launch_woodbury(w, s);
+  if (hooks) hooks->end(WLC_PHASE_SNR_PREP);
+  if (hooks) hooks->begin(WLC_PHASE_CHOL);
+  chol_factor(w.W, n, ldw, scratch, flag, s, probe);
+  launch_sumsq_row(w.W, n, ldw, out, s);
+  if (hooks) hooks->end(WLC_PHASE_CHOL);
+  *flag_dev = flag;
+  *out_dev = out;
+  return hip_check(hipGetLastError(), "structured snr launch");
 }
 
 int hip_check(hipError_t e, const char *what) {
@@ -261,7 +331,12 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   a.gm_f32 = !prec_f64(c.precision);
   a.Ps = Ps;
   a.nmodes = at<double>(ws, L, B_NMODES);
-  a.ntri = tb.n_tri ? tb.n_tri : at<double>(ws, L, B_NTRI);
+  if (tb.n_tri && p.n_tri > 0) {  // the workspace keeps the counts this run used
+    rc = hip_check(hipMemcpyAsync(at<double>(ws, L, B_NTRI), tb.n_tri, (size_t)p.n_tri * 8, hipMemcpyDeviceToDevice,
+                                  s), "triangle counts");
+    if (rc) return rc;
+  }
+  a.ntri = at<double>(ws, L, B_NTRI);
   a.rR = rR;
   a.dR = dR;
   a.n_z = c.n_z;
@@ -404,6 +479,7 @@ int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out) {
   out->c_elem_bytes = prec_f64(p.cfg.precision) ? 8 : 4;
   out->ws_run_bytes = p.ws_run;
   out->ws_snr_bytes = p.ws_snr;
+  out->ws_snr_structured_bytes = snr_structured_ws_bytes(p);
   return WLC_OK;
 }
 
@@ -484,6 +560,37 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
   int32_t *flag = nullptr;
   double *out = nullptr;
   int rc = snr_enqueue(p, C, row_exp2, d, ws, s, timed ? &tm : nullptr, probe, &flag, &out);
+  if (rc) return rc;
+  struct { int32_t flag; int32_t pad; double v; } h{};
+  rc = hip_check(hipMemcpyAsync(&h.flag, flag, 4, hipMemcpyDeviceToHost, s), "snr copy");
+  if (!rc) rc = hip_check(hipMemcpyAsync(&h.v, out, 8, hipMemcpyDeviceToHost, s), "snr copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "snr sync");
+  if (rc) return rc;
+  if (h.flag) return fail(WLC_ENOTPD, "covariance is not positive definite");
+  *snr2_host = h.v;
+  return WLC_OK;
+}
+
+int wlc_snr2_structured(wlc_plan plan, const void *ws_run, void *ws, double *snr2_host, void *stream) {
+  if (!plan || !ws_run || !ws || !snr2_host) return fail(WLC_EINVAL, "null argument");
+  if (((uintptr_t)ws & 255) != 0 || ((uintptr_t)ws_run & 255) != 0)
+    return fail(WLC_EINVAL, "workspaces must be 256-byte aligned");
+  const Plan &p = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  plan->recorded[WLC_PHASE_SNR_PREP] = plan->recorded[WLC_PHASE_CHOL] = false;
+  PlanTimer tm(plan, s);
+  const bool timed = plan->timing && plan->events_ready;
+  KernelProbe *probe = nullptr;
+  if (timed) {
+    plan->probe = KernelProbe{};
+    plan->probe.ev = plan->upd_ev.data();
+    plan->probe.cap = (int)plan->upd_ev.size() / 2;
+    probe = &plan->probe;
+    plan->probe_valid = true;
+  }
+  int32_t *flag = nullptr;
+  double *out = nullptr;
+  int rc = snr_structured_enqueue(p, ws_run, ws, s, timed ? &tm : nullptr, probe, &flag, &out);
   if (rc) return rc;
   struct { int32_t flag; int32_t pad; double v; } h{};
   rc = hip_check(hipMemcpyAsync(&h.flag, flag, 4, hipMemcpyDeviceToHost, s), "snr copy");

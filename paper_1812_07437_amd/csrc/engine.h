@@ -35,6 +35,13 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
 int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const double *d, void *ws, hipStream_t s,
                 PhaseHooks *hooks, KernelProbe *probe, int32_t **flag_dev, double **out_dev);
 
+// The same (S/N)^2 through the distinct rows, from the run workspace of a
+// completed wlc_run (PAPER tomography only): the bordered Cholesky of
+// I + L^T M L on n_R rows.  Same completion protocol as snr_enqueue.
+size_t snr_structured_ws_bytes(const Plan &p);
+int snr_structured_enqueue(const Plan &p, const void *ws_run, void *ws, hipStream_t s, PhaseHooks *hooks,
+                           KernelProbe *probe, int32_t **flag_dev, double **out_dev);
+
 int hip_check(hipError_t e, const char *what);
 
 // Enumerate and size a plan.

@@ -88,6 +88,46 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
                     double *part, int64_t part_rows, hipStream_t s, KernelProbe *probe = nullptr);
 void launch_sumsq_row(const double *Wm, int64_t n, int64_t ld, double *out, hipStream_t s);
 
+// ---- S/N through the distinct rows (k_woodbury.hip)
+// Distinct rows are grouped by configuration: nl power-spectrum blocks of sp
+// rows, then n_tri bispectrum blocks of sb rows.
+struct BlockMap {
+  int nl, n_tri, sp, sb;
+  int64_t n_R;
+  __host__ __device__ int blk(int64_t e) const {
+    return e < (int64_t)nl * sp ? (int)(e / sp) : nl + (int)((e - (int64_t)nl * sp) / sb);
+  }
+  __host__ __device__ int64_t start(int c) const {
+    return c < nl ? (int64_t)c * sp : (int64_t)nl * sp + (int64_t)(c - nl) * sb;
+  }
+  __host__ __device__ int size(int c) const { return c < nl ? sp : sb; }
+  // offset of block c in a packed array of square blocks
+  __host__ __device__ int64_t off(int c) const {
+    return c < nl ? (int64_t)c * sp * sp : (int64_t)nl * sp * sp + (int64_t)(c - nl) * sb * sb;
+  }
+};
+struct WoodArgs {
+  BlockMap B;
+  int n_ell, nz;                  // ell-bins used, redshift bins (nz <= 32)
+  const double *Ps, *nmodes, *ntri, *dR, *rR;
+  const int32_t *cfgT, *sexp;
+  const void *Gm;                 // symmetric Gram of the run, pitch ld_g
+  int gm_f32;
+  int64_t ld_g;
+  double omega, sigma_b2;
+  double *Q;                      // [n_ell][nz][nz]
+  double *Gb;                     // packed blocks of G
+  double *rhat;                   // [n_R]
+  int32_t *tau;                   // [n_R]
+  double *T;                      // [n_R][ld_t]
+  int64_t ld_t;
+  double *W;                      // [n_R + 1][ld_w], bordered I + Z
+  int64_t ld_w;
+  int *flag;
+};
+constexpr int WOOD_NZ_MAX = 32;
+void launch_woodbury(const WoodArgs &w, hipStream_t s);
+
 // ---- lattice counts (k_lattice.hip); thr_max = largest threshold used
 void launch_lattice(const int64_t *thr_dev, int64_t thr_max, int n_ell, const int32_t *tri, int n_tri,
                     uint64_t *modes, uint64_t *tris, hipStream_t s);

@@ -47,7 +47,8 @@ class wlc_tables(ct.Structure):
 class wlc_sizes(ct.Structure):
     _fields_ = [("n_data", ct.c_int64), ("n_distinct", ct.c_int64), ("n_p", ct.c_int64), ("n_tri", ct.c_int64),
                 ("n_cfg", ct.c_int64), ("n_ell_used", ct.c_int64), ("k_len", ct.c_int64),
-                ("c_elem_bytes", ct.c_size_t), ("ws_run_bytes", ct.c_size_t), ("ws_snr_bytes", ct.c_size_t)]
+                ("c_elem_bytes", ct.c_size_t), ("ws_run_bytes", ct.c_size_t), ("ws_snr_bytes", ct.c_size_t),
+                ("ws_snr_structured_bytes", ct.c_size_t)]
 
 
 def _load():
@@ -65,6 +66,7 @@ def _load():
     L.wlc_lattice_counts.argtypes = [vp, vp, vp, vp, vp]
     L.wlc_run.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp, vp, vp, vp, vp]
     L.wlc_snr2.argtypes = [vp, vp, vp, vp, vp, ct.POINTER(ct.c_double), vp]
+    L.wlc_snr2_structured.argtypes = [vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
     L.wlc_plan_timings.argtypes = [vp, vp]
     L.wlc_plan_kernel_stats.argtypes = [vp, vp, vp, vp, vp]
@@ -74,7 +76,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_snr2", "wlc_plan_set_timing", "wlc_plan_timings",
+            "wlc_lattice_counts", "wlc_run", "wlc_snr2", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
 
@@ -139,6 +142,12 @@ def wlc_run(plan, tables: wlc_tables, ws, d, r, C, row_exp2, stream):
 def wlc_snr2(plan, C, row_exp2, d, ws, stream):
     out = ct.c_double()
     _check(lib.wlc_snr2(plan, C, row_exp2, d, ws, ct.byref(out), stream))
+    return out.value
+
+
+def wlc_snr2_structured(plan, ws_run, ws, stream):
+    out = ct.c_double()
+    _check(lib.wlc_snr2_structured(plan, ws_run, ws, ct.byref(out), stream))
     return out.value
 
 
@@ -218,8 +227,18 @@ class Problem:
         return wlc_snr2(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(self.ws_snr),
                         _stream_handle(stream))
 
+    def snr2_structured(self, stream=None):
+        """(S/N)^2 through the distinct rows, from this problem's last run."""
+        if getattr(self, "ws_struct", None) is None:
+            n = int(self.sizes.ws_snr_structured_bytes)
+            if n == 0:
+                raise WlcError(WLC_EINVAL, "structured S/N not available for this plan")
+            self.ws_struct = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        return wlc_snr2_structured(self.plan, _ptr(self.ws), _ptr(self.ws_struct), _stream_handle(stream))
+
     def free_snr_workspace(self):
         self.ws_snr = None
+        self.ws_struct = None
 
     def covariance_true(self):
         """C_true = C * 2^-(t_a + t_b) in float64 (host numpy)."""

@@ -98,6 +98,10 @@ def test_large10_fp64_chi_and_bf16x3(wl, ref):
     _check(pc, ref, 1e-10, 1e-10)
     _say("  (S/N)^2 fp64_chi %.12e fp64 %.12e" % (snr_chi, snr64))
     assert abs(snr_chi - snr64) / snr64 < 1e-9
+    snr_st = pc.snr2_structured()
+    _say("  (S/N)^2 structured (fp64_chi) %.12e" % snr_st)
+    assert abs(snr_st - snr64) / snr64 < 1e-9
+    pc.free_snr_workspace()
     pc.close()
     del pc
     torch.cuda.empty_cache()
@@ -110,6 +114,10 @@ def test_large10_fp64_chi_and_bf16x3(wl, ref):
     _check(pm, ref, 1e-5, 1e-5)
     _say("  (S/N)^2 bf16x3 %.9e fp64 %.9e" % (snr, snr64))
     assert abs(snr - snr64) / snr64 < 1e-4
+    pm.free_snr_workspace()
+    snr_st = pm.snr2_structured()
+    _say("  (S/N)^2 structured (bf16x3) %.9e" % snr_st)
+    assert abs(snr_st - snr64) / snr64 < 1e-4
     pm.close()
     del pm
     torch.cuda.empty_cache()

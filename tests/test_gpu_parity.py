@@ -192,3 +192,41 @@ def test_snr2_random_spd(wl, preset):
         prob.snr2()
     assert ex.value.code == wl.WLC_ENOTPD
     prob.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp64_chi", 1e-10), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("preset", ["tiny", "mid"])
+def test_snr2_structured(wl, preset, precision, tol):
+    """(S/N)^2 through the distinct rows equals the oracle's d^T C^-1 d and
+    the direct bordered Cholesky on the whole covariance."""
+    _say("case structured snr2 %s %s" % (preset, precision))
+    t, o, ref = _oracle_full(preset, "paper")
+    prob, direct = _run(wl, t, precision, "paper")
+    got = prob.snr2_structured()
+    torch.cuda.synchronize()
+    assert abs(got - ref["snr2"]) / ref["snr2"] < tol
+    assert abs(got - direct) / direct < (1e-10 if precision != "bf16x3" else 1e-6)
+    prob.close()
+
+
+def test_snr2_structured_sorted_rejected(wl):
+    _say("case structured snr2 sorted rejected")
+    t = synth.make_tables("tiny")
+    prob = wl.Problem(t.cfg, t.arrays(), precision="fp64", tomo="sorted")
+    assert prob.sizes.ws_snr_structured_bytes == 0
+    prob.run()
+    with pytest.raises(wl.WlcError) as e:
+        wl.wlc_snr2_structured(prob.plan, wl._ptr(prob.ws), wl._ptr(prob.ws), None)
+    assert e.value.code == wl.WLC_EINVAL
+    prob.close()
+
+
+def test_snr2_structured_euclid5(wl):
+    _say("case structured snr2 euclid5")
+    t = synth.make_tables("euclid5")
+    prob, direct = _run(wl, t, "fp64_chi")
+    got = prob.snr2_structured()
+    torch.cuda.synchronize()
+    _say("  structured %.15e direct %.15e" % (got, direct))
+    assert abs(got - direct) / direct < 1e-9
+    prob.close()
