@@ -352,17 +352,65 @@ class Oracle:
                              ct.c_int64(len(pairs)), _p(pairs), _p(out))
         return out
 
-    def cov_pairs(self, pairs, ntri=None):
+    def bfull(self):
+        """Projected bispectrum of every triangle for every ordering of bins
+        on its legs, [n_tri][n_z][n_z][n_z]: the data-vector value of the
+        multiset of bins (the Limber kernels are symmetric in the bins)."""
+        if getattr(self, "_bfull", None) is None:
+            d, _ = self.data_vector()
+            nz, nt = self.n_z, len(self.tris)
+            val = {}
+            for a in range(self.N):
+                if self.rows["kind"][a] == 3:
+                    val[(int(self.rows["tri"][a]), tuple(sorted(int(x) for x in self.rows["zbin"][a])))] = d[a]
+            B = np.zeros((max(nt, 1), nz, nz, nz))
+            for t in range(nt):
+                for i in range(nz):
+                    for j in range(nz):
+                        for k in range(nz):
+                            B[t, i, j, k] = val[(t, tuple(sorted((i, j, k))))]
+            self._bfull = np.ascontiguousarray(B)
+        return self._bfull
+
+    def trispec(self, legs, z):
+        """Projected one-halo trispectrum at four ell-bins and redshift bins."""
+        ell, U = self.u_table()
+        legs = np.ascontiguousarray(legs, np.int32)
+        z = np.ascontiguousarray(z, np.int32)
+        lib().or_trispec.restype = ct.c_double
+        return lib().or_trispec(ct.byref(self.T), _p(ell), _p(U), _p(legs), _p(z))
+
+    def ngins_pairs(self, pairs, rows=None):
+        """The B.B, P.T and P.B in-survey terms (eqs. CovBB, Covpb) for the
+        given (a, b) pairs of rows (default: the data-vector rows)."""
+        rows = self.rows if rows is None else rows
+        ell, U = self.u_table()
+        ps, nm, bf = self.ps_table(), self.nmodes(), self.bfull()
+        pairs = np.ascontiguousarray(pairs, np.int64)
+        out = np.zeros(len(pairs))
+        lib().or_ngins_pairs(ct.byref(self.T), _p(ell), _p(U), ct.c_int(self.n_z), _p(ps), _p(nm), _p(bf),
+                             _p(np.ascontiguousarray(rows["kind"], np.int32)),
+                             _p(np.ascontiguousarray(rows["lbin"], np.int32)),
+                             _p(np.ascontiguousarray(rows["zbin"], np.int32)),
+                             _p(np.ascontiguousarray(rows["tri"], np.int32)), ct.c_int64(len(pairs)),
+                             _p(pairs), _p(out))
+        return out
+
+    def cov_pairs(self, pairs, ntri=None, ngins=False):
         """Covariance entries C[a, b] for the given (a, b) pairs: Gaussian +
-        one-halo + rank-one super-sample term."""
+        one-halo + rank-one super-sample term (+ the B.B, P.T and P.B terms
+        when ngins is set)."""
         _, r = self.data_vector()
         pairs = np.ascontiguousarray(pairs, np.int64)
         ssc = float(self.cfg["sigma_b2"]) * r[pairs[:, 0]] * r[pairs[:, 1]]
-        return self.gauss_pairs(pairs, ntri) + self.cov1h_pairs(pairs) + ssc
+        out = self.gauss_pairs(pairs, ntri) + self.cov1h_pairs(pairs) + ssc
+        if ngins:
+            out = out + self.ngins_pairs(pairs)
+        return out
 
-    def covariance(self, ntri=None):
+    def covariance(self, ntri=None, ngins=False):
         """Full joint covariance C^D (eq. eq:SN2) on the lower triangle,
-        mirrored."""
+        mirrored (+ the B.B, P.T and P.B terms when ngins is set)."""
         canon, reps = canonical_rows(self.rows)
         nc = len(reps)
         ell, U = self.u_table()
@@ -383,6 +431,11 @@ class Oracle:
                           _p(ps), _p(nm), _p(nt), ct.c_double(self.omega), _p(self.rows["kind"]),
                           _p(lbf), _p(zbf), _p(self.rows["tri"]), _p(r),
                           ct.c_double(float(self.cfg["sigma_b2"])), _p(C))
+        if ngins:
+            ii, jj = np.tril_indices(self.N)
+            v = self.ngins_pairs(np.stack([ii, jj], 1))
+            C[ii, jj] += v
+            C[jj[ii != jj], ii[ii != jj]] += v[ii != jj]
         return C
 
     @staticmethod
@@ -398,9 +451,9 @@ class Oracle:
             raise MemoryError("oracle S/N allocation failed")
         return out.value
 
-    def run(self, ntri=None):
+    def run(self, ntri=None, ngins=False):
         d, r = self.data_vector()
-        C = self.covariance(ntri)
+        C = self.covariance(ntri, ngins)
         return dict(d=d, r=r, C=C, snr2=self.snr2(C, d))
 
     # ---- scalar pieces for pins

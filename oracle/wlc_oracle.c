@@ -392,6 +392,112 @@ void or_cov_full(int n, const double *c1h_canon, int nc, const int *canon,
 }
 
 /* One-halo values for all canonical row pairs (lower triangle), [nc][nc]. */
+/* --------------------------------------------------------------------
+ * Projected one-halo trispectrum at four legs: the Limber projection of
+ * eq. nProjection with n = 4 applied to I_4^0 of eq. ImunuHalos,
+ *   sum_n w_n chi_n^-6 prod_q W_{z_q}(chi_n)
+ *         sum_m w_m n_m (m/rho)^4 prod_q u(m, l_q / chi_n),
+ * zero at nodes where a leg exceeds k_max (U is zero there).  legs[q] are
+ * ell-bin indices, z[q] redshift bins. */
+static double trispec(const or_tables *T, const double *ell, const double *U, const double *mw,
+                      const int legs[4], const int z[4]) {
+  double lmax = 0.0;
+  for (int q = 0; q < 4; ++q) if (ell[legs[q]] > lmax) lmax = ell[legs[q]];
+  double total = 0.0;
+  for (int n = 0; n < T->n_chi; ++n) {
+    double chi = T->chi[n];
+    if (lmax / chi > T->k_max) continue;
+    double tw = T->w_chi[n] * pow(chi, -6.0);
+    for (int q = 0; q < 4; ++q) tw *= T->W[(size_t)z[q] * T->n_chi + n];
+    double sm = 0.0;
+    for (int mi = 0; mi < T->n_m; ++mi) {
+      double x = mw[(size_t)4 * T->n_m + mi];
+      for (int q = 0; q < 4; ++q) x *= U[((size_t)legs[q] * T->n_chi + n) * T->n_m + mi];
+      sm += x;
+    }
+    total += tw * sm;
+  }
+  return total;
+}
+
+double or_trispec(const or_tables *T, const double *ell, const double *U, const int *legs, const int *z) {
+  double *mw = mass_weights(T);
+  double v = trispec(T, ell, U, mw, legs, z);
+  free(mw);
+  return v;
+}
+
+/* --------------------------------------------------------------------
+ * The in-survey non-Gaussian terms of App. B built from lower-order
+ * spectra: B.B and P.T between two bispectrum rows (eq. CovBB), P.B between
+ * a power-spectrum and a bispectrum row (eq. Covpb).  Each term needs one leg
+ * of the first row to lie in the same ell-bin as one leg of the second
+ * (the Kronecker deltas), and carries 2 pi / (Omega l Delta l) = 1 / N(l)
+ * for that bin.  Summing over the three legs a of the first row and the
+ * three legs b of the second reproduces the printed bracket and its two
+ * permutations:
+ *   B.B: B[first row with bin z_a replaced by z'_b]
+ *        * B[second row with bin z'_b replaced by z_a]
+ *   P.T: P^s_{z_a z'_b}(l_a) * T(the two other legs of each row)
+ *   P.B: for a power-spectrum row (l; i, j) and bispectrum leg b in bin l:
+ *        P^s_{z'_b j}(l) B[z'_b replaced by i] + P^s_{i z'_b}(l) B[z'_b replaced by j].
+ * Bfull[(t * n_z + i) * n_z^2 + j * n_z + k] is the projected bispectrum of
+ * triangle t with bins (i, j, k) on its legs in order (the data vector
+ * value of that multiset of bins); T the projected one-halo trispectrum
+ * above.  Two power-spectrum rows get nothing here (their only term beyond
+ * the Gaussian one is the one-halo trispectrum, eq. CovPPNG). */
+static double ngins(const or_tables *T, const double *ell, const double *U, const double *mw, int n_z,
+                    const double *Ps, const double *nmodes, const double *Bfull,
+                    int ka, const int *la, const int *za, int ta, int kb, const int *lb, const int *zb, int tb) {
+#define PS(b, i, j) Ps[((size_t)(b) * n_z + (i)) * n_z + (j)]
+#define BF(t, z) Bfull[(((size_t)(t) * n_z + (z)[0]) * n_z + (z)[1]) * n_z + (z)[2]]
+  if (ka == 2 && kb == 2) return 0.0;
+  if (ka == 2 || kb == 2) {
+    const int *lp = ka == 2 ? la : lb, *zp = ka == 2 ? za : zb;
+    const int *lt = ka == 2 ? lb : la, *zt = ka == 2 ? zb : za;
+    int tt = ka == 2 ? tb : ta;
+    double s = 0.0;
+    for (int b = 0; b < 3; ++b) {
+      if (lt[b] != lp[0]) continue;
+      int zi[3] = {zt[0], zt[1], zt[2]}, zj[3] = {zt[0], zt[1], zt[2]};
+      zi[b] = zp[0];
+      zj[b] = zp[1];
+      s += (PS(lp[0], zt[b], zp[1]) * BF(tt, zi) + PS(lp[0], zp[0], zt[b]) * BF(tt, zj)) / nmodes[lp[0]];
+    }
+    return s;
+  }
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      if (la[a] != lb[b]) continue;
+      int z1[3] = {za[0], za[1], za[2]}, z2[3] = {zb[0], zb[1], zb[2]};
+      z1[a] = zb[b];
+      z2[b] = za[a];
+      const double bb = BF(ta, z1) * BF(tb, z2);
+      int legs[4], zz[4], q = 0;
+      for (int x = 0; x < 3; ++x) if (x != a) { legs[q] = la[x]; zz[q] = za[x]; ++q; }
+      for (int x = 0; x < 3; ++x) if (x != b) { legs[q] = lb[x]; zz[q] = zb[x]; ++q; }
+      const double pt = PS(la[a], za[a], zb[b]) * trispec(T, ell, U, mw, legs, zz);
+      s += (bb + pt) / nmodes[la[a]];
+    }
+  return s;
+#undef BF
+#undef PS
+}
+
+void or_ngins_pairs(const or_tables *T, const double *ell, const double *U, int n_z, const double *Ps,
+                    const double *nmodes, const double *Bfull, const int *kind, const int *lbin, const int *zbin,
+                    const int *tri, int64_t n_pairs, const int64_t *pairs, double *out) {
+  double *mw = mass_weights(T);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t q = 0; q < n_pairs; ++q) {
+    int64_t a = pairs[2 * q], b = pairs[2 * q + 1];
+    out[q] = ngins(T, ell, U, mw, n_z, Ps, nmodes, Bfull, kind[a], &lbin[3 * a], &zbin[3 * a], tri[a], kind[b],
+                   &lbin[3 * b], &zbin[3 * b], tri[b]);
+  }
+  free(mw);
+}
+
 void or_cov1h_canon(const or_tables *T, const double *ell, const double *U, double omega, int nc,
                     const int *kind, const int *lbin, const int *zbin, double *out) {
   double *mw = mass_weights(T);
