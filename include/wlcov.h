@@ -59,7 +59,13 @@ enum { WLC_FP64 = 0, WLC_BF16 = 1, WLC_BF16X3 = 2, WLC_FP32 = 3, WLC_FP64_CHI = 
 
 /* ---- flags */
 enum {
-  WLC_FLAG_NOCHECK = 1 /* skip the table validation pass (and its one stream sync) */
+  WLC_FLAG_NOCHECK = 1, /* skip the table validation pass (and its one stream sync) */
+  WLC_FLAG_NGINS = 2    /* add the in-survey terms built from lower-order spectra:
+                           B.B and P.T between bispectra (eq. CovBB), P.B between
+                           power spectrum and bispectrum (eq. Covpb); the P.T term
+                           uses the projected one-halo trispectrum of the two other
+                           legs of each triangle.  Not combinable with
+                           wlc_snr2_structured. */
 };
 
 typedef struct {
@@ -188,7 +194,8 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
  *         precision, the result carries the Gram's precision);
  * ws:     DEVICE workspace of at least ws_snr_structured_bytes.
  * Synchronises the stream.  WLC_EINVAL for SORTED tomography (there
- * n_data = n_distinct and wlc_snr2 is the same computation) or n_z > 32;
+ * n_data = n_distinct and wlc_snr2 is the same computation), n_z > 32, or
+ * WLC_FLAG_NGINS (its terms are not of the form E M E^T);
  * WLC_ENOTPD if a pivot is not positive. */
 int wlc_snr2_structured(wlc_plan plan, const void *ws_run, void *ws, double *snr2_host, void *stream);
 

@@ -52,8 +52,16 @@ constexpr int64_t K_ALIGN = 64;
 enum Buf {
   B_ROWR, B_ROWO, B_CFGT, B_CENT, B_NMODES, B_NTRI, B_THR, B_TRI, B_FLAGS,
   B_U, B_PK, B_NE, B_X, B_R, B_DR, B_RR, B_PS, B_G, B_GMAX, B_TS, B_SEXP,
-  B_A0, B_A1, B_GM, B_PART, B_H, NBUF
+  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, NBUF
 };
+
+// two-leg trispectrum (B.B / P.T / P.B terms): configurations and rows
+static int twoleg_configs(const Plan &p) { return p.n_ell + p.n_ell * (p.n_ell - 1) / 2; }
+static int64_t twoleg_rows(const Plan &p) {
+  const int nz = p.cfg.n_z;
+  return (int64_t)p.n_ell * (nz * (nz + 1) / 2) + (int64_t)(twoleg_configs(p) - p.n_ell) * nz * nz;
+}
+static int64_t twoleg_ld(const Plan &p) { return round_up(twoleg_rows(p), 64); }
 
 struct Layout {
   size_t off[NBUF];
@@ -92,6 +100,13 @@ static Layout run_layout(const Plan &p) {
   GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
   sz[B_PART] = chi ? 0 : gram_partial_bytes(c.precision, g);
   sz[B_H] = chi ? (size_t)n_cfg * n_cfg * c.n_chi * 8 : 0;
+  if (c.flags & WLC_FLAG_NGINS) {
+    const int n2 = twoleg_configs(p);
+    sz[B_G2] = (size_t)n2 * c.n_chi * c.n_m * 8;
+    sz[B_H2] = (size_t)n2 * n2 * c.n_chi * 8;
+    sz[B_TS2] = (size_t)twoleg_rows(p) * c.n_chi * 8;
+    sz[B_T2] = (size_t)twoleg_rows(p) * twoleg_ld(p) * 8;
+  }
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < NBUF; ++b) {
@@ -112,7 +127,7 @@ size_t snr_ws_bytes(const Plan &p) {
 }
 
 size_t snr_structured_ws_bytes(const Plan &p) {
-  if (p.cfg.tomo_mode != WLC_TOMO_PAPER || p.cfg.n_z > WOOD_NZ_MAX) return 0;
+  if (p.cfg.tomo_mode != WLC_TOMO_PAPER || p.cfg.n_z > WOOD_NZ_MAX || (p.cfg.flags & WLC_FLAG_NGINS)) return 0;
   const int64_t n = p.n_R, ldw = snr_ld(n), ldt = round_up(n, 8);
   const int nz = p.cfg.n_z, sp = nz * (nz + 1) / 2, sb = nz * (nz + 1) * (nz + 2) / 6;
   const size_t blocks = (size_t)p.n_ell * sp * sp + (size_t)p.n_tri * sb * sb;
@@ -134,6 +149,8 @@ int snr_structured_enqueue(const Plan &p, const void *ws_run, void *ws, hipStrea
   if (p.cfg.tomo_mode != WLC_TOMO_PAPER)
     return fail(WLC_EINVAL, "the structured S/N needs PAPER tomography (with SORTED rows use wlc_snr2)");
   if (p.cfg.n_z > WOOD_NZ_MAX) return fail(WLC_EINVAL, "the structured S/N supports at most 32 redshift bins");
+  if (p.cfg.flags & WLC_FLAG_NGINS)
+    return fail(WLC_EINVAL, "the structured S/N does not cover the B.B, P.T and P.B terms (WLC_FLAG_NGINS)");
   const Layout L = run_layout(p);
   const wlc_config &c = p.cfg;
   const int64_t n = p.n_R, ldw = snr_ld(n), ldt = round_up(n, 8);
@@ -298,6 +315,15 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   launch_ps(dR, Ps, p.n_ell, c.n_z, p.noise, s);
   launch_gfactor(T, cfgT, n_cfg, U, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
+  if (c.flags & WLC_FLAG_NGINS) {
+    // the projected one-halo trispectrum of two legs per triangle (the P.T
+    // term), in FP64 through the factorisation along chi
+    const int nz = c.n_z;
+    double *Ts2 = at<double>(ws, L, B_TS2), *G2 = at<double>(ws, L, B_G2);
+    launch_twoleg(T, p.n_ell, U, G2, Ts2, s);
+    launch_chifact(Ts2, G2, at<double>(ws, L, B_H2), twoleg_configs(p), c.n_chi, c.n_m, p.n_ell,
+                   nz * (nz + 1) / 2, nz * nz, twoleg_configs(p) - p.n_ell, at<double>(ws, L, B_T2), twoleg_ld(p), s);
+  }
   if (hooks) hooks->end(WLC_PHASE_TABLES);
 
   void *Gm = at<void>(ws, L, B_GM);
@@ -345,6 +371,9 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   a.omega = p.omega;
   a.inv_omega = 1.0 / p.omega;
   a.sigma_b2 = c.sigma_b2;
+  a.ngins = (c.flags & WLC_FLAG_NGINS) != 0;
+  a.T2 = a.ngins ? at<double>(ws, L, B_T2) : nullptr;
+  a.ld_t2 = a.ngins ? twoleg_ld(p) : 0;
   if (hooks) hooks->begin(WLC_PHASE_ASSEMBLE);
   launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
   launch_rowexp(a, row_exp2, d, r, s);

@@ -42,6 +42,81 @@ __device__ __forceinline__ double gauss_entry(const AsmArgs &A, const int32_t *r
   return A.omega / A.ntri[ra[0] - A.n_ell] * s;
 }
 
+// ---- in-survey terms beyond the one-halo functions (eqs. CovBB, Covpb)
+// Index of the distinct row of a bin multiset: pairs i <= j and triples
+// i <= j <= k are ranked in the plan's order (first index slowest).
+__device__ __forceinline__ int pair_rank(int i, int j, int nz) {
+  if (i > j) { const int t = i; i = j; j = t; }
+  return i * nz - i * (i - 1) / 2 + (j - i);
+}
+
+__device__ __forceinline__ int trip_rank(int a, int b, int c, int nz) {
+  // sort three values
+  if (a > b) { const int t = a; a = b; b = t; }
+  if (b > c) { const int t = b; b = c; c = t; }
+  if (a > b) { const int t = a; a = b; b = t; }
+  int r = 0;
+  for (int x = 0; x < a; ++x) r += (nz - x) * (nz - x + 1) / 2;
+  for (int y = a; y < b; ++y) r += nz - y;
+  return r + (c - b);
+}
+
+// Row of the two-leg trispectrum for legs p <= q (ell-bins) carrying bins
+// (j on p, k on q).
+__device__ __forceinline__ int64_t twoleg_row(int p, int q, int j, int k, int nl, int nz) {
+  const int sp = nz * (nz + 1) / 2;
+  if (p == q) return (int64_t)p * sp + pair_rank(j, k, nz);
+  const int r = p * (nl - 1) - p * (p - 1) / 2 + (q - p - 1);
+  return (int64_t)nl * sp + (int64_t)r * nz * nz + j * nz + k;
+}
+
+__device__ __forceinline__ double ngins_entry(const AsmArgs &A, const int32_t *ra, const int32_t *rb) {
+  const int nz = A.n_z, nl = A.n_ell;
+  const int kind_a = A.cfgT[4 * ra[0]], kind_b = A.cfgT[4 * rb[0]];
+  if (kind_a == 2 && kind_b == 2) return 0.0;
+  const int sp = nz * (nz + 1) / 2, st = nz * (nz + 1) * (nz + 2) / 6;
+  const int64_t np = (int64_t)nl * sp;  // first distinct bispectrum row
+  const double *Ps = A.Ps;
+  auto ps = [&](int b, int i, int j) { return Ps[((size_t)b * nz + i) * nz + j]; };
+  auto bval = [&](int cfg, int z0, int z1, int z2) {
+    return A.dR[np + (int64_t)(cfg - nl) * st + trip_rank(z0, z1, z2, nz)];
+  };
+  if (kind_a == 2 || kind_b == 2) {
+    const int32_t *rp = kind_a == 2 ? ra : rb, *rt = kind_a == 2 ? rb : ra;
+    const int l = rp[5], i = rp[2], j = rp[3];
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (rt[5 + b] != l) continue;
+      int zi[3] = {rt[2], rt[3], rt[4]}, zj[3] = {rt[2], rt[3], rt[4]};
+      zi[b] = i;
+      zj[b] = j;
+      s += (ps(l, rt[2 + b], j) * bval(rt[0], zi[0], zi[1], zi[2]) +
+            ps(l, i, rt[2 + b]) * bval(rt[0], zj[0], zj[1], zj[2])) / A.nmodes[l];
+    }
+    return s;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int l = ra[5 + a];
+      if (l != rb[5 + b]) continue;
+      int z1[3] = {ra[2], ra[3], ra[4]}, z2[3] = {rb[2], rb[3], rb[4]};
+      z1[a] = rb[2 + b];
+      z2[b] = ra[2 + a];
+      const double bb = bval(ra[0], z1[0], z1[1], z1[2]) * bval(rb[0], z2[0], z2[1], z2[2]);
+      // the two other legs of each row, in leg order (ell-bins non-decreasing)
+      const int ax = a == 0 ? 1 : 0, ay = a == 2 ? 1 : 2, bx = b == 0 ? 1 : 0, by = b == 2 ? 1 : 2;
+      const int64_t ta = twoleg_row(ra[5 + ax], ra[5 + ay], ra[2 + ax], ra[2 + ay], nl, nz);
+      const int64_t tb = twoleg_row(rb[5 + bx], rb[5 + by], rb[2 + bx], rb[2 + by], nl, nz);
+      const double t4 = ta >= tb ? A.T2[ta * A.ld_t2 + tb] : A.T2[tb * A.ld_t2 + ta];
+      s += (bb + ps(l, ra[2 + a], rb[2 + b]) * t4) / A.nmodes[l];
+    }
+  return s;
+}
+
 // G has been mirrored to exact symmetry, so it is read along rows: for the
 // 64 consecutive data rows b of a wavefront the distinct rows e(b) are
 // clustered, and the reads touch few cache lines.
@@ -57,7 +132,8 @@ __global__ void k_rowexp(AsmArgs A, int32_t *row_exp2, double *d, double *r) {
   const int64_t e = ra[1];
   const double g = gram_at(A, e, e);
   const double rr = A.rR[e];
-  const double c = ldexp(g, -2 * A.sexp[e]) * A.inv_omega + gauss_entry(A, ra, ra) + A.sigma_b2 * rr * rr;
+  double c = ldexp(g, -2 * A.sexp[e]) * A.inv_omega + gauss_entry(A, ra, ra) + A.sigma_b2 * rr * rr;
+  if (A.ngins) c += ngins_entry(A, ra, ra);
   int t = 0;
   if (c > 0.0 && isfinite(c)) {
     const int E = exp2_of(c);
@@ -123,7 +199,8 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__re
     if (live) {
       const int tt = tA[ra] + tB[cb];
       const double g = gram_at(A, rowA[ra][1], rowB[cb][1]);
-      const double rest = A.sigma_b2 * rA[ra] * rB[cb] + gauss_entry(A, rowA[ra], rowB[cb]);
+      double rest = A.sigma_b2 * rA[ra] * rB[cb] + gauss_entry(A, rowA[ra], rowB[cb]);
+      if (A.ngins) rest += ngins_entry(A, rowA[ra], rowB[cb]);
       v = ldexp(g * A.inv_omega, tt - sA[ra] - sB[cb]) + ldexp(rest, tt);
       C[a * A.n + b] = (OutT)v;
     }

@@ -340,6 +340,71 @@ void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT
   hipLaunchKernelGGL(k_tfactor, dim3((int)((n_R + 3) / 4)), dim3(256), 0, s, T, rowR, cfgT, n_R, Gmax, Ts, sexp);
 }
 
+// ------------------------------------------------------------- two-leg factors
+// The projected one-halo trispectrum that enters the P.T term of eq. CovBB
+// at the two remaining legs of each of two triangles factorises like the
+// one-halo covariance: for a two-leg configuration (ell-bins p <= q) and
+// bins (j at p, k at q),
+//   T[(pq, jk)][(p'q', j'k')] = sum_n Ts2[(pq, jk)][n] Ts2[(p'q', j'k')][n]
+//                               * sum_m G2[pq][n][m] G2[p'q'][n][m],
+//   Ts2 = sqrt(w_n) chi_n^-3 W_j(chi_n) W_k(chi_n),
+//   G2  = sqrt(w_m n_m) (m/rho)^2 u(m, l_p/chi_n) u(m, l_q/chi_n)
+// (eq. nProjection with n = 4, I_4^0 of eq. ImunuHalos).  Configurations:
+// p = q first (index p), then p < q in lexicographic order; rows: pairs
+// j <= k for p = q, all n_z^2 ordered pairs (j, k) for p < q.
+__global__ void k_g2factor(DevTables T, int n_ell, const double *U, double *G2) {
+  const int n2 = n_ell + n_ell * (n_ell - 1) / 2;
+  const int64_t total = (int64_t)n2 * T.n_chi * T.n_m_pts;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int mi = (int)(i % T.n_m_pts);
+    const int64_t cn = i / T.n_m_pts;
+    const int n = (int)(cn % T.n_chi), c = (int)(cn / T.n_chi);
+    int p, q;
+    if (c < n_ell) {
+      p = q = c;
+    } else {
+      int r = c - n_ell;
+      for (p = 0; r >= n_ell - 1 - p; ++p) r -= n_ell - 1 - p;
+      q = p + 1 + r;
+    }
+    const double x = T.m[mi] / T.rho;
+    G2[i] = sqrt(T.w_m[mi] * T.n_m[mi]) * x * x * U[((size_t)p * T.n_chi + n) * T.n_m_pts + mi] *
+            U[((size_t)q * T.n_chi + n) * T.n_m_pts + mi];
+  }
+}
+
+__global__ void k_t2factor(DevTables T, int n_ell, int64_t rows, double *Ts2) {
+  const int nz = T.n_z, sp = nz * (nz + 1) / 2;
+  const int64_t total = rows * T.n_chi;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(i % T.n_chi);
+    const int64_t row = i / T.n_chi;
+    int j, k;
+    if (row < (int64_t)n_ell * sp) {
+      int w = (int)(row % sp);
+      for (j = 0; w >= nz - j; ++j) w -= nz - j;
+      k = j + w;
+    } else {
+      const int w = (int)((row - (int64_t)n_ell * sp) % (nz * nz));
+      j = w / nz;
+      k = w % nz;
+    }
+    const double chi = T.chi[n];
+    Ts2[i] = sqrt(T.w_chi[n]) / (chi * chi * chi) * T.W[(size_t)j * T.n_chi + n] * T.W[(size_t)k * T.n_chi + n];
+  }
+}
+
+void launch_twoleg(const DevTables &T, int n_ell, const double *U, double *G2, double *Ts2, hipStream_t s) {
+  const int n2 = n_ell + n_ell * (n_ell - 1) / 2;
+  const int nz = T.n_z;
+  const int64_t rows = (int64_t)n_ell * (nz * (nz + 1) / 2) + (int64_t)(n2 - n_ell) * nz * nz;
+  const int64_t tg = (int64_t)n2 * T.n_chi * T.n_m_pts, tt = rows * T.n_chi;
+  hipLaunchKernelGGL(k_g2factor, dim3((unsigned)std::min<int64_t>((tg + 255) / 256, 65536)), dim3(256), 0, s, T,
+                     n_ell, U, G2);
+  hipLaunchKernelGGL(k_t2factor, dim3((unsigned)std::min<int64_t>((tt + 255) / 256, 65536)), dim3(256), 0, s, T,
+                     n_ell, rows, Ts2);
+}
+
 // ------------------------------------------------------------- A build
 // A[row][k], k = n * n_m + m, row-major [r_pad][lda]; rows >= n_R and
 // k >= n_chi * n_m are zero.  A row of A is T_row(chi_n) G_cfg(chi_n, M_m),

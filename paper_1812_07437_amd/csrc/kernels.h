@@ -26,6 +26,11 @@ void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
                    int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s);
 
+// Two-leg factors of the projected one-halo trispectrum (P.T term): G2
+// [n2][n_chi][n_m] and Ts2 [rows][n_chi] for the n2 = n_ell (n_ell + 1) / 2
+// ell-bin pairs p <= q (p = q first) and their bin rows.
+void launch_twoleg(const DevTables &T, int n_ell, const double *U, double *G2, double *Ts2, hipStream_t s);
+
 // ---- Gram product (k_gram.hip): lower-triangle tiles of A A^T
 struct GramShape {
   int64_t r_pad;   // padded rows (multiple of the tile)
@@ -62,6 +67,10 @@ struct AsmArgs {
   int n_z, n_ell;
   int64_t n;              // output rows
   double inv_omega, omega, sigma_b2;
+  // B.B, P.T and P.B in-survey terms (eqs. CovBB, Covpb), when ngins != 0:
+  int ngins;
+  const double *T2;       // two-leg trispectrum, lower triangle, pitch ld_t2
+  int64_t ld_t2;
 };
 void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hipStream_t s);
 void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libwlcov.so")
 WLC_OK, WLC_EINVAL, WLC_ERANGE, WLC_ENOMEM, WLC_ENOTPD, WLC_EDEVICE, WLC_EBUSY = 0, -1, -2, -3, -4, -5, -6
 WLC_TOMO_PAPER, WLC_TOMO_SORTED = 0, 1
 WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32, WLC_FP64_CHI = 0, 1, 2, 3, 4
-WLC_FLAG_NOCHECK = 1
+WLC_FLAG_NOCHECK, WLC_FLAG_NGINS = 1, 2
 PRECISIONS = {"fp64": WLC_FP64, "bf16": WLC_BF16, "bf16x3": WLC_BF16X3, "fp32": WLC_FP32,
               "fp64_chi": WLC_FP64_CHI}
 
@@ -152,14 +152,14 @@ def wlc_snr2_structured(plan, ws_run, ws, stream):
 
 
 # ---------------------------------------------------------------- helpers
-def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False) -> wlc_config:
+def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False, ngins=False) -> wlc_config:
     """wlc_config from a dict of scalars (n_z, n_ell, n_chi, n_k, n_m, ell_min,
     ell_max, f_sky, sigma_eps, n_gal_arcmin2, sigma_b2, k_max, rho_mean and
-    optionally ell_cut)."""
+    optionally ell_cut); ngins adds the B.B, P.T and P.B terms."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return wlc_config(n_z=int(cfg["n_z"]), n_ell=int(cfg["n_ell"]), n_chi=int(cfg["n_chi"]), n_k=int(cfg["n_k"]),
                       n_m=int(cfg["n_m"]), tomo_mode=WLC_TOMO_SORTED if tomo == "sorted" else WLC_TOMO_PAPER,
-                      precision=prec, flags=WLC_FLAG_NOCHECK if nocheck else 0,
+                      precision=prec, flags=(WLC_FLAG_NOCHECK if nocheck else 0) | (WLC_FLAG_NGINS if ngins else 0),
                       ell_min=float(cfg["ell_min"]), ell_max=float(cfg["ell_max"]),
                       ell_cut=float(cfg.get("ell_cut", 0.0) or 0.0), f_sky=float(cfg["f_sky"]),
                       sigma_eps=float(cfg["sigma_eps"]), n_gal_arcmin2=float(cfg["n_gal_arcmin2"]),
@@ -181,11 +181,11 @@ class Problem:
     u, n_m, optional b1, b2, n_tri) to float64 arrays (numpy or torch)."""
 
     def __init__(self, cfg: dict, arrays: dict, precision="fp64", tomo="paper", device="cuda:0",
-                 nocheck=False):
+                 nocheck=False, ngins=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.config = make_config(cfg, precision, tomo, nocheck)
+        self.config = make_config(cfg, precision, tomo, nocheck, ngins)
         self.plan = wlc_plan_create(self.config)
         self.sizes = wlc_plan_sizes(self.plan)
         self._tabs = {}

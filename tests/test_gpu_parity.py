@@ -28,17 +28,17 @@ def wl():
 _ORACLE = {}
 
 
-def _oracle_full(preset, tomo="paper", **kw):
-    key = (preset, tomo, tuple(sorted(kw.items())))
+def _oracle_full(preset, tomo="paper", ngins=False, **kw):
+    key = (preset, tomo, ngins, tuple(sorted(kw.items())))
     if key not in _ORACLE:
         t = synth.make_tables(preset, **kw)
         o = oracle.Oracle(t, tomo=tomo)
-        _ORACLE[key] = (t, o, o.run())
+        _ORACLE[key] = (t, o, o.run(ngins=ngins))
     return _ORACLE[key]
 
 
-def _run(wl, t, precision="fp64", tomo="paper", snr=True):
-    prob = wl.Problem(t.cfg, t.arrays(), precision=precision, tomo=tomo)
+def _run(wl, t, precision="fp64", tomo="paper", snr=True, ngins=False):
+    prob = wl.Problem(t.cfg, t.arrays(), precision=precision, tomo=tomo, ngins=ngins)
     prob.run()
     s = prob.snr2() if snr else None
     torch.cuda.synchronize()
@@ -229,4 +229,24 @@ def test_snr2_structured_euclid5(wl):
     torch.cuda.synchronize()
     _say("  structured %.15e direct %.15e" % (got, direct))
     assert abs(got - direct) / direct < 1e-9
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_chi"])
+@pytest.mark.parametrize("preset,tomo", [("tiny", "paper"), ("tiny", "sorted"), ("mid", "paper")])
+def test_ngins_full_parity(wl, preset, tomo, precision):
+    """With the B.B, P.T and P.B terms (eqs. CovBB, Covpb): the whole
+    covariance and the S/N against the oracle."""
+    _say("case ngins %s %s %s" % (precision, preset, tomo))
+    t, o, ref = _oracle_full(preset, tomo, ngins=True)
+    prob, snr2 = _run(wl, t, precision, tomo, ngins=True)
+    C = prob.covariance_true()
+    assert _rel(C, ref["C"]) < 1e-10
+    Cs = prob.C.cpu().numpy()
+    assert np.array_equal(Cs, Cs.T)
+    dg = np.diag(Cs)
+    assert np.all((dg >= 1.0) & (dg < 4.0))
+    assert abs(snr2 - ref["snr2"]) / ref["snr2"] < 1e-10
+    with pytest.raises(wl.WlcError):
+        prob.snr2_structured()
     prob.close()
