@@ -310,6 +310,29 @@ def main():
         del pc
         torch.cuda.empty_cache()
 
+    # the same FP64 step with the B.B, P.T and P.B in-survey terms added
+    ngins = None
+    if args.chi_steps > 0:
+        log("fp64 chi path with the B.B, P.T, P.B terms")
+        pn = wl.Problem(cfg, t.arrays(), precision="fp64_chi", device="cuda:0", ngins=True)
+        try:
+            dtn, phn, snrn, _ = timed_steps(pn, args.chi_steps, 1, torch, wl)
+            ngins = dict(ms_per_step=dtn / args.chi_steps * 1e3, phases_ms=phn, snr2=snrn[-1],
+                         snr2_without=(fp64["snr2"] if fp64 else snr_mixed))
+            log("fp64 chi + in-survey terms: %.1f ms/step  phases %s  (S/N)^2 %.6e (without: %.6e)" % (
+                ngins["ms_per_step"], {k: round(v, 2) for k, v in phn.items()}, snrn[-1], ngins["snr2_without"]))
+        except wl.WlcError as e:
+            # the printed B.B / P.B terms need not keep the covariance positive
+            # definite; report the run time and the failure
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pn.run(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            ngins = dict(run_ms=(time.perf_counter() - t0) * 1e3, snr2=None, error=str(e))
+            log("fp64 chi + in-survey terms: run %.1f ms; S/N: %s" % (ngins["run_ms"], e))
+        del pn
+        torch.cuda.empty_cache()
+
     # roofline of the dominant kernel of the step: the one-halo Gram (one
     # launch per step) or the Cholesky block update (many launches per step,
     # timed one by one with HIP events on the run's stream)
@@ -371,6 +394,7 @@ def main():
         "snr": math.sqrt(snr_mixed) if snr_mixed > 0 else None,
         "fp64_path": fp64,
         "fp64_chi_path": chi,
+        "fp64_chi_ngins_path": ngins,
         "serving": srv,
     }
     print(json.dumps(out), flush=True)

@@ -121,3 +121,27 @@ def test_large10_fp64_chi_and_bf16x3(wl, ref):
     pm.close()
     del pm
     torch.cuda.empty_cache()
+
+
+def test_large10_ngins_sampled(wl, ref):
+    """The B.B, P.T and P.B terms at full size: sampled entries against the
+    oracle (FP64, one-halo term factorised along chi)."""
+    t = ref["t"]
+    o = oracle.Oracle(t)
+    pairs = np.concatenate([ref["off"][:200], np.stack([ref["rows"][:200]] * 2, 1)])
+    _say("oracle with B.B, P.T, P.B terms: %d entries" % len(pairs))
+    want = o.cov_pairs(pairs, ngins=True)
+    _say("case large10 fp64_chi with the in-survey terms")
+    pc = wl.Problem(t.cfg, t.arrays(), precision="fp64_chi", ngins=True)
+    pc.run()
+    torch.cuda.synchronize()
+    got, sym = _entries(pc, pairs)
+    assert sym
+    scale = np.sqrt(np.abs(o.cov_pairs(np.stack([pairs[:, 0], pairs[:, 0]], 1), ngins=True) *
+                           o.cov_pairs(np.stack([pairs[:, 1], pairs[:, 1]], 1), ngins=True)))
+    err = np.max(np.abs(got - want) / scale)
+    _say("  max rel to sqrt(C_aa C_bb) %.3e" % err)
+    assert err < 1e-10
+    pc.close()
+    del pc
+    torch.cuda.empty_cache()
