@@ -396,21 +396,55 @@ class Oracle:
                              _p(pairs), _p(out))
         return out
 
-    def cov_pairs(self, pairs, ntri=None, ngins=False):
-        """Covariance entries C[a, b] for the given (a, b) pairs: Gaussian +
-        one-halo + rank-one super-sample term (+ the B.B, P.T and P.B terms
-        when ngins is set)."""
-        _, r = self.data_vector()
+    # ---- super-sample term resolved along the line of sight
+    SIGMA_W_NODES = 16384
+
+    def theta_sky(self):
+        """Radius of the survey disk: a flat disk of solid angle Omega."""
+        return math.sqrt(self.omega / math.pi)
+
+    def sigma_w2(self, n_eps=SIGMA_W_NODES):
+        """sigma_W^2(chi_n) at every chi node (eq. Mask in the thin-shell
+        limit, App. B; definition after eq. CovPP22)."""
+        out = np.zeros(self.n_chi)
+        lib().or_sigma_w2(ct.byref(self.T), ct.c_double(self.theta_sky()), ct.c_int(n_eps), _p(out))
+        return out
+
+    def ssc_chi_pairs(self, pairs, rows=None, sw=None):
+        """The super-sample term of eq. WLSSCflatskyLimber with sigma_W^2(chi)
+        for the given (a, b) pairs of rows (default: the data-vector rows)."""
+        rows = self.rows if rows is None else rows
+        sw = self.sigma_w2() if sw is None else np.ascontiguousarray(sw, np.float64)
+        _, R = self.spectra()
         pairs = np.ascontiguousarray(pairs, np.int64)
-        ssc = float(self.cfg["sigma_b2"]) * r[pairs[:, 0]] * r[pairs[:, 1]]
-        out = self.gauss_pairs(pairs, ntri) + self.cov1h_pairs(pairs) + ssc
+        out = np.zeros(len(pairs))
+        lib().or_ssc_chi_pairs(ct.byref(self.T), _p(sw), _p(R),
+                               _p(np.ascontiguousarray(rows["kind"], np.int32)),
+                               _p(np.ascontiguousarray(rows["zbin"], np.int32)),
+                               _p(np.ascontiguousarray(rows["cfg"], np.int32)), ct.c_int64(len(pairs)),
+                               _p(pairs), _p(out))
+        return out
+
+    def cov_pairs(self, pairs, ntri=None, ngins=False, ssc="rank1"):
+        """Covariance entries C[a, b] for the given (a, b) pairs: Gaussian +
+        one-halo + super-sample term (+ the B.B, P.T and P.B terms when ngins
+        is set).  ssc="rank1": sigma_b^2 r r^T (one coherent long mode);
+        ssc="chi": the line-of-sight form with sigma_W^2(chi)."""
+        pairs = np.ascontiguousarray(pairs, np.int64)
+        if ssc == "chi":
+            sscv = self.ssc_chi_pairs(pairs)
+        else:
+            _, r = self.data_vector()
+            sscv = float(self.cfg["sigma_b2"]) * r[pairs[:, 0]] * r[pairs[:, 1]]
+        out = self.gauss_pairs(pairs, ntri) + self.cov1h_pairs(pairs) + sscv
         if ngins:
             out = out + self.ngins_pairs(pairs)
         return out
 
-    def covariance(self, ntri=None, ngins=False):
+    def covariance(self, ntri=None, ngins=False, ssc="rank1"):
         """Full joint covariance C^D (eq. eq:SN2) on the lower triangle,
-        mirrored (+ the B.B, P.T and P.B terms when ngins is set)."""
+        mirrored (+ the B.B, P.T and P.B terms when ngins is set; ssc as in
+        cov_pairs)."""
         canon, reps = canonical_rows(self.rows)
         nc = len(reps)
         ell, U = self.u_table()
@@ -430,12 +464,18 @@ class Oracle:
         lib().or_cov_full(ct.c_int(self.N), _p(c1h), ct.c_int(nc), _p(canon), ct.c_int(self.n_z),
                           _p(ps), _p(nm), _p(nt), ct.c_double(self.omega), _p(self.rows["kind"]),
                           _p(lbf), _p(zbf), _p(self.rows["tri"]), _p(r),
-                          ct.c_double(float(self.cfg["sigma_b2"])), _p(C))
+                          ct.c_double(float(self.cfg["sigma_b2"]) if ssc != "chi" else 0.0), _p(C))
+        extra = []
         if ngins:
+            extra.append(self.ngins_pairs)
+        if ssc == "chi":
+            extra.append(self.ssc_chi_pairs)
+        if extra:
             ii, jj = np.tril_indices(self.N)
-            v = self.ngins_pairs(np.stack([ii, jj], 1))
-            C[ii, jj] += v
-            C[jj[ii != jj], ii[ii != jj]] += v[ii != jj]
+            for f in extra:
+                v = f(np.stack([ii, jj], 1))
+                C[ii, jj] += v
+                C[jj[ii != jj], ii[ii != jj]] += v[ii != jj]
         return C
 
     @staticmethod
@@ -451,9 +491,9 @@ class Oracle:
             raise MemoryError("oracle S/N allocation failed")
         return out.value
 
-    def run(self, ntri=None, ngins=False):
+    def run(self, ntri=None, ngins=False, ssc="rank1"):
         d, r = self.data_vector()
-        C = self.covariance(ntri, ngins)
+        C = self.covariance(ntri, ngins, ssc)
         return dict(d=d, r=r, C=C, snr2=self.snr2(C, d))
 
     # ---- scalar pieces for pins

@@ -510,6 +510,68 @@ void or_cov1h_canon(const or_tables *T, const double *ell, const double *U, doub
 }
 
 /* --------------------------------------------------------------------
+ * Super-sample covariance resolved along the line of sight.
+ *
+ * sigma_W^2(chi) is the variance of the linear density contrast averaged
+ * over the survey's disk at distance chi: the delta_chi -> 0 limit of the
+ * cylinder window of eq. Mask (App. B; the quantity is defined after eq.
+ * CovPP22, Sec. 3.2.3).  In polar coordinates, d^2 eps = 2 pi eps d eps:
+ *   sigma_W^2(chi) = 4 int d^2 eps / (2 pi)^2 [J1(x) / x]^2 P(eps, chi)
+ *                  = (2 / pi) int eps^2 [J1(x) / x]^2 P(eps, chi) d ln eps,
+ *   x = eps chi Theta.
+ * Readings: Theta is the radius of a flat disk of solid angle Omega
+ * (pi Theta^2 = Omega); the integral runs over the k table by the trapezoid
+ * rule in ln eps on n_eps uniformly spaced nodes whose two end nodes are the
+ * table's first and last k; P(eps, chi) is read like every other table
+ * value; J1 is the C library's. */
+#define OR_PI 3.14159265358979323846
+
+void or_sigma_w2(const or_tables *T, double theta, int n_eps, double *out) {
+  const double l0 = log(T->k[0]), l1 = log(T->k[T->n_k - 1]);
+  const double h = (l1 - l0) / (n_eps - 1);
+#pragma omp parallel for schedule(static)
+  for (int n = 0; n < T->n_chi; ++n) {
+    const double *Pn = T->P + (size_t)n * T->n_k;
+    double s = 0.0;
+    for (int j = 0; j < n_eps; ++j) {
+      double eps = j == 0 ? T->k[0] : (j == n_eps - 1 ? T->k[T->n_k - 1] : exp(l0 + j * h));
+      double x = eps * T->chi[n] * theta;
+      double win = j1(x) / x;
+      double w = (j == 0 || j == n_eps - 1) ? 0.5 * h : h;
+      s += w * eps * eps * win * win * or_interp(T->k, Pn, T->n_k, eps);
+    }
+    out[n] = 2.0 / OR_PI * s;
+  }
+}
+
+/* The super-sample term of eq. WLSSCflatskyLimber with this variance:
+ *   C_ssc[a][b] = sum_n w_n sigma_W^2(chi_n) T_a(chi_n) R_a(chi_n) T_b(chi_n) R_b(chi_n),
+ * T_a = chi^(2 - 2 p_a) prod_q W_{z_q} the projection function of eq.
+ * nProjection and R_a the 3-D response of the row's ell-configuration at
+ * chi_n (tabulated by or_spectra_table; zero above k_max). */
+static double ssc_chi(const or_tables *T, const double *sw, const double *R, int ka, const int *za, int ca,
+                      int kb, const int *zb, int cb) {
+  double total = 0.0;
+  for (int n = 0; n < T->n_chi; ++n) {
+    double chi = T->chi[n];
+    double ta = pow(chi, 2.0 - 2.0 * ka), tb = pow(chi, 2.0 - 2.0 * kb);
+    for (int q = 0; q < ka; ++q) ta *= T->W[(size_t)za[q] * T->n_chi + n];
+    for (int q = 0; q < kb; ++q) tb *= T->W[(size_t)zb[q] * T->n_chi + n];
+    total += T->w_chi[n] * sw[n] * ta * R[(size_t)ca * T->n_chi + n] * tb * R[(size_t)cb * T->n_chi + n];
+  }
+  return total;
+}
+
+void or_ssc_chi_pairs(const or_tables *T, const double *sw, const double *R, const int *kind, const int *zbin,
+                      const int *cfg, int64_t n_pairs, const int64_t *pairs, double *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < n_pairs; ++q) {
+    int64_t a = pairs[2 * q], b = pairs[2 * q + 1];
+    out[q] = ssc_chi(T, sw, R, kind[a], &zbin[3 * a], cfg[a], kind[b], &zbin[3 * b], cfg[b]);
+  }
+}
+
+/* --------------------------------------------------------------------
  * Signal-to-noise, eq. SNprim (Sec. 5): (S/N)^2 = D^T C^{-1} D, through the
  * Cholesky-Banachiewicz factorisation C = L L^T (row by row) and forward
  * substitution y = L^{-1} D, (S/N)^2 = y^T y.  Returns -1 if C is not

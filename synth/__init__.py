@@ -25,7 +25,11 @@ model that is not reproduced; these stand in for them):
 * u(k, M) = exp(-(k r)^2 / 2), r = (3 M / (4 pi 200 rho))^(1/3), floored at
   1e-300 so that every table entry is strictly positive;
 * chi nodes are the midpoints of [0, chi(2.5)] (weight = spacing), masses
-  use the trapezoid rule in ln M, k is log-spaced.
+  use the trapezoid rule in ln M, k is log-spaced from
+  min(ell_min / (2 chi_max), 0.02 / (chi_max Theta)) to k_max, Theta =
+  2 sqrt(f_sky) the radius of a flat disk of solid angle 4 pi f_sky, so that
+  the table also covers the variance of the long mode in the survey window
+  (eps chi Theta <= 0.02 at the low end for every chi).
 """
 from __future__ import annotations
 
@@ -43,10 +47,10 @@ ARCMIN2_PER_SR = (10800.0 / math.pi) ** 2
 # "euclid5": 5 equipopulated bins, 10 ell-bins over 20-3000, 256 x 128;
 # "large10": 10 bins, 15 ell-bins over 10-5000, 512 x 256 (K = 131072).
 PRESETS = {
-    "tiny":    dict(n_z=2, n_ell=5, ell_min=100.0, ell_max=1000.0, n_chi=64, n_m=32, n_k=512),
-    "mid":     dict(n_z=3, n_ell=7, ell_min=50.0, ell_max=2000.0, n_chi=96, n_m=48, n_k=512),
-    "euclid5": dict(n_z=5, n_ell=10, ell_min=20.0, ell_max=3000.0, n_chi=256, n_m=128, n_k=512),
-    "large10": dict(n_z=10, n_ell=15, ell_min=10.0, ell_max=5000.0, n_chi=512, n_m=256, n_k=512),
+    "tiny":    dict(n_z=2, n_ell=5, ell_min=100.0, ell_max=1000.0, n_chi=64, n_m=32, n_k=768),
+    "mid":     dict(n_z=3, n_ell=7, ell_min=50.0, ell_max=2000.0, n_chi=96, n_m=48, n_k=768),
+    "euclid5": dict(n_z=5, n_ell=10, ell_min=20.0, ell_max=3000.0, n_chi=256, n_m=128, n_k=768),
+    "large10": dict(n_z=10, n_ell=15, ell_min=10.0, ell_max=5000.0, n_chi=512, n_m=256, n_k=768),
 }
 
 SURVEY_DEFAULTS = dict(f_sky=0.36, sigma_eps=0.3, n_gal_arcmin2=30.0,
@@ -182,9 +186,12 @@ def make_tables(preset="tiny", omega_m=0.3, sigma8=0.8, chi_grid_om=None,
     z_edges = equipopulated_edges(cfg["n_z"])
     W = lensing_kernels(chi, om, z_edges)
 
-    # k grid: from half the smallest ell over chi_max up to k_max
+    # k grid: from half the smallest ell over chi_max (or lower, down to the
+    # scale of the survey window at chi_max) up to k_max
     n_k = cfg["n_k"]
-    k = np.exp(np.linspace(math.log(0.5 * cfg["ell_min"] / chi_max), math.log(cfg["k_max"]), n_k))
+    theta = 2.0 * math.sqrt(cfg["f_sky"])
+    k_lo = min(0.5 * cfg["ell_min"] / chi_max, 0.02 / (chi_max * theta))
+    k = np.exp(np.linspace(math.log(k_lo), math.log(cfg["k_max"]), n_k))
     zt_om, chit_om = comoving_distance_table(om, n=40001)
     z_nodes = np.interp(chi, chit_om, zt_om, right=zt_om[-1])
     D = growth_table(om, z_nodes)
@@ -244,7 +251,7 @@ def sample_pairs(n, count, seed=42):
 # ---------------------------------------------------------- serving stream
 SERVE_GRID_OM = 0.28       # chi grid: midpoints of [0, chi(2.5; Omega_m = 0.28)]
 SERVE_FID = dict(omega_m=0.3, sigma8=0.8)
-PRESETS["serve"] = dict(n_z=10, n_ell=15, ell_min=10.0, ell_max=5000.0, n_chi=256, n_m=128, n_k=512)
+PRESETS["serve"] = dict(n_z=10, n_ell=15, ell_min=10.0, ell_max=5000.0, n_chi=256, n_m=128, n_k=768)
 
 
 def serving_fiducial() -> Tables:
