@@ -60,12 +60,20 @@ enum { WLC_FP64 = 0, WLC_BF16 = 1, WLC_BF16X3 = 2, WLC_FP32 = 3, WLC_FP64_CHI = 
 /* ---- flags */
 enum {
   WLC_FLAG_NOCHECK = 1, /* skip the table validation pass (and its one stream sync) */
-  WLC_FLAG_NGINS = 2    /* add the in-survey terms built from lower-order spectra:
+  WLC_FLAG_NGINS = 2,   /* add the in-survey terms built from lower-order spectra:
                            B.B and P.T between bispectra (eq. CovBB), P.B between
                            power spectrum and bispectrum (eq. Covpb); the P.T term
                            uses the projected one-halo trispectrum of the two other
                            legs of each triangle.  Not combinable with
                            wlc_snr2_structured. */
+  WLC_FLAG_SSC_CHI = 4  /* super-sample term resolved along the line of sight
+                           (eq. WLSSCflatskyLimber with sigma_W^2(chi)):
+                             sum_n w_n sigma_W^2(chi_n) T_a R_a T_b R_b at chi_n,
+                           T the projection function of eq. nProjection, R the
+                           3-D response, sigma_W^2 as in wlc_sigma_w2; it joins
+                           the Gram product as one more column per chi node
+                           (k_len = n_chi (n_m + 1)) and sigma_b2 is not used.
+                           Needs k[0] chi_max Theta <= 0.1 (WLC_ERANGE). */
 };
 
 typedef struct {
@@ -112,7 +120,8 @@ typedef struct {
   int64_t n_tri;       /* binned triangles                                    */
   int64_t n_cfg;       /* ell-configurations: ell-bins + triangles            */
   int64_t n_ell_used;  /* ell-bins below ell_cut                              */
-  int64_t k_len;       /* contraction length n_chi * n_m of the Gram product  */
+  int64_t k_len;       /* contraction length of the Gram product: n_chi * n_m,
+                          n_chi * (n_m + 1) with WLC_FLAG_SSC_CHI            */
   size_t c_elem_bytes; /* 8 (FP64) or 4 (mixed precisions)                    */
   size_t ws_run_bytes; /* device workspace needed by wlc_run                  */
   size_t ws_snr_bytes; /* device workspace needed by wlc_snr2                 */
@@ -164,13 +173,28 @@ int wlc_lattice_counts(wlc_plan plan, void *ws, uint64_t *modes, uint64_t *tris,
  *                     analogue, App. B) + one-halo 4/5/6-point terms (eqs.
  *                     CovPPNG, Ins5P, Ins6P with eq. General1h) computed as the
  *                     Gram product A A^T over the flattened (chi, M) axis +
- *                     sigma_b2 r r^T (eq. WLSSCflatskyLimber, single long mode);
+ *                     the super-sample term (eq. WLSSCflatskyLimber): sigma_b2
+ *                     r r^T for a single long mode, or with WLC_FLAG_SSC_CHI
+ *                     its line-of-sight form inside the Gram product;
  *   row_exp2 [n_data] the power-of-two scaling of C (see above).
  * ws: DEVICE workspace of at least ws_run_bytes, 256-byte aligned.
  * Unless WLC_FLAG_NOCHECK is set, validates the tables first and synchronises
  * the stream once (WLC_EINVAL / WLC_ERANGE); everything else is asynchronous. */
 int wlc_run(wlc_plan plan, const wlc_tables *tables, void *ws, double *d, double *r, void *C,
             int32_t *row_exp2, void *stream);
+
+/* sigma_W^2(chi_n) into DEVICE sw [n_chi]: the variance of the linear density
+ * contrast averaged over the survey's disk at each chi node, the thin-shell
+ * limit of the cylinder window of eq. Mask (App. B; definition after eq.
+ * CovPP22, Sec. 3.2.3):
+ *   sigma_W^2(chi) = 4 int d^2 eps / (2 pi)^2 [J1(x) / x]^2 P(eps, chi)
+ *                  = (2 / pi) int eps^2 [J1(x) / x]^2 P(eps, chi) d ln eps,
+ *   x = eps chi Theta, pi Theta^2 = Omega = 4 pi f_sky (a flat disk).
+ * The integral runs over the k table [k_0, k_last] by the trapezoid rule in
+ * ln eps on 16384 uniform nodes (end nodes: the table's own end values);
+ * P(eps, chi) is read like every table value.  Only chi, k and P are read.
+ * Asynchronous; no validation (the tables must satisfy wlc_run's rules). */
+int wlc_sigma_w2(wlc_plan plan, const wlc_tables *tables, double *sw, void *stream);
 
 /* (S/N)^2 = d^T C_true^-1 d (eq. SNprim) from wlc_run's outputs (DEVICE
  * C, row_exp2, d), by an FP64 Cholesky factorisation of the scaled matrix

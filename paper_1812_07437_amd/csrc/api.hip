@@ -52,8 +52,14 @@ constexpr int64_t K_ALIGN = 64;
 enum Buf {
   B_ROWR, B_ROWO, B_CFGT, B_CENT, B_NMODES, B_NTRI, B_THR, B_TRI, B_FLAGS,
   B_U, B_PK, B_NE, B_X, B_R, B_DR, B_RR, B_PS, B_G, B_GMAX, B_TS, B_SEXP,
-  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, NBUF
+  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, B_SW, NBUF
 };
+
+// Columns per chi node of the configuration factor G: the mass nodes, and
+// with the chi-resolved super-sample term one more.
+static int g_cols(const wlc_config &c) { return c.n_m + ((c.flags & WLC_FLAG_SSC_CHI) ? 1 : 0); }
+// Radius of the survey disk: a flat disk of solid angle Omega.
+static double theta_sky(const Plan &p) { return std::sqrt(p.omega / 3.14159265358979323846); }
 
 // two-leg trispectrum (B.B / P.T / P.B terms): configurations and rows
 static int twoleg_configs(const Plan &p) { return p.n_ell + p.n_ell * (p.n_ell - 1) / 2; }
@@ -87,7 +93,7 @@ static Layout run_layout(const Plan &p) {
   sz[B_X] = sz[B_R] = (size_t)n_cfg * c.n_chi * 8;
   sz[B_DR] = sz[B_RR] = (size_t)p.n_R * 8;
   sz[B_PS] = (size_t)nl * c.n_z * c.n_z * 8;
-  sz[B_G] = (size_t)n_cfg * c.n_chi * c.n_m * 8;
+  sz[B_G] = (size_t)n_cfg * c.n_chi * g_cols(c) * 8;
   sz[B_GMAX] = (size_t)n_cfg * c.n_chi * 8;
   sz[B_TS] = (size_t)p.n_R * c.n_chi * 8;
   sz[B_SEXP] = (size_t)p.n_R * 4;
@@ -107,6 +113,7 @@ static Layout run_layout(const Plan &p) {
     sz[B_TS2] = (size_t)twoleg_rows(p) * c.n_chi * 8;
     sz[B_T2] = (size_t)twoleg_rows(p) * twoleg_ld(p) * 8;
   }
+  if (c.flags & WLC_FLAG_SSC_CHI) sz[B_SW] = (size_t)c.n_chi * 8;
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < NBUF; ++b) {
@@ -137,7 +144,7 @@ size_t snr_structured_ws_bytes(const Plan &p) {
 }
 
 static void finish_sizes(Plan &p) {
-  p.k_len = (int64_t)p.cfg.n_chi * p.cfg.n_m;
+  p.k_len = (int64_t)p.cfg.n_chi * g_cols(p.cfg);
   p.k_pad = round_up(p.k_len, K_ALIGN);
   p.r_pad = round_up(p.n_R, GRAM_TILE);
   p.ws_run = run_ws_bytes(p);
@@ -191,7 +198,7 @@ int snr_structured_enqueue(const Plan &p, const void *ws_run, void *ws, hipStrea
   w.gm_f32 = !prec_f64(c.precision);
   w.ld_g = p.r_pad;
   w.omega = p.omega;
-  w.sigma_b2 = c.sigma_b2;
+  w.sigma_b2 = (c.flags & WLC_FLAG_SSC_CHI) ? 0.0 : c.sigma_b2;  // else inside the Gram product
   w.flag = flag;
   if (hooks) hooks->begin(WLC_PHASE_SNR_PREP);
   launch_fill_i32(flag, 1, 0, s);
@@ -278,13 +285,15 @@ int validate_tables(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s
   const DevTables T = dev_tables(p, tb);
   int32_t *flags = at<int32_t>(ws, L, B_FLAGS);
   launch_fill_i32(flags, 64, 0, s);
-  launch_validate(T, at<double>(ws, L, B_CENT), p.n_ell, flags, s);
-  int32_t hf[2] = {0, 0};
+  launch_validate(T, at<double>(ws, L, B_CENT), p.n_ell, (p.cfg.flags & WLC_FLAG_SSC_CHI) ? theta_sky(p) : 0.0,
+                  flags, s);
+  int32_t hf[3] = {0, 0, 0};
   rc = hip_check(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s), "validation copy");
   if (!rc) rc = hip_check(hipStreamSynchronize(s), "validation sync");
   if (rc) return rc;
   if (hf[0]) return fail(WLC_EINVAL, "tables must be finite, positive where required, and grids increasing");
   if (hf[1]) return fail(WLC_ERANGE, "the k table does not cover every ell/chi below k_max");
+  if (hf[2]) return fail(WLC_ERANGE, "the k table must start below 0.1 / (chi_max Theta) for sigma_W^2");
   return WLC_OK;
 }
 
@@ -313,7 +322,11 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   launch_spectra(T, cfgT, n_cfg, U, Pk, Ne, cent, X, R, s);
   launch_project(T, rowR, cfgT, p.n_R, X, R, dR, rR, s);
   launch_ps(dR, Ps, p.n_ell, c.n_z, p.noise, s);
-  launch_gfactor(T, cfgT, n_cfg, U, G, Gmax, s);
+  const bool ssc_chi = (c.flags & WLC_FLAG_SSC_CHI) != 0;
+  const int n_mg = g_cols(c);
+  double *sw = ssc_chi ? at<double>(ws, L, B_SW) : nullptr;
+  if (ssc_chi) launch_sigma_w2(T, theta_sky(p), sw, s);
+  launch_gfactor(T, cfgT, n_cfg, U, R, sw, std::sqrt(p.omega), n_mg, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
   if (c.flags & WLC_FLAG_NGINS) {
     // the projected one-halo trispectrum of two legs per triangle (the P.T
@@ -333,14 +346,14 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
     if (hooks) hooks->end(WLC_PHASE_ABUILD);
     if (hooks) hooks->begin(WLC_PHASE_GRAM);
     const int nz = c.n_z;
-    launch_chifact(Ts, G, at<double>(ws, L, B_H), n_cfg, c.n_chi, c.n_m, p.n_ell, nz * (nz + 1) / 2,
+    launch_chifact(Ts, G, at<double>(ws, L, B_H), n_cfg, c.n_chi, n_mg, p.n_ell, nz * (nz + 1) / 2,
                    nz * (nz + 1) * (nz + 2) / 6, p.n_tri, (double *)Gm, p.r_pad, s);
     if (hooks) hooks->end(WLC_PHASE_GRAM);
   } else {
     const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
     void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
     if (hooks) hooks->begin(WLC_PHASE_ABUILD);
-    launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, c.n_m, p.k_pad, p.k_pad, A0, A1, s);
+    launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, n_mg, p.k_pad, p.k_pad, A0, A1, s);
     if (hooks) hooks->end(WLC_PHASE_ABUILD);
     GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
     if (hooks) hooks->begin(WLC_PHASE_GRAM);
@@ -370,7 +383,7 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   a.n = p.n_out;
   a.omega = p.omega;
   a.inv_omega = 1.0 / p.omega;
-  a.sigma_b2 = c.sigma_b2;
+  a.sigma_b2 = ssc_chi ? 0.0 : c.sigma_b2;  // else inside the Gram product
   a.ngins = (c.flags & WLC_FLAG_NGINS) != 0;
   a.T2 = a.ngins ? at<double>(ws, L, B_T2) : nullptr;
   a.ld_t2 = a.ngins ? twoleg_ld(p) : 0;
@@ -567,6 +580,13 @@ int wlc_run(wlc_plan plan, const wlc_tables *tb, void *ws, double *d, double *r,
   PlanTimer tm(plan, s);
   const bool timed = plan->timing && plan->events_ready;
   return run_enqueue(p, *tb, ws, d, r, C, row_exp2, s, timed ? &tm : nullptr);
+}
+
+int wlc_sigma_w2(wlc_plan plan, const wlc_tables *tb, double *sw, void *stream) {
+  if (!plan || !tb || !sw || !tb->chi || !tb->k || !tb->P) return fail(WLC_EINVAL, "null argument");
+  const Plan &p = plan->p;
+  launch_sigma_w2(dev_tables(p, *tb), theta_sky(p), sw, (hipStream_t)stream);
+  return hip_check(hipGetLastError(), "sigma_W^2 launch");
 }
 
 int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws, double *snr2_host,

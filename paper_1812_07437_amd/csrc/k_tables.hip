@@ -17,7 +17,10 @@
 namespace wlc {
 
 // ------------------------------------------------------------- validation
-__global__ void k_validate(DevTables T, const double *centres, int n_ell, int *flags) {
+// flags[0]: a bad value; flags[1]: some ell/chi below k_max off the k table;
+// flags[2]: theta > 0 and k_0 chi_max theta > 0.1 (the table starts above the
+// scale of the survey window at the farthest node).
+__global__ void k_validate(DevTables T, const double *centres, int n_ell, double theta, int *flags) {
   const int64_t nP = (int64_t)T.n_chi * T.n_k, nU = (int64_t)T.n_m_pts * T.n_k, nW = (int64_t)T.n_z * T.n_chi;
   const int64_t nM = T.n_m_pts, nC = T.n_chi, nK = T.n_k, nCov = (int64_t)n_ell * T.n_chi;
   const int64_t total = nP + nU + nW + nM + nC + nK + nCov;
@@ -59,10 +62,13 @@ __global__ void k_validate(DevTables T, const double *centres, int n_ell, int *f
   }
   if (bad) atomicOr(&flags[0], 1);
   if (range) atomicOr(&flags[1], 1);
+  if (theta > 0.0 && blockIdx.x == 0 && threadIdx.x == 0 && !(T.k[0] * T.chi[T.n_chi - 1] * theta <= 0.1))
+    atomicOr(&flags[2], 1);
 }
 
-void launch_validate(const DevTables &T, const double *centres, int n_ell, int *flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_validate, dim3(512), dim3(256), 0, s, T, centres, n_ell, flags);
+void launch_validate(const DevTables &T, const double *centres, int n_ell, double theta, int *flags,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(512), dim3(256), 0, s, T, centres, n_ell, theta, flags);
 }
 
 // ------------------------------------------------------------- staging
@@ -277,7 +283,12 @@ void launch_ps(const double *dR, double *Ps, int n_ell, int n_z, double noise, h
 //   A[row][(n, m)] = sqrt(w_n) chi_n^-(2p-1) prod_i W_i(chi_n)        (= T[row][n])
 //                  * sqrt(w_m n_m) (m/rho)^p prod_legs u(m, l/chi_n)   (= G[cfg][n][m])
 // and (1/Omega) A A^T is the one-halo covariance of eqs. CovPPNG, Ins5P, Ins6P.
-__global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, const double *U, double *G, double *Gmax) {
+// With sw, one more column per chi node carries the super-sample term of eq.
+// WLSSCflatskyLimber resolved along chi,
+//   sum_n w_n sigma_W^2(chi_n) chi_n^(2-2p) prod W R_cfg(chi_n) (same for b),
+// as G[cfg][n][n_m] = sqrt(Omega) chi_n sqrt(sigma_W^2(chi_n)) R[cfg][n].
+__global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, const double *U, const double *R,
+                          const double *sw, double sq_omega, int n_mg, double *G, double *Gmax) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t item = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (item >= (int64_t)n_cfg * T.n_chi) return;
@@ -289,7 +300,7 @@ __global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, const dou
   const double *U2 = kind == 3 ? U + ((size_t)cfgT[4 * c + 3] * T.n_chi + n) * nm : nullptr;
   const double inv_rho = 1.0 / T.rho;
   double mx = 0.0;
-  double *Gout = G + (size_t)item * nm;
+  double *Gout = G + (size_t)item * n_mg;
   for (int mi = lane; mi < nm; mi += WAVE) {
     const double x = T.m[mi] * inv_rho;
     double g = sqrt(T.w_m[mi] * T.n_m[mi]) * x * x * U0[mi] * U1[mi];
@@ -297,14 +308,20 @@ __global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, const dou
     Gout[mi] = g;
     mx = fmax(mx, fabs(g));
   }
+  if (sw && lane == 0) {
+    const double g = sq_omega * T.chi[n] * sqrt(sw[n]) * R[item];
+    Gout[nm] = g;
+    mx = fmax(mx, fabs(g));
+  }
   mx = wave_max(mx);
   if (lane == 0) Gmax[item] = mx;
 }
 
-void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, double *G, double *Gmax,
-                    hipStream_t s) {
+void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *R,
+                    const double *sw, double sq_omega, int n_mg, double *G, double *Gmax, hipStream_t s) {
   const int64_t items = (int64_t)n_cfg * T.n_chi;
-  hipLaunchKernelGGL(k_gfactor, dim3((int)((items + 3) / 4)), dim3(256), 0, s, T, cfgT, n_cfg, U, G, Gmax);
+  hipLaunchKernelGGL(k_gfactor, dim3((int)((items + 3) / 4)), dim3(256), 0, s, T, cfgT, n_cfg, U, R, sw, sq_omega,
+                     n_mg, G, Gmax);
 }
 
 // Per distinct row: T[n] and the row exponent s = -e with
@@ -441,7 +458,7 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
       if (c != cc) {
         cc = c;
         const double *Gc = G + (size_t)c * k_len + k0;
-        if (k0 + 8 <= k_len) {
+        if (k0 + 8 <= k_len && (k_len & 1) == 0) {  // 16-byte aligned pairs
 #pragma unroll
           for (int q = 0; q < 8; q += 2) {
             const double2 t = *(const double2 *)(Gc + q);

@@ -10,7 +10,7 @@
 namespace wlc {
 
 // ---- tables and quadrature (k_tables.hip)
-void launch_validate(const DevTables &T, const double *centres, int n_ell, int *flags, hipStream_t s);
+void launch_validate(const DevTables &T, const double *centres, int n_ell, double theta, int *flags, hipStream_t s);
 void launch_stage(const DevTables &T, const double *centres, int n_ell, double *U, double *Pk, double *Ne,
                   hipStream_t s);
 void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *Pk,
@@ -18,8 +18,11 @@ void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const do
 void launch_project(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *X,
                     const double *R, double *dR, double *rR, hipStream_t s);
 void launch_ps(const double *dR, double *Ps, int n_ell, int n_z, double noise, hipStream_t s);
-void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, double *G, double *Gmax,
-                    hipStream_t s);
+// G [n_cfg][n_chi][n_mg]: n_mg = n_m, or n_m + 1 when sw != NULL, the last
+// column then holding sqrt(Omega) chi_n sqrt(sigma_W^2(chi_n)) R[cfg][n] (the
+// super-sample term resolved along chi as one more Gram column).
+void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *R,
+                    const double *sw, double sq_omega, int n_mg, double *G, double *Gmax, hipStream_t s);
 void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *Gmax,
                     double *Ts, int32_t *sexp, hipStream_t s);
 // fmt: 0 = f64, 1 = bf16 (hi only), 2 = bf16 hi + lo, 3 = f32
@@ -30,6 +33,11 @@ void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double 
 // [n2][n_chi][n_m] and Ts2 [rows][n_chi] for the n2 = n_ell (n_ell + 1) / 2
 // ell-bin pairs p <= q (p = q first) and their bin rows.
 void launch_twoleg(const DevTables &T, int n_ell, const double *U, double *G2, double *Ts2, hipStream_t s);
+
+// ---- survey window (k_window.hip): sigma_W^2 at every chi node, the
+// trapezoid rule in ln eps on WINDOW_NODES nodes over the k table
+constexpr int WINDOW_NODES = 16384;
+void launch_sigma_w2(const DevTables &T, double theta, double *sw, hipStream_t s);
 
 // ---- Gram product (k_gram.hip): lower-triangle tiles of A A^T
 struct GramShape {

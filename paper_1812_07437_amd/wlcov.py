@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libwlcov.so")
 WLC_OK, WLC_EINVAL, WLC_ERANGE, WLC_ENOMEM, WLC_ENOTPD, WLC_EDEVICE, WLC_EBUSY = 0, -1, -2, -3, -4, -5, -6
 WLC_TOMO_PAPER, WLC_TOMO_SORTED = 0, 1
 WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32, WLC_FP64_CHI = 0, 1, 2, 3, 4
-WLC_FLAG_NOCHECK, WLC_FLAG_NGINS = 1, 2
+WLC_FLAG_NOCHECK, WLC_FLAG_NGINS, WLC_FLAG_SSC_CHI = 1, 2, 4
 PRECISIONS = {"fp64": WLC_FP64, "bf16": WLC_BF16, "bf16x3": WLC_BF16X3, "fp32": WLC_FP32,
               "fp64_chi": WLC_FP64_CHI}
 
@@ -65,6 +65,7 @@ def _load():
     L.wlc_counts_closed.argtypes = [vp, vp, vp]
     L.wlc_lattice_counts.argtypes = [vp, vp, vp, vp, vp]
     L.wlc_run.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp, vp, vp, vp, vp]
+    L.wlc_sigma_w2.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp]
     L.wlc_snr2.argtypes = [vp, vp, vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_snr2_structured.argtypes = [vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
@@ -76,7 +77,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_snr2", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
@@ -139,6 +140,10 @@ def wlc_run(plan, tables: wlc_tables, ws, d, r, C, row_exp2, stream):
     _check(lib.wlc_run(plan, ct.byref(tables), ws, d, r, C, row_exp2, stream))
 
 
+def wlc_sigma_w2(plan, tables: wlc_tables, sw, stream):
+    _check(lib.wlc_sigma_w2(plan, ct.byref(tables), sw, stream))
+
+
 def wlc_snr2(plan, C, row_exp2, d, ws, stream):
     out = ct.c_double()
     _check(lib.wlc_snr2(plan, C, row_exp2, d, ws, ct.byref(out), stream))
@@ -152,14 +157,18 @@ def wlc_snr2_structured(plan, ws_run, ws, stream):
 
 
 # ---------------------------------------------------------------- helpers
-def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False, ngins=False) -> wlc_config:
+def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False, ngins=False,
+                ssc_chi=False) -> wlc_config:
     """wlc_config from a dict of scalars (n_z, n_ell, n_chi, n_k, n_m, ell_min,
     ell_max, f_sky, sigma_eps, n_gal_arcmin2, sigma_b2, k_max, rho_mean and
-    optionally ell_cut); ngins adds the B.B, P.T and P.B terms."""
+    optionally ell_cut); ngins adds the B.B, P.T and P.B terms, ssc_chi
+    resolves the super-sample term along the line of sight."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    flags = (WLC_FLAG_NOCHECK if nocheck else 0) | (WLC_FLAG_NGINS if ngins else 0) | \
+        (WLC_FLAG_SSC_CHI if ssc_chi else 0)
     return wlc_config(n_z=int(cfg["n_z"]), n_ell=int(cfg["n_ell"]), n_chi=int(cfg["n_chi"]), n_k=int(cfg["n_k"]),
                       n_m=int(cfg["n_m"]), tomo_mode=WLC_TOMO_SORTED if tomo == "sorted" else WLC_TOMO_PAPER,
-                      precision=prec, flags=(WLC_FLAG_NOCHECK if nocheck else 0) | (WLC_FLAG_NGINS if ngins else 0),
+                      precision=prec, flags=flags,
                       ell_min=float(cfg["ell_min"]), ell_max=float(cfg["ell_max"]),
                       ell_cut=float(cfg.get("ell_cut", 0.0) or 0.0), f_sky=float(cfg["f_sky"]),
                       sigma_eps=float(cfg["sigma_eps"]), n_gal_arcmin2=float(cfg["n_gal_arcmin2"]),
@@ -181,11 +190,11 @@ class Problem:
     u, n_m, optional b1, b2, n_tri) to float64 arrays (numpy or torch)."""
 
     def __init__(self, cfg: dict, arrays: dict, precision="fp64", tomo="paper", device="cuda:0",
-                 nocheck=False, ngins=False):
+                 nocheck=False, ngins=False, ssc_chi=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.config = make_config(cfg, precision, tomo, nocheck, ngins)
+        self.config = make_config(cfg, precision, tomo, nocheck, ngins, ssc_chi)
         self.plan = wlc_plan_create(self.config)
         self.sizes = wlc_plan_sizes(self.plan)
         self._tabs = {}
@@ -220,6 +229,12 @@ class Problem:
     def run(self, stream=None):
         wlc_run(self.plan, self.tables, _ptr(self.ws), _ptr(self.d), _ptr(self.r), _ptr(self.C),
                 _ptr(self.row_exp2), _stream_handle(stream))
+
+    def sigma_w2(self, stream=None):
+        """sigma_W^2 at every chi node of this problem's tables (device)."""
+        sw = self.torch.empty(int(self.config.n_chi), dtype=self.torch.float64, device=self.device)
+        wlc_sigma_w2(self.plan, self.tables, _ptr(sw), _stream_handle(stream))
+        return sw
 
     def snr2(self, stream=None):
         if self.ws_snr is None:

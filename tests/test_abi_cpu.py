@@ -149,3 +149,24 @@ def test_workspace_sizes_cover_buffers():
         assert s.ws_run_bytes > a_bytes + r_pad * r_pad * el
         assert s.ws_snr_bytes >= (s.n_data + 1) ** 2 * 8
         w.wlc_plan_destroy(p)
+
+
+def test_chi_resolved_ssc_sizes():
+    """With the line-of-sight super-sample term the Gram product gains one
+    column per chi node; the rest of the plan is unchanged."""
+    t = dict(synth.PRESETS["large10"]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 1e11
+    for prec in ("fp64", "bf16x3", "fp64_chi"):
+        p0 = w.wlc_plan_create(w.make_config(t, prec))
+        p1 = w.wlc_plan_create(w.make_config(t, prec, ssc_chi=True))
+        s0, s1 = w.wlc_plan_sizes(p0), w.wlc_plan_sizes(p1)
+        assert s0.k_len == t["n_chi"] * t["n_m"]
+        assert s1.k_len == t["n_chi"] * (t["n_m"] + 1)
+        assert (s1.n_data, s1.n_distinct, s1.ws_snr_bytes) == (s0.n_data, s0.n_distinct, s0.ws_snr_bytes)
+        assert s1.ws_run_bytes > s0.ws_run_bytes
+        w.wlc_plan_destroy(p0)
+        w.wlc_plan_destroy(p1)
+    _, plan = _plan("tiny")
+    with pytest.raises(w.WlcError) as e:
+        w.wlc_sigma_w2(plan, w.wlc_tables(), None, None)
+    assert e.value.code == w.WLC_EINVAL
+    w.wlc_plan_destroy(plan)

@@ -145,3 +145,33 @@ def test_large10_ngins_sampled(wl, ref):
     pc.close()
     del pc
     torch.cuda.empty_cache()
+
+
+def test_large10_ssc_chi_sampled(wl, ref):
+    """The super-sample term resolved along chi at full size (FP64, one-halo
+    term factorised along chi): sampled entries against the oracle, and the
+    structured S/N against the plain one."""
+    t = ref["t"]
+    o = oracle.Oracle(t)
+    pairs = np.concatenate([ref["off"][:200], np.stack([ref["rows"][:200]] * 2, 1)])
+    _say("oracle with the chi-resolved super-sample term: %d entries" % len(pairs))
+    want = o.cov_pairs(pairs, ssc="chi")
+    _say("case large10 fp64_chi ssc_chi")
+    pc = wl.Problem(t.cfg, t.arrays(), precision="fp64_chi", ssc_chi=True)
+    pc.run()
+    snr = pc.snr2()
+    torch.cuda.synchronize()
+    got, sym = _entries(pc, pairs)
+    assert sym
+    scale = np.sqrt(np.abs(o.cov_pairs(np.stack([pairs[:, 0], pairs[:, 0]], 1), ssc="chi") *
+                           o.cov_pairs(np.stack([pairs[:, 1], pairs[:, 1]], 1), ssc="chi")))
+    err = np.max(np.abs(got - want) / scale)
+    _say("  max rel to sqrt(C_aa C_bb) %.3e" % err)
+    assert err < 1e-10
+    pc.free_snr_workspace()
+    st = pc.snr2_structured()
+    _say("  (S/N)^2 plain %.12e structured %.12e" % (snr, st))
+    assert abs(st - snr) / snr < 1e-9
+    pc.close()
+    del pc
+    torch.cuda.empty_cache()

@@ -130,7 +130,8 @@ def test_validation_errors(wl):
     with pytest.raises(wl.WlcError) as e:
         prob.run()
     assert e.value.code == wl.WLC_EINVAL
-    short = dict(arr); short["k"] = arr["k"] * 3.0
+    short = dict(arr)  # the table starts above ell_min / chi_max
+    short["k"] = arr["k"] * (2.0 * t.cfg["ell_min"] / (t.chi[-1] * arr["k"][0]))
     prob = wl.Problem(t.cfg, short, "fp64")
     with pytest.raises(wl.WlcError) as e:
         prob.run()

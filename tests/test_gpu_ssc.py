@@ -1,0 +1,143 @@
+"""Parity of the super-sample term resolved along the line of sight between
+the HIP path (through the C ABI) and the FP64 oracle: sigma_W^2(chi) of the
+survey disk (eq. Mask in the thin-shell limit, App. B) and the covariance
+with the term of eq. WLSSCflatskyLimber carried by the Gram product."""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def wl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_07437_amd import wlcov
+    return wlcov
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b) / np.abs(b))
+
+
+@pytest.mark.parametrize("preset", ["tiny", "mid", "euclid5", "large10"])
+def test_sigma_w2(wl, preset):
+    """FP64: the GPU's own J1 and quadrature against the oracle's (C library
+    J1); every term of the sum is positive, so 1e-12 is a loose bound."""
+    _say("case sigma_w2 %s" % preset)
+    t = synth.make_tables(preset)
+    want = oracle.Oracle(t).sigma_w2()
+    prob = wl.Problem(t.cfg, t.arrays(), precision="fp64", ssc_chi=True)
+    got = prob.sigma_w2().cpu().numpy()
+    err = _rel(got, want)
+    _say("  max rel %.3e" % err)
+    assert err < 1e-12
+    prob.close()
+
+
+def test_sigma_w2_white_noise(wl):
+    """Constant P: the GPU value is the variance of white noise over the disk,
+    P0 / (Omega chi^2), within the quadrature's aliasing bound."""
+    _say("case sigma_w2 white noise")
+    P0 = 2.5e3
+    t = synth.power_law_tables(n_chi=16, n_k=64)
+    theta = 2.0 * math.sqrt(t.cfg["f_sky"])
+    k = np.exp(np.linspace(math.log(1e-5 / (t.chi[-1] * theta)), math.log(1e6 / (t.chi[0] * theta)), 64))
+    t = dataclasses.replace(t, k=k, P=np.full((16, 64), P0), u=np.ones((len(t.m), 64)))
+    prob = wl.Problem(t.cfg, t.arrays(), precision="fp64", ssc_chi=True)
+    got = prob.sigma_w2().cpu().numpy()
+    want = P0 / (4.0 * math.pi * t.cfg["f_sky"] * t.chi ** 2)
+    assert np.max(np.abs(got / want - 1.0)) < 1e-4
+    prob.close()
+
+
+_ORACLE = {}
+
+
+def _oracle(preset, tomo):
+    key = (preset, tomo)
+    if key not in _ORACLE:
+        t = synth.make_tables(preset)
+        o = oracle.Oracle(t, tomo=tomo)
+        _ORACLE[key] = (t, o, o.run(ssc="chi"))
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp64_chi"])
+@pytest.mark.parametrize("preset,tomo", [("tiny", "paper"), ("tiny", "sorted"), ("mid", "paper")])
+def test_ssc_chi_full_parity(wl, preset, tomo, precision):
+    _say("case ssc_chi %s %s %s" % (precision, preset, tomo))
+    t, o, ref = _oracle(preset, tomo)
+    prob = wl.Problem(t.cfg, t.arrays(), precision=precision, tomo=tomo, ssc_chi=True)
+    prob.run()
+    snr2 = prob.snr2()
+    torch.cuda.synchronize()
+    assert _rel(prob.d.cpu().numpy(), ref["d"]) < 1e-10
+    C = prob.covariance_true()
+    err = _rel(C, ref["C"])
+    _say("  C max rel %.3e" % err)
+    assert err < 1e-10
+    Cs = prob.C.cpu().numpy()
+    assert np.array_equal(Cs, Cs.T)
+    assert abs(snr2 - ref["snr2"]) / ref["snr2"] < 1e-10
+    if tomo == "paper":
+        st = prob.snr2_structured()
+        assert abs(st - ref["snr2"]) / ref["snr2"] < 1e-10
+    # the term is really there: it differs from the rank-one form
+    o1 = o.run()["C"]
+    assert _rel(ref["C"], o1) > 1e-6
+    prob.close()
+
+
+@pytest.mark.parametrize("preset", ["tiny", "mid"])
+def test_ssc_chi_mixed(wl, preset):
+    """bf16x3: the extra column rides through the split-bf16 product; 1e-5 on
+    the diagonal and off it relative to sqrt(C_aa C_bb), 1e-4 on S/N."""
+    _say("case ssc_chi bf16x3 %s" % preset)
+    t, o, ref = _oracle(preset, "paper")
+    prob = wl.Problem(t.cfg, t.arrays(), precision="bf16x3", ssc_chi=True)
+    prob.run()
+    snr2 = prob.snr2()
+    st = prob.snr2_structured()
+    torch.cuda.synchronize()
+    C = prob.covariance_true()
+    dg = np.diag(ref["C"])
+    assert np.max(np.abs(np.diag(C) - dg) / dg) < 1e-5
+    assert np.max(np.abs(C - ref["C"]) / np.sqrt(np.outer(dg, dg))) < 1e-5
+    assert abs(snr2 - ref["snr2"]) / ref["snr2"] < 1e-4
+    assert abs(st - ref["snr2"]) / ref["snr2"] < 1e-4
+    prob.close()
+
+
+def test_ssc_chi_needs_window_scale(wl):
+    """A k table that starts above 0.1 / (chi_max Theta) is refused with the
+    chi-resolved term and accepted without it."""
+    _say("case ssc_chi range check")
+    t = synth.make_tables("tiny")
+    keep = t.k >= 0.5 * t.cfg["ell_min"] / t.chi[-1]
+    cfg = dict(t.cfg, n_k=int(np.count_nonzero(keep)))
+    t = dataclasses.replace(t, cfg=cfg, k=t.k[keep], P=np.ascontiguousarray(t.P[:, keep]),
+                            u=np.ascontiguousarray(t.u[:, keep]))
+    prob = wl.Problem(t.cfg, t.arrays(), precision="fp64", ssc_chi=True)
+    with pytest.raises(wl.WlcError) as e:
+        prob.run()
+    assert e.value.code == wl.WLC_ERANGE
+    prob.close()
+    prob = wl.Problem(t.cfg, t.arrays(), precision="fp64")
+    prob.run()
+    torch.cuda.synchronize()
+    prob.close()
