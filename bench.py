@@ -333,6 +333,22 @@ def main():
         del pn
         torch.cuda.empty_cache()
 
+    # the FP64 step with the super-sample term resolved along chi (sigma_W^2
+    # of the survey disk), S/N through the distinct rows
+    sscc = None
+    if args.chi_steps > 0:
+        log("fp64 chi path with the chi-resolved super-sample term")
+        ps = wl.Problem(cfg, t.arrays(), precision="fp64_chi", device="cuda:0", ssc_chi=True)
+        dtx, phx, snrx, _ = timed_steps(ps, args.chi_steps, 1, torch, wl, structured=True)
+        ref_snr = fp64["snr2"] if fp64 else snr_mixed
+        sw = ps.sigma_w2().cpu().numpy()
+        sscc = dict(ms_per_step=dtx / args.chi_steps * 1e3, phases_ms=phx, snr2=snrx[-1], snr2_rank_one=ref_snr,
+                    sigma_w2_range=[float(sw.min()), float(sw.max())])
+        log("fp64 chi + chi-resolved SSC (structured S/N): %.1f ms/step  phases %s  (S/N)^2 %.6e (rank-one: %.6e)"
+            % (sscc["ms_per_step"], {k: round(v, 2) for k, v in phx.items()}, snrx[-1], ref_snr))
+        del ps
+        torch.cuda.empty_cache()
+
     # roofline of the dominant kernel of the step: the one-halo Gram (one
     # launch per step) or the Cholesky block update (many launches per step,
     # timed one by one with HIP events on the run's stream)
@@ -395,6 +411,7 @@ def main():
         "fp64_path": fp64,
         "fp64_chi_path": chi,
         "fp64_chi_ngins_path": ngins,
+        "fp64_chi_ssc_chi_path": sscc,
         "serving": srv,
     }
     print(json.dumps(out), flush=True)

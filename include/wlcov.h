@@ -189,7 +189,8 @@ int wlc_run(wlc_plan plan, const wlc_tables *tables, void *ws, double *d, double
  * CovPP22, Sec. 3.2.3):
  *   sigma_W^2(chi) = 4 int d^2 eps / (2 pi)^2 [J1(x) / x]^2 P(eps, chi)
  *                  = (2 / pi) int eps^2 [J1(x) / x]^2 P(eps, chi) d ln eps,
- *   x = eps chi Theta, pi Theta^2 = Omega = 4 pi f_sky (a flat disk).
+ *   x = eps chi Theta, Theta the survey's angular radius:
+ *   Omega = 4 pi f_sky = 2 pi (1 - cos Theta) (Sec. 3.2.2, after eq. PSest).
  * The integral runs over the k table [k_0, k_last] by the trapezoid rule in
  * ln eps on 16384 uniform nodes (end nodes: the table's own end values);
  * P(eps, chi) is read like every table value.  Only chi, k and P are read.

@@ -400,8 +400,9 @@ class Oracle:
     SIGMA_W_NODES = 16384
 
     def theta_sky(self):
-        """Radius of the survey disk: a flat disk of solid angle Omega."""
-        return math.sqrt(self.omega / math.pi)
+        """Angular radius of the survey, Omega = 2 pi (1 - cos Theta) (the
+        relation given after eq. PSest, Sec. 3.2.2)."""
+        return math.acos(1.0 - self.omega / (2.0 * math.pi))
 
     def sigma_w2(self, n_eps=SIGMA_W_NODES):
         """sigma_W^2(chi_n) at every chi node (eq. Mask in the thin-shell

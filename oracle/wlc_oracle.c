@@ -519,11 +519,11 @@ void or_cov1h_canon(const or_tables *T, const double *ell, const double *U, doub
  *   sigma_W^2(chi) = 4 int d^2 eps / (2 pi)^2 [J1(x) / x]^2 P(eps, chi)
  *                  = (2 / pi) int eps^2 [J1(x) / x]^2 P(eps, chi) d ln eps,
  *   x = eps chi Theta.
- * Readings: Theta is the radius of a flat disk of solid angle Omega
- * (pi Theta^2 = Omega); the integral runs over the k table by the trapezoid
- * rule in ln eps on n_eps uniformly spaced nodes whose two end nodes are the
- * table's first and last k; P(eps, chi) is read like every other table
- * value; J1 is the C library's. */
+ * Theta is the survey's angular radius, Omega = 2 pi (1 - cos Theta) (Sec.
+ * 3.2.2, after eq. PSest).  Readings: the integral runs over the k table by
+ * the trapezoid rule in ln eps on n_eps uniformly spaced nodes whose two end
+ * nodes are the table's first and last k; P(eps, chi) is read like every
+ * other table value; J1 is the C library's. */
 #define OR_PI 3.14159265358979323846
 
 void or_sigma_w2(const or_tables *T, double theta, int n_eps, double *out) {

@@ -58,8 +58,8 @@ enum Buf {
 // Columns per chi node of the configuration factor G: the mass nodes, and
 // with the chi-resolved super-sample term one more.
 static int g_cols(const wlc_config &c) { return c.n_m + ((c.flags & WLC_FLAG_SSC_CHI) ? 1 : 0); }
-// Radius of the survey disk: a flat disk of solid angle Omega.
-static double theta_sky(const Plan &p) { return std::sqrt(p.omega / 3.14159265358979323846); }
+// Angular radius of the survey: Omega = 2 pi (1 - cos Theta) (Sec. 3.2.2).
+static double theta_sky(const Plan &p) { return std::acos(1.0 - p.omega / (2.0 * 3.14159265358979323846)); }
 
 // two-leg trispectrum (B.B / P.T / P.B terms): configurations and rows
 static int twoleg_configs(const Plan &p) { return p.n_ell + p.n_ell * (p.n_ell - 1) / 2; }

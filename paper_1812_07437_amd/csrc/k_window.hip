@@ -6,8 +6,8 @@
 // window of eq. Mask (App. B).  In polar coordinates,
 //   sigma_W^2(chi) = (2 / pi) int eps^2 [J1(x) / x]^2 P(eps, chi) d ln eps,
 //   x = eps chi Theta,
-// with Theta the radius of a flat disk of solid angle Omega (pi Theta^2 =
-// Omega).  The integral runs over the k table by the trapezoid rule in ln eps
+// with Theta the survey's angular radius, Omega = 2 pi (1 - cos Theta) (the
+// relation given after eq. PSest, Sec. 3.2.2).  The integral runs over the k table by the trapezoid rule in ln eps
 // on WINDOW_NODES uniformly spaced nodes, the two end nodes being the table's
 // first and last k; P is read by the table interpolation of every other
 // kernel (linear in ln P against ln k).

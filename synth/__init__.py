@@ -26,8 +26,8 @@ model that is not reproduced; these stand in for them):
   1e-300 so that every table entry is strictly positive;
 * chi nodes are the midpoints of [0, chi(2.5)] (weight = spacing), masses
   use the trapezoid rule in ln M, k is log-spaced from
-  min(ell_min / (2 chi_max), 0.02 / (chi_max Theta)) to k_max, Theta =
-  2 sqrt(f_sky) the radius of a flat disk of solid angle 4 pi f_sky, so that
+  min(ell_min / (2 chi_max), 0.02 / (chi_max Theta)) to k_max, Theta the
+  survey's angular radius (4 pi f_sky = 2 pi (1 - cos Theta)), so that
   the table also covers the variance of the long mode in the survey window
   (eps chi Theta <= 0.02 at the low end for every chi).
 """
@@ -189,7 +189,7 @@ def make_tables(preset="tiny", omega_m=0.3, sigma8=0.8, chi_grid_om=None,
     # k grid: from half the smallest ell over chi_max (or lower, down to the
     # scale of the survey window at chi_max) up to k_max
     n_k = cfg["n_k"]
-    theta = 2.0 * math.sqrt(cfg["f_sky"])
+    theta = math.acos(1.0 - 2.0 * cfg["f_sky"])
     k_lo = min(0.5 * cfg["ell_min"] / chi_max, 0.02 / (chi_max * theta))
     k = np.exp(np.linspace(math.log(k_lo), math.log(cfg["k_max"]), n_k))
     zt_om, chit_om = comoving_distance_table(om, n=40001)

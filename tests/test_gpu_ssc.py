@@ -51,16 +51,16 @@ def test_sigma_w2(wl, preset):
 
 def test_sigma_w2_white_noise(wl):
     """Constant P: the GPU value is the variance of white noise over the disk,
-    P0 / (Omega chi^2), within the quadrature's aliasing bound."""
+    P0 / (pi (chi Theta)^2), within the quadrature's aliasing bound."""
     _say("case sigma_w2 white noise")
     P0 = 2.5e3
     t = synth.power_law_tables(n_chi=16, n_k=64)
-    theta = 2.0 * math.sqrt(t.cfg["f_sky"])
+    theta = math.acos(1.0 - 2.0 * t.cfg["f_sky"])  # Omega = 2 pi (1 - cos Theta)
     k = np.exp(np.linspace(math.log(1e-5 / (t.chi[-1] * theta)), math.log(1e6 / (t.chi[0] * theta)), 64))
     t = dataclasses.replace(t, k=k, P=np.full((16, 64), P0), u=np.ones((len(t.m), 64)))
     prob = wl.Problem(t.cfg, t.arrays(), precision="fp64", ssc_chi=True)
     got = prob.sigma_w2().cpu().numpy()
-    want = P0 / (4.0 * math.pi * t.cfg["f_sky"] * t.chi ** 2)
+    want = P0 / (math.pi * (t.chi * theta) ** 2)
     assert np.max(np.abs(got / want - 1.0)) < 1e-4
     prob.close()
 

@@ -15,7 +15,7 @@ def _flat_tables(P_of_k, n_chi=16, chi_max=3000.0, n_k=64):
     """Tables whose P(k, chi) = P_of_k(k) at every chi, on a k range wide
     enough that the disk window is resolved at every chi node."""
     t = synth.power_law_tables(n_chi=n_chi, chi_max=chi_max, n_k=n_k)
-    theta = 2.0 * math.sqrt(t.cfg["f_sky"])
+    theta = math.acos(1.0 - 2.0 * t.cfg["f_sky"])  # Omega = 2 pi (1 - cos Theta)
     k = np.exp(np.linspace(math.log(1e-5 / (chi_max * theta)), math.log(1e6 / (t.chi[0] * theta)), n_k))
     P = np.tile(P_of_k(k), (n_chi, 1))
     u = np.ones((len(t.m), n_k))
@@ -24,8 +24,7 @@ def _flat_tables(P_of_k, n_chi=16, chi_max=3000.0, n_k=64):
 
 def test_white_noise_disk_variance():
     """Constant P = P0: the disk average of white noise has variance P0 over
-    the disk's area pi (chi Theta)^2 = Omega chi^2 (from int_0^inf J1(x)^2 / x
-    dx = 1/2).  Truncation of the k range costs < 1e-6 here; the trapezoid
+    the disk's area pi (chi Theta)^2 (from int_0^inf J1(x)^2 / x dx = 1/2).  Truncation of the k range costs < 1e-6 here; the trapezoid
     rule aliases the unresolved oscillation of J1^2 at x >> 1 / h, which
     the tolerance bounds (a few 1e-5 at most)."""
     P0 = 2.5e3
