@@ -191,6 +191,79 @@ def n_tri_closed(l1, l2, l3, d1, d2, d3, f_sky):
     return om ** 2 * l1 * l2 * l3 * d1 * d2 * d3 / (2.0 * math.pi ** 3 * math.sqrt(lam2))
 
 
+def sub_bin_centres(edges, centres, n_ell, S):
+    """Centres of S equal-width sub-bins of each of the first n_ell ell-bins,
+    bin b owning entries b S .. b S + S - 1 (the bin centres when S = 1)."""
+    if S == 1:
+        return list(centres[:n_ell])
+    out = []
+    for b in range(n_ell):
+        w = edges[b + 1] - edges[b]
+        out.extend(edges[b] + (s + 0.5) * w / S for s in range(S))
+    return out
+
+
+def cell_pairs(a1, b1, a2, b2, a3, b3, n=8):
+    """Continuum number of ordered mode pairs (l1, l2) with |l1| in [a1, b1),
+    |l2| in [a2, b2) and |l1 + l2| in [a3, b3), up to the constant
+    (Omega / (2 pi)^2)^2 2 pi: the triangle count of App. B (a sum of the
+    selection function) in the continuum.  With phi the angle between the
+    modes, |l1 + l2|^2 = l1^2 + l2^2 + 2 l1 l2 cos phi, so the angles in the
+    cell form an interval of cos phi, integrated exactly; l1 and l2 by
+    Gauss-Legendre on n x n nodes."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    total = 0.0
+    for xi, wi in zip(x, w):
+        l1 = 0.5 * (a1 + b1) + 0.5 * (b1 - a1) * xi
+        for xj, wj in zip(x, w):
+            l2 = 0.5 * (a2 + b2) + 0.5 * (b2 - a2) * xj
+            lo = min(1.0, max(-1.0, (a3 * a3 - l1 * l1 - l2 * l2) / (2 * l1 * l2)))
+            hi = min(1.0, max(-1.0, (b3 * b3 - l1 * l1 - l2 * l2) / (2 * l1 * l2)))
+            dphi = 2.0 * (math.acos(lo) - math.acos(hi))
+            total += 0.25 * (b1 - a1) * (b2 - a2) * wi * wj * l1 * l2 * dphi
+    return total
+
+
+def averaging_lists(kinds, legs, S, sub_c, widths):
+    """The binned estimators average over the modes of each bin (Sec. 3.2.2)
+    and over the triangles of each triangle bin (App. B); the paper takes
+    the bin centres instead.  With S sub-bins per side: a power-spectrum bin
+    averages over its sub-bins weighted by their number of modes (2 l dl
+    f_sky, so proportional to l at equal widths); a triangle bin over the
+    cells of sub-bin triples whose centres obey the strict triangle
+    inequality, weighted by the continuum count of mode pairs in the cell
+    (cell_pairs), with the polyspectra taken at the cell centres.  Returns,
+    per configuration, (legs [E][3] as sub-bin indices, weights [E] summing
+    to one); S = 1 gives the bin centres with weight 1."""
+    out = []
+    for kind, lg in zip(kinds, legs):
+        if S == 1:
+            L = [(lg[0], lg[0], lg[0]) if kind == 2 else tuple(lg)]
+            W = [1.0]
+        elif kind == 2:
+            L = [(lg[0] * S + s,) * 3 for s in range(S)]
+            W = [sub_c[lg[0] * S + s] for s in range(S)]
+        else:
+            L, W = [], []
+            for s1 in range(S):
+                for s2 in range(S):
+                    for s3 in range(S):
+                        g = (lg[0] * S + s1, lg[1] * S + s2, lg[2] * S + s3)
+                        l1, l2, l3 = (sub_c[x] for x in g)
+                        if not (l1 < l2 + l3 and l2 < l1 + l3 and l3 < l1 + l2):
+                            continue
+                        h = [widths[lg[q]] / S / 2 for q in range(3)]
+                        n = cell_pairs(l1 - h[0], l1 + h[0], l2 - h[1], l2 + h[1], l3 - h[2], l3 + h[2])
+                        if n > 0:
+                            L.append(g)
+                            W.append(n)
+            if not L:
+                raise ValueError("a binned triangle has no sub-bin triangle")
+        W = np.array(W, np.float64)
+        out.append((np.array(L, np.int32), W / W.sum() if S > 1 else W))
+    return out
+
+
 def lattice_thresholds(edges, f_sky):
     """Integer thresholds on |q|^2 for the mode lattice: fundamental mode
     l_f = 2 pi / sqrt(Omega) (a square patch of area Omega; reading of
@@ -217,7 +290,7 @@ def lattice_triangles(thr, b1, b2, b3):
 class Oracle:
     """Holds one set of input tables and evaluates the method on them."""
 
-    def __init__(self, tables, tomo="paper"):
+    def __init__(self, tables, tomo="paper", n_sub=1):
         self.t = tables
         cfg = tables.cfg
         self.cfg = cfg
@@ -248,6 +321,13 @@ class Oracle:
         self.n_m = len(arr["m"])
         self._spectra = None
         self._U = None
+        # bin averaging over n_sub sub-bins per side (1: bin centres)
+        self.n_sub = max(1, int(n_sub))
+        self.sub_c = sub_bin_centres(edges, centres, self.n_ell, self.n_sub)
+        kinds, _ = self.configs()
+        cl = [(b, b, -1) for b in range(self.n_ell)] + [t[:3] for t in self.tris]
+        self.avg = averaging_lists(kinds, cl, self.n_sub, self.sub_c, widths)
+        self._Usub = None
 
     # ---- ell-configurations
     def configs(self):
@@ -264,7 +344,10 @@ class Oracle:
             raise ValueError("a needed k = ell/chi lies outside the k table")
 
     def spectra(self):
-        """3-D spectra and responses at every (configuration, chi) node."""
+        """3-D spectra and responses at every (configuration, chi) node (bin
+        averages when n_sub > 1)."""
+        if self._spectra is None and self.n_sub > 1:
+            self._spectra = self.spectra_avg()
         if self._spectra is None:
             kinds, ells = self.configs()
             nc = len(kinds)
@@ -274,6 +357,59 @@ class Oracle:
             self._check()
             self._spectra = (X, R)
         return self._spectra
+
+    def spectra_avg(self):
+        """X and R averaged over each configuration's averaging list: every
+        entry's ell-triple evaluated like a configuration of its own, then
+        the weighted sum."""
+        kinds, _ = self.configs()
+        ke, le, owner, we = [], [], [], []
+        for c, (L, W) in enumerate(self.avg):
+            for g, w in zip(L, W):
+                ke.append(kinds[c])
+                le.append((self.sub_c[g[0]], self.sub_c[g[1]], self.sub_c[g[2]]) if kinds[c] == 3
+                          else (self.sub_c[g[0]], 0.0, 0.0))
+                owner.append(c)
+                we.append(w)
+        ke = np.array(ke, np.int32)
+        le = np.array(le, np.float64)
+        Xe = np.zeros((len(ke), self.n_chi)); Re = np.zeros((len(ke), self.n_chi))
+        lib().or_clear_error()
+        lib().or_spectra_table(ct.byref(self.T), ct.c_int(len(ke)), _p(ke), _p(le), _p(Xe), _p(Re))
+        self._check()
+        X = np.zeros((len(kinds), self.n_chi)); R = np.zeros((len(kinds), self.n_chi))
+        for e, c in enumerate(owner):
+            X[c] += we[e] * Xe[e]
+            R[c] += we[e] * Re[e]
+        return X, R
+
+    def u_table_sub(self):
+        """u(m, l_s / chi_n) at every sub-bin centre."""
+        if self._Usub is None:
+            ell = np.array(self.sub_c, np.float64)
+            U = np.zeros((len(ell), self.n_chi, self.n_m))
+            lib().or_clear_error()
+            lib().or_tab_u(ct.byref(self.T), ct.c_int(len(ell)), _p(ell), _p(U))
+            self._check()
+            self._Usub = (ell, U)
+        return self._Usub
+
+    def cov1h_avg_pairs(self, pairs):
+        """One-halo covariance averaged over both rows' averaging lists."""
+        ell, U = self.u_table_sub()
+        off = np.zeros(len(self.avg) + 1, np.int32)
+        for c, (L, _) in enumerate(self.avg):
+            off[c + 1] = off[c] + len(L)
+        leg = np.ascontiguousarray(np.concatenate([L for L, _ in self.avg]), np.int32)
+        w = np.ascontiguousarray(np.concatenate([W for _, W in self.avg]), np.float64)
+        pairs = np.ascontiguousarray(pairs, np.int64)
+        out = np.zeros(len(pairs))
+        lib().or_cov1h_avg_pairs(ct.byref(self.T), _p(ell), _p(U), ct.c_double(self.omega),
+                                 _p(np.ascontiguousarray(self.rows["kind"], np.int32)),
+                                 _p(np.ascontiguousarray(self.rows["zbin"], np.int32)),
+                                 _p(np.ascontiguousarray(self.rows["cfg"], np.int32)), _p(off), _p(leg), _p(w),
+                                 ct.c_int64(len(pairs)), _p(pairs), _p(out))
+        return out
 
     def data_vector(self, rows=None):
         """(D, r): eq. nProjection of the halo-model spectra (data vector) and
@@ -329,6 +465,8 @@ class Oracle:
 
     # ---- covariance
     def cov1h_pairs(self, pairs):
+        if self.n_sub > 1:
+            return self.cov1h_avg_pairs(pairs)
         ell, U = self.u_table()
         pairs = np.ascontiguousarray(pairs, np.int64)
         out = np.zeros(len(pairs))
@@ -384,6 +522,8 @@ class Oracle:
         """The B.B, P.T and P.B in-survey terms (eqs. CovBB, Covpb) for the
         given (a, b) pairs of rows (default: the data-vector rows)."""
         rows = self.rows if rows is None else rows
+        if self.n_sub > 1:
+            raise ValueError("the in-survey B.B, P.T, P.B terms are not bin-averaged")
         ell, U = self.u_table()
         ps, nm, bf = self.ps_table(), self.nmodes(), self.bfull()
         pairs = np.ascontiguousarray(pairs, np.int64)
@@ -453,8 +593,12 @@ class Oracle:
         lb = np.ascontiguousarray(self.rows["lbin"][reps], np.int32)
         zb = np.ascontiguousarray(self.rows["zbin"][reps], np.int32)
         c1h = np.zeros((nc, nc))
-        lib().or_cov1h_canon(ct.byref(self.T), _p(ell), _p(U), ct.c_double(self.omega), ct.c_int(nc),
-                             _p(kind), _p(lb), _p(zb), _p(c1h))
+        if self.n_sub > 1:
+            ii, jj = np.tril_indices(nc)
+            c1h[ii, jj] = self.cov1h_avg_pairs(np.stack([reps[ii], reps[jj]], 1))
+        else:
+            lib().or_cov1h_canon(ct.byref(self.T), _p(ell), _p(U), ct.c_double(self.omega), ct.c_int(nc),
+                                 _p(kind), _p(lb), _p(zb), _p(c1h))
         _, r = self.data_vector()
         ps = self.ps_table()
         nm = self.nmodes()

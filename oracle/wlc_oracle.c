@@ -391,7 +391,31 @@ void or_cov_full(int n, const double *c1h_canon, int nc, const int *canon,
     }
 }
 
-/* One-halo values for all canonical row pairs (lower triangle), [nc][nc]. */
+/* Bin-averaged one-halo covariance (the average over the modes of each bin
+ * that the paper replaces by the bin centres, Sec. 3.2.2 and the discussion
+ * of Sec. 7): the one-halo term of eq. General1h averaged over the sub-bin
+ * entries of both rows,
+ *   sum_e sum_f w_e w_f C_1h(legs of entry e of row a, legs of entry f of row b),
+ * entries off[c] .. off[c+1]-1 of the row's configuration c, each with three
+ * legs leg[3 e + q] indexing ell_sub / U_sub and a weight w[e]. */
+void or_cov1h_avg_pairs(const or_tables *T, const double *ell_sub, const double *U_sub, double omega,
+                        const int *kind, const int *zbin, const int *cfg, const int *off, const int *leg,
+                        const double *w, int64_t n_pairs, const int64_t *pairs, double *out) {
+  double *mw = mass_weights(T);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t q = 0; q < n_pairs; ++q) {
+    int64_t a = pairs[2 * q], b = pairs[2 * q + 1];
+    int ca = cfg[a], cb = cfg[b];
+    double s = 0.0;
+    for (int e = off[ca]; e < off[ca + 1]; ++e)
+      for (int f = off[cb]; f < off[cb + 1]; ++f)
+        s += w[e] * w[f] * cov1h(T, ell_sub, U_sub, mw, omega, &kind[a], &leg[3 * e], &zbin[3 * a], &kind[b],
+                                 &leg[3 * f], &zbin[3 * b]);
+    out[q] = s;
+  }
+  free(mw);
+}
+
 /* --------------------------------------------------------------------
  * Projected one-halo trispectrum at four legs: the Limber projection of
  * eq. nProjection with n = 4 applied to I_4^0 of eq. ImunuHalos,
@@ -622,6 +646,44 @@ uint64_t or_lattice_modes(int64_t tlo, int64_t thi) {
       if (s > 0 && s >= tlo && s < thi) ++c;
     }
   return c;
+}
+
+/* Sum over the modes of a bin of |q|^(2 p) (for averages of a power of
+ * |q| over the bin's modes). */
+double or_lattice_mode_moment(int64_t tlo, int64_t thi, int p) {
+  int64_t R = (int64_t)sqrt((double)thi) + 2;
+  double acc = 0.0;
+  for (int64_t x = -R; x <= R; ++x)
+    for (int64_t y = -R; y <= R; ++y) {
+      int64_t s = x * x + y * y;
+      if (s > 0 && s >= tlo && s < thi) acc += pow((double)s, p);
+    }
+  return acc;
+}
+
+/* Over the ordered pairs (q1, q2) of a triangle bin: the pair count (return
+ * value) and, in *moment, the sum of (|q1|^2 |q2|^2 |q1 + q2|^2)^p. */
+double or_lattice_triangle_moment(int64_t tlo1, int64_t thi1, int64_t tlo2, int64_t thi2, int64_t tlo3,
+                                  int64_t thi3, int p, double *moment) {
+  int64_t R1 = (int64_t)sqrt((double)thi1) + 2, R2 = (int64_t)sqrt((double)thi2) + 2;
+  double count = 0.0, acc = 0.0;
+#pragma omp parallel for reduction(+ : count, acc) collapse(2) schedule(dynamic, 4)
+  for (int64_t x1 = -R1; x1 <= R1; ++x1)
+    for (int64_t y1 = -R1; y1 <= R1; ++y1) {
+      int64_t s1 = x1 * x1 + y1 * y1;
+      if (!(s1 > 0 && s1 >= tlo1 && s1 < thi1)) continue;
+      for (int64_t x2 = -R2; x2 <= R2; ++x2)
+        for (int64_t y2 = -R2; y2 <= R2; ++y2) {
+          int64_t s2 = x2 * x2 + y2 * y2;
+          if (!(s2 > 0 && s2 >= tlo2 && s2 < thi2)) continue;
+          int64_t x = x1 + x2, y = y1 + y2, s3 = x * x + y * y;
+          if (!(s3 > 0 && s3 >= tlo3 && s3 < thi3)) continue;
+          count += 1.0;
+          acc += pow((double)s1 * (double)s2 * (double)s3, p);
+        }
+    }
+  *moment = acc;
+  return count;
 }
 
 uint64_t or_lattice_triangles(int64_t tlo1, int64_t thi1, int64_t tlo2, int64_t thi2,
