@@ -93,6 +93,19 @@ typedef struct {
   double sigma_b2;    /* variance of the long background mode (super-sample)   */
   double k_max;       /* line-of-sight integrand vanishes above this k (Sec. 4.4) */
   double rho_mean;    /* comoving mean matter density, (M_sun/h)/(Mpc/h)^3     */
+  int32_t n_sub;      /* bin averaging: 0 or 1 evaluates every polyspectrum at the
+                         bin centres (the paper's approximation, Sec. 3.2.2 and
+                         App. B); 2..8 averages it over n_sub equal sub-bins per
+                         ell-bin: a power-spectrum bin over its sub-bins with
+                         weights proportional to the number of modes (ell), a
+                         triangle bin over the cells of sub-bin triples whose
+                         centres obey the strict triangle inequality, weighted
+                         by the continuum count of mode pairs in the cell
+                         (App. B), the polyspectra taken at the cell centres.
+                         The data vector, the responses and
+                         the one-halo and super-sample terms average; the
+                         Gaussian term keeps its form with the averaged power
+                         spectra.  Not combinable with WLC_FLAG_NGINS. */
 } wlc_config;
 
 /* Input tables, all DEVICE pointers to float64, row-major:
@@ -127,6 +140,7 @@ typedef struct {
   size_t ws_snr_bytes; /* device workspace needed by wlc_snr2                 */
   size_t ws_snr_structured_bytes; /* ... by wlc_snr2_structured (0: not available
                                      for this plan: SORTED tomography or n_z > 32) */
+  int64_t n_avg;       /* entries of the bin-averaging lists (n_cfg at n_sub <= 1) */
 } wlc_sizes;
 
 typedef struct wlc_plan_s *wlc_plan;
@@ -146,6 +160,15 @@ int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out);
  *                           redshift bins z1 z2 z3 (-1 where unused);
  *   distinct [n_data]       index of the row's distinct (sorted) row. */
 int wlc_plan_index(wlc_plan plan, int32_t *tri, int32_t *rows, int32_t *distinct);
+
+/* The plan's bin-averaging lists into HOST buffers (any may be NULL):
+ *   off [n_cfg + 1]    entries off[c] .. off[c+1]-1 belong to configuration c
+ *                      (ell-bins first, then triangles in data-vector order);
+ *   legs [n_avg][3]    sub-bin index of each leg (bin b, sub-bin s -> b n_sub
+ *                      + s; a P entry holds its leg twice, then -1);
+ *   ell [n_ell_used * max(1, n_sub)] sub-bin centres;
+ *   w [n_avg]          weights (sum 1 per configuration): see wlc_config.n_sub. */
+int wlc_plan_averaging(wlc_plan plan, int32_t *off, int32_t *legs, double *ell, double *w);
 
 /* Closed-form counts into HOST buffers (Sec. 3.2.2, App. B):
  *   n_modes [n_ell_used] = 2 l Delta_l f_sky;

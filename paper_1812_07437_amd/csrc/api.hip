@@ -52,7 +52,7 @@ constexpr int64_t K_ALIGN = 64;
 enum Buf {
   B_ROWR, B_ROWO, B_CFGT, B_CENT, B_NMODES, B_NTRI, B_THR, B_TRI, B_FLAGS,
   B_U, B_PK, B_NE, B_X, B_R, B_DR, B_RR, B_PS, B_G, B_GMAX, B_TS, B_SEXP,
-  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, B_SW, NBUF
+  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, B_SW, B_SOFF, B_SLEG, B_SWT, NBUF
 };
 
 // Columns per chi node of the configuration factor G: the mass nodes, and
@@ -82,14 +82,15 @@ static Layout run_layout(const Plan &p) {
   sz[B_ROWR] = p.rowR.size() * 4;
   sz[B_ROWO] = p.rowO.size() * 4;
   sz[B_CFGT] = (size_t)n_cfg * 16;
-  sz[B_CENT] = (size_t)p.n_ell_all * 8;
+  const size_t n_ls = (size_t)nl * p.n_sub;  // staged ell values: bin centres or sub-bins
+  sz[B_CENT] = n_ls * 8;
   sz[B_NMODES] = (size_t)nl * 8;
   sz[B_NTRI] = (size_t)std::max(1, p.n_tri) * 8;
   sz[B_THR] = p.lattice_thr.size() * 8;
   sz[B_TRI] = (size_t)std::max(1, p.n_tri) * 12;
   sz[B_FLAGS] = 64 * 4;
-  sz[B_U] = (size_t)nl * c.n_chi * c.n_m * 8;
-  sz[B_PK] = sz[B_NE] = (size_t)nl * c.n_chi * 8;
+  sz[B_U] = n_ls * c.n_chi * c.n_m * 8;
+  sz[B_PK] = sz[B_NE] = n_ls * c.n_chi * 8;
   sz[B_X] = sz[B_R] = (size_t)n_cfg * c.n_chi * 8;
   sz[B_DR] = sz[B_RR] = (size_t)p.n_R * 8;
   sz[B_PS] = (size_t)nl * c.n_z * c.n_z * 8;
@@ -114,6 +115,9 @@ static Layout run_layout(const Plan &p) {
     sz[B_T2] = (size_t)twoleg_rows(p) * twoleg_ld(p) * 8;
   }
   if (c.flags & WLC_FLAG_SSC_CHI) sz[B_SW] = (size_t)c.n_chi * 8;
+  sz[B_SOFF] = p.sub_off.size() * 4;
+  sz[B_SLEG] = p.sub_leg.size() * 4;
+  sz[B_SWT] = p.sub_w.size() * 8;
   Layout L{};
   size_t o = 0;
   for (int b = 0; b < NBUF; ++b) {
@@ -249,7 +253,10 @@ static int upload_index(const Plan &p, void *ws, const Layout &L, hipStream_t s)
       {B_ROWR, p.rowR.data(), p.rowR.size() * 4},
       {B_ROWO, p.rowO.data(), p.rowO.size() * 4},
       {B_CFGT, p.cfgT.data(), p.cfgT.size() * 4},
-      {B_CENT, p.centres.data(), p.centres.size() * 8},
+      {B_CENT, p.sub_centres.data(), p.sub_centres.size() * 8},
+      {B_SOFF, p.sub_off.data(), p.sub_off.size() * 4},
+      {B_SLEG, p.sub_leg.data(), p.sub_leg.size() * 4},
+      {B_SWT, p.sub_w.data(), p.sub_w.size() * 8},
       {B_NMODES, p.n_modes.data(), p.n_modes.size() * 8},
       {B_NTRI, p.n_tri_closed.data(), p.n_tri_closed.size() * 8},
       {B_THR, p.lattice_thr.data(), p.lattice_thr.size() * 8},
@@ -285,7 +292,7 @@ int validate_tables(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s
   const DevTables T = dev_tables(p, tb);
   int32_t *flags = at<int32_t>(ws, L, B_FLAGS);
   launch_fill_i32(flags, 64, 0, s);
-  launch_validate(T, at<double>(ws, L, B_CENT), p.n_ell, (p.cfg.flags & WLC_FLAG_SSC_CHI) ? theta_sky(p) : 0.0,
+  launch_validate(T, at<double>(ws, L, B_CENT), p.n_ell * p.n_sub, (p.cfg.flags & WLC_FLAG_SSC_CHI) ? theta_sky(p) : 0.0,
                   flags, s);
   int32_t hf[3] = {0, 0, 0};
   rc = hip_check(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s), "validation copy");
@@ -318,15 +325,16 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   int32_t *sexp = at<int32_t>(ws, L, B_SEXP);
 
   if (hooks) hooks->begin(WLC_PHASE_TABLES);
-  launch_stage(T, cent, p.n_ell, U, Pk, Ne, s);
-  launch_spectra(T, cfgT, n_cfg, U, Pk, Ne, cent, X, R, s);
+  const SubList sl{at<int32_t>(ws, L, B_SOFF), at<int32_t>(ws, L, B_SLEG), at<double>(ws, L, B_SWT)};
+  launch_stage(T, cent, p.n_ell * p.n_sub, U, Pk, Ne, s);
+  launch_spectra(T, cfgT, n_cfg, sl, U, Pk, Ne, cent, X, R, s);
   launch_project(T, rowR, cfgT, p.n_R, X, R, dR, rR, s);
   launch_ps(dR, Ps, p.n_ell, c.n_z, p.noise, s);
   const bool ssc_chi = (c.flags & WLC_FLAG_SSC_CHI) != 0;
   const int n_mg = g_cols(c);
   double *sw = ssc_chi ? at<double>(ws, L, B_SW) : nullptr;
   if (ssc_chi) launch_sigma_w2(T, theta_sky(p), sw, s);
-  launch_gfactor(T, cfgT, n_cfg, U, R, sw, std::sqrt(p.omega), n_mg, G, Gmax, s);
+  launch_gfactor(T, cfgT, n_cfg, sl, U, R, sw, std::sqrt(p.omega), n_mg, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
   if (c.flags & WLC_FLAG_NGINS) {
     // the projected one-halo trispectrum of two legs per triangle (the P.T
@@ -522,6 +530,19 @@ int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out) {
   out->ws_run_bytes = p.ws_run;
   out->ws_snr_bytes = p.ws_snr;
   out->ws_snr_structured_bytes = snr_structured_ws_bytes(p);
+  out->n_avg = (int64_t)p.sub_w.size();
+  return WLC_OK;
+}
+
+int wlc_plan_averaging(wlc_plan plan, int32_t *off, int32_t *legs, double *ell, double *w) {
+  if (!plan) return fail(WLC_EINVAL, "null plan");
+  const Plan &p = plan->p;
+  if (off) std::memcpy(off, p.sub_off.data(), p.sub_off.size() * 4);
+  if (legs)
+    for (size_t e = 0; e < p.sub_w.size(); ++e)
+      for (int a = 0; a < 3; ++a) legs[3 * e + a] = p.sub_leg[4 * e + a];
+  if (ell) std::memcpy(ell, p.sub_centres.data(), p.sub_centres.size() * 8);
+  if (w) std::memcpy(w, p.sub_w.data(), p.sub_w.size() * 8);
   return WLC_OK;
 }
 

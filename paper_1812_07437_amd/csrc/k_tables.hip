@@ -124,28 +124,24 @@ void launch_stage(const DevTables &T, const double *centres, int n_ell, double *
 }
 
 // ------------------------------------------------------------- 3-D spectra
-// One wavefront per (configuration, chi node): lanes stride over the mass
-// nodes, then a wavefront reduction of every mass integral.
+// One wavefront per (configuration, chi node): for each entry of the
+// configuration's averaging list (its bin centres, or its sub-bins), lanes
+// stride over the mass nodes, a wavefront reduction gives every mass
+// integral, and lane 0 adds the entry's weighted X and R.
 __device__ __forceinline__ double cosine3(double ki, double kj, double kl) {
   return (kl * kl - ki * ki - kj * kj) / (2.0 * ki * kj);
 }
 
-__global__ void k_spectra(DevTables T, const int32_t *cfgT, int n_cfg, const double *U, const double *Pk,
-                          const double *Ne, const double *centres, double *X, double *R) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-  if (item >= (int64_t)n_cfg * T.n_chi) return;
-  const int c = (int)(item / T.n_chi), n = (int)(item % T.n_chi);
-  const int kind = cfgT[4 * c];
-  const int l0 = cfgT[4 * c + 1], l1 = cfgT[4 * c + 2], l2 = cfgT[4 * c + 3];
+// X and R at one ell-triple (kind 3) or ell (kind 2) and chi node; valid on
+// lane 0.  l0, l1, l2 index the staged ell values.
+__device__ void spectrum_at(const DevTables &T, int kind, int l0, int l1, int l2, int n, const double *U,
+                            const double *Pk, const double *Ne, const double *centres, int lane, double &X,
+                            double &R) {
   const double chi = T.chi[n];
   double lmax = centres[l0];
   if (kind == 3) lmax = fmax(lmax, fmax(centres[l1], centres[l2]));
-  const size_t out = (size_t)c * T.n_chi + n;
-  if (lmax / chi > T.k_max) {
-    if (lane == 0) { X[out] = 0.0; R[out] = 0.0; }
-    return;
-  }
+  X = R = 0.0;
+  if (lmax / chi > T.k_max) return;
   const int nm = T.n_m_pts;
   const double inv_rho = 1.0 / T.rho;
   if (kind == 2) {
@@ -164,8 +160,8 @@ __global__ void k_spectra(DevTables T, const int32_t *cfgT, int n_cfg, const dou
     if (lane == 0) {
       const double P = Pk[(size_t)l0 * T.n_chi + n], ne = Ne[(size_t)l0 * T.n_chi + n];
       const double Rlin = 47.0 / 21.0 * P - ne * P / 3.0;
-      X[out] = I20 + I11 * I11 * P;
-      R[out] = I11 * I11 * Rlin + I21;
+      X = I20 + I11 * I11 * P;
+      R = I11 * I11 * Rlin + I21;
     }
     return;
   }
@@ -218,16 +214,37 @@ __global__ void k_spectra(DevTables T, const int32_t *cfgT, int n_cfg, const dou
       dil += 2.0 * F * P[i] * P[j] * (ne[i] + ne[j]);
     }
     const double I111 = I11[0] * I11[1] * I11[2];
-    X[out] = I30 + two_halo + I111 * Bpt;
-    R[out] = I111 * (433.0 / 126.0 * Bpt + 5.0 / 126.0 * Bg2 - dil / 3.0) + resp_cyc + I31;
+    X = I30 + two_halo + I111 * Bpt;
+    R = I111 * (433.0 / 126.0 * Bpt + 5.0 / 126.0 * Bg2 - dil / 3.0) + resp_cyc + I31;
   }
 }
 
-void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *Pk,
-                    const double *Ne, const double *centres, double *X, double *R, hipStream_t s) {
+__global__ void k_spectra(DevTables T, const int32_t *cfgT, int n_cfg, SubList sl, const double *U,
+                          const double *Pk, const double *Ne, const double *centres, double *X, double *R) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (item >= (int64_t)n_cfg * T.n_chi) return;
+  const int c = (int)(item / T.n_chi), n = (int)(item % T.n_chi);
+  const int kind = cfgT[4 * c];
+  double xs = 0.0, rs = 0.0;
+  for (int e = sl.off[c]; e < sl.off[c + 1]; ++e) {
+    double xe, re;
+    spectrum_at(T, kind, sl.leg[4 * e], sl.leg[4 * e + 1], sl.leg[4 * e + 2], n, U, Pk, Ne, centres, lane, xe,
+                re);
+    xs += sl.w[e] * xe;
+    rs += sl.w[e] * re;
+  }
+  if (lane == 0) {
+    X[item] = xs;
+    R[item] = rs;
+  }
+}
+
+void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const SubList &sl, const double *U,
+                    const double *Pk, const double *Ne, const double *centres, double *X, double *R, hipStream_t s) {
   const int64_t items = (int64_t)n_cfg * T.n_chi;
   const int g = (int)((items + 3) / 4);
-  hipLaunchKernelGGL(k_spectra, dim3(g), dim3(256), 0, s, T, cfgT, n_cfg, U, Pk, Ne, centres, X, R);
+  hipLaunchKernelGGL(k_spectra, dim3(g), dim3(256), 0, s, T, cfgT, n_cfg, sl, U, Pk, Ne, centres, X, R);
 }
 
 // ------------------------------------------------------------- projection
@@ -287,24 +304,30 @@ void launch_ps(const double *dR, double *Ps, int n_ell, int n_z, double noise, h
 // WLSSCflatskyLimber resolved along chi,
 //   sum_n w_n sigma_W^2(chi_n) chi_n^(2-2p) prod W R_cfg(chi_n) (same for b),
 // as G[cfg][n][n_m] = sqrt(Omega) chi_n sqrt(sigma_W^2(chi_n)) R[cfg][n].
-__global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, const double *U, const double *R,
-                          const double *sw, double sq_omega, int n_mg, double *G, double *Gmax) {
+__global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, SubList sl, const double *U,
+                          const double *R, const double *sw, double sq_omega, int n_mg, double *G, double *Gmax) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t item = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
   if (item >= (int64_t)n_cfg * T.n_chi) return;
   const int c = (int)(item / T.n_chi), n = (int)(item % T.n_chi);
   const int kind = cfgT[4 * c];
   const int nm = T.n_m_pts;
-  const double *U0 = U + ((size_t)cfgT[4 * c + 1] * T.n_chi + n) * nm;
-  const double *U1 = kind == 3 ? U + ((size_t)cfgT[4 * c + 2] * T.n_chi + n) * nm : U0;
-  const double *U2 = kind == 3 ? U + ((size_t)cfgT[4 * c + 3] * T.n_chi + n) * nm : nullptr;
   const double inv_rho = 1.0 / T.rho;
+  const int e0 = sl.off[c], e1 = sl.off[c + 1];
   double mx = 0.0;
   double *Gout = G + (size_t)item * n_mg;
   for (int mi = lane; mi < nm; mi += WAVE) {
     const double x = T.m[mi] * inv_rho;
-    double g = sqrt(T.w_m[mi] * T.n_m[mi]) * x * x * U0[mi] * U1[mi];
-    if (kind == 3) g *= x * U2[mi];
+    double g = 0.0;
+    // the average over the configuration's entries (one entry of weight 1
+    // at the bin centres)
+    for (int e = e0; e < e1; ++e) {
+      const double *U0 = U + ((size_t)sl.leg[4 * e] * T.n_chi + n) * nm;
+      const double *U1 = kind == 3 ? U + ((size_t)sl.leg[4 * e + 1] * T.n_chi + n) * nm : U0;
+      double ge = sqrt(T.w_m[mi] * T.n_m[mi]) * x * x * U0[mi] * U1[mi];
+      if (kind == 3) ge *= x * U[((size_t)sl.leg[4 * e + 2] * T.n_chi + n) * nm + mi];
+      g += sl.w[e] * ge;
+    }
     Gout[mi] = g;
     mx = fmax(mx, fabs(g));
   }
@@ -317,11 +340,12 @@ __global__ void k_gfactor(DevTables T, const int32_t *cfgT, int n_cfg, const dou
   if (lane == 0) Gmax[item] = mx;
 }
 
-void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *R,
-                    const double *sw, double sq_omega, int n_mg, double *G, double *Gmax, hipStream_t s) {
+void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const SubList &sl, const double *U,
+                    const double *R, const double *sw, double sq_omega, int n_mg, double *G, double *Gmax,
+                    hipStream_t s) {
   const int64_t items = (int64_t)n_cfg * T.n_chi;
-  hipLaunchKernelGGL(k_gfactor, dim3((int)((items + 3) / 4)), dim3(256), 0, s, T, cfgT, n_cfg, U, R, sw, sq_omega,
-                     n_mg, G, Gmax);
+  hipLaunchKernelGGL(k_gfactor, dim3((int)((items + 3) / 4)), dim3(256), 0, s, T, cfgT, n_cfg, sl, U, R, sw,
+                     sq_omega, n_mg, G, Gmax);
 }
 
 // Per distinct row: T[n] and the row exponent s = -e with

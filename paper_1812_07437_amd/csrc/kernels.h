@@ -10,19 +10,27 @@
 namespace wlc {
 
 // ---- tables and quadrature (k_tables.hip)
+// Averaging list of the ell-configurations (the bin centres, or the sub-bins
+// of bin averaging): entries off[c] .. off[c + 1] - 1 with legs leg[4 e + a]
+// (indices into the staged ell values) and weights w[e] summing to one.
+struct SubList {
+  const int32_t *off, *leg;
+  const double *w;
+};
 void launch_validate(const DevTables &T, const double *centres, int n_ell, double theta, int *flags, hipStream_t s);
 void launch_stage(const DevTables &T, const double *centres, int n_ell, double *U, double *Pk, double *Ne,
                   hipStream_t s);
-void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *Pk,
-                    const double *Ne, const double *centres, double *X, double *R, hipStream_t s);
+void launch_spectra(const DevTables &T, const int32_t *cfgT, int n_cfg, const SubList &sl, const double *U,
+                    const double *Pk, const double *Ne, const double *centres, double *X, double *R, hipStream_t s);
 void launch_project(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *X,
                     const double *R, double *dR, double *rR, hipStream_t s);
 void launch_ps(const double *dR, double *Ps, int n_ell, int n_z, double noise, hipStream_t s);
 // G [n_cfg][n_chi][n_mg]: n_mg = n_m, or n_m + 1 when sw != NULL, the last
 // column then holding sqrt(Omega) chi_n sqrt(sigma_W^2(chi_n)) R[cfg][n] (the
 // super-sample term resolved along chi as one more Gram column).
-void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const double *U, const double *R,
-                    const double *sw, double sq_omega, int n_mg, double *G, double *Gmax, hipStream_t s);
+void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const SubList &sl, const double *U,
+                    const double *R, const double *sw, double sq_omega, int n_mg, double *G, double *Gmax,
+                    hipStream_t s);
 void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *Gmax,
                     double *Ts, int32_t *sexp, hipStream_t s);
 // fmt: 0 = f64, 1 = bf16 (hi only), 2 = bf16 hi + lo, 3 = f32

@@ -27,6 +27,49 @@ int fail(int code, const std::string &msg) {
   return code;
 }
 
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+static void gauss_legendre(int n, double *x, double *w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Continuum number of ordered pairs (l1, l2) of 2-D modes with |l1| in
+// [a1, b1), |l2| in [a2, b2) and |l1 + l2| in [a3, b3), up to the constant
+// (Omega / (2 pi)^2)^2 2 pi (App. B: N_tri as the sum of the selection
+// function): int int l1 l2 dphi(l1, l2) dl1 dl2, where dphi is the measure
+// of the angles phi between the two modes with l1^2 + l2^2 + 2 l1 l2 cos
+// phi in [a3^2, b3^2), by Gauss-Legendre on 8 x 8 nodes.
+static double cell_count(double a1, double b1, double a2, double b2, double a3, double b3) {
+  double x[8], w[8];
+  gauss_legendre(8, x, w);
+  double s = 0.0;
+  for (int i = 0; i < 8; ++i) {
+    const double l1 = 0.5 * (a1 + b1) + 0.5 * (b1 - a1) * x[i], w1 = 0.5 * (b1 - a1) * w[i];
+    for (int j = 0; j < 8; ++j) {
+      const double l2 = 0.5 * (a2 + b2) + 0.5 * (b2 - a2) * x[j], w2 = 0.5 * (b2 - a2) * w[j];
+      const double clo = std::min(1.0, std::max(-1.0, (a3 * a3 - l1 * l1 - l2 * l2) / (2.0 * l1 * l2)));
+      const double chi = std::min(1.0, std::max(-1.0, (b3 * b3 - l1 * l1 - l2 * l2) / (2.0 * l1 * l2)));
+      s += w1 * w2 * l1 * l2 * 2.0 * (std::acos(clo) - std::acos(chi));
+    }
+  }
+  return s;
+}
+
 static inline int64_t rank_pair(int n, int i, int j) {  // i <= j
   return (int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i);
 }
@@ -44,6 +87,9 @@ int build_plan(const wlc_config &c, Plan &p) {
   if (c.tomo_mode != WLC_TOMO_PAPER && c.tomo_mode != WLC_TOMO_SORTED)
     return fail(WLC_EINVAL, "unknown tomo_mode");
   if (!prec_valid(c.precision)) return fail(WLC_EINVAL, "unknown precision");
+  if (c.n_sub < 0 || c.n_sub > 8) return fail(WLC_EINVAL, "n_sub must be in 0..8");
+  if (c.n_sub > 1 && (c.flags & WLC_FLAG_NGINS))
+    return fail(WLC_EINVAL, "bin averaging (n_sub > 1) does not cover the B.B, P.T and P.B terms");
   p.cfg = c;
   const int nz = c.n_z;
 
@@ -145,6 +191,59 @@ int build_plan(const wlc_config &c, Plan &p) {
   p.n_out = (int64_t)p.rowO.size() / 8;
   if (p.n_out > (int64_t)std::numeric_limits<int32_t>::max() / 2)
     return fail(WLC_EINVAL, "data vector too long");
+
+  // bin averaging: sub-bins of equal width; a power-spectrum bin averages
+  // over its sub-bins with weights proportional to their number of modes
+  // (2 l dl f_sky, Sec. 3.2.2), a triangle bin over the cells of sub-bin
+  // triples whose centres obey the strict triangle inequality, weighted by
+  // the continuum count of triangles in the cell (App. B)
+  const int S = c.n_sub > 1 ? c.n_sub : 1;
+  p.n_sub = S;
+  p.sub_centres.resize((size_t)nl * S);
+  for (int i = 0; i < nl; ++i)
+    for (int s = 0; s < S; ++s)
+      p.sub_centres[(size_t)i * S + s] = S == 1 ? p.centres[i] : p.edges[i] + (s + 0.5) * p.widths[i] / S;
+  p.sub_off.assign(p.cfgs.size() + 1, 0);
+  p.sub_leg.clear();
+  p.sub_w.clear();
+  for (size_t q = 0; q < p.cfgs.size(); ++q) {
+    const Config &cf = p.cfgs[q];
+    const size_t first = p.sub_w.size();
+    double wsum = 0.0;
+    if (S == 1) {
+      int32_t e[4] = {cf.leg[0], cf.leg[1], cf.leg[2], -1};
+      p.sub_leg.insert(p.sub_leg.end(), e, e + 4);
+      p.sub_w.push_back(1.0);
+    } else if (cf.kind == 2) {
+      for (int s = 0; s < S; ++s) {
+        const int32_t g = cf.leg[0] * S + s;
+        int32_t e[4] = {g, g, -1, -1};
+        p.sub_leg.insert(p.sub_leg.end(), e, e + 4);
+        p.sub_w.push_back(p.sub_centres[g]);
+        wsum += p.sub_centres[g];
+      }
+    } else {
+      for (int s1 = 0; s1 < S; ++s1)
+        for (int s2 = 0; s2 < S; ++s2)
+          for (int s3 = 0; s3 < S; ++s3) {
+            const int32_t g1 = cf.leg[0] * S + s1, g2 = cf.leg[1] * S + s2, g3 = cf.leg[2] * S + s3;
+            const double l1 = p.sub_centres[g1], l2 = p.sub_centres[g2], l3 = p.sub_centres[g3];
+            if (!(l1 < l2 + l3 && l2 < l1 + l3 && l3 < l1 + l2)) continue;
+            const double h1 = p.widths[cf.leg[0]] / S, h2 = p.widths[cf.leg[1]] / S, h3 = p.widths[cf.leg[2]] / S;
+            const double rho = cell_count(l1 - 0.5 * h1, l1 + 0.5 * h1, l2 - 0.5 * h2, l2 + 0.5 * h2,
+                                          l3 - 0.5 * h3, l3 + 0.5 * h3);
+            if (!(rho > 0.0)) continue;
+            int32_t e[4] = {g1, g2, g3, -1};
+            p.sub_leg.insert(p.sub_leg.end(), e, e + 4);
+            p.sub_w.push_back(rho);
+            wsum += rho;
+          }
+      if (p.sub_w.size() == first) return fail(WLC_EINVAL, "a binned triangle has no sub-bin triangle");
+    }
+    if (S > 1)
+      for (size_t e = first; e < p.sub_w.size(); ++e) p.sub_w[e] /= wsum;
+    p.sub_off[q + 1] = (int32_t)p.sub_w.size();
+  }
 
   // closed-form counts (Sec. 3.2.2, App. B)
   p.omega = 4.0 * M_PI * c.f_sky;

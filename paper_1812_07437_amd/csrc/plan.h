@@ -31,6 +31,14 @@ struct Plan {
   int64_t n_R = 0, n_out = 0, n_p = 0;
   std::vector<double> n_modes, n_tri_closed; // closed-form counts
   std::vector<int64_t> lattice_thr;         // ceil((e_b/l_f)^2), [n_ell_all + 1]
+  // bin averaging: n_sub equal sub-bins per used ell-bin; sub_centres
+  // [n_ell * n_sub] (the bin centres when n_sub = 1), and per configuration
+  // c the entries sub_off[c] .. sub_off[c + 1] - 1 of sub_leg [.][4] (the
+  // sub-bin index of each leg, -1 where unused) and sub_w (weights, sum 1)
+  int n_sub = 1;
+  std::vector<double> sub_centres;
+  std::vector<int32_t> sub_off, sub_leg;
+  std::vector<double> sub_w;
   double omega = 0.0;                       // 4 pi f_sky
   double noise = 0.0;                       // sigma_eps^2 / n_i
   // sizes

@@ -36,7 +36,8 @@ class wlc_config(ct.Structure):
                 ("n_m", ct.c_int32), ("tomo_mode", ct.c_int32), ("precision", ct.c_int32), ("flags", ct.c_int32),
                 ("ell_min", ct.c_double), ("ell_max", ct.c_double), ("ell_cut", ct.c_double),
                 ("f_sky", ct.c_double), ("sigma_eps", ct.c_double), ("n_gal_arcmin2", ct.c_double),
-                ("sigma_b2", ct.c_double), ("k_max", ct.c_double), ("rho_mean", ct.c_double)]
+                ("sigma_b2", ct.c_double), ("k_max", ct.c_double), ("rho_mean", ct.c_double),
+                ("n_sub", ct.c_int32)]
 
 
 class wlc_tables(ct.Structure):
@@ -48,7 +49,7 @@ class wlc_sizes(ct.Structure):
     _fields_ = [("n_data", ct.c_int64), ("n_distinct", ct.c_int64), ("n_p", ct.c_int64), ("n_tri", ct.c_int64),
                 ("n_cfg", ct.c_int64), ("n_ell_used", ct.c_int64), ("k_len", ct.c_int64),
                 ("c_elem_bytes", ct.c_size_t), ("ws_run_bytes", ct.c_size_t), ("ws_snr_bytes", ct.c_size_t),
-                ("ws_snr_structured_bytes", ct.c_size_t)]
+                ("ws_snr_structured_bytes", ct.c_size_t), ("n_avg", ct.c_int64)]
 
 
 def _load():
@@ -63,6 +64,7 @@ def _load():
     L.wlc_plan_sizes.argtypes = [vp, ct.POINTER(wlc_sizes)]
     L.wlc_plan_index.argtypes = [vp, vp, vp, vp]
     L.wlc_counts_closed.argtypes = [vp, vp, vp]
+    L.wlc_plan_averaging.argtypes = [vp, vp, vp, vp, vp]
     L.wlc_lattice_counts.argtypes = [vp, vp, vp, vp, vp]
     L.wlc_run.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp, vp, vp, vp, vp]
     L.wlc_sigma_w2.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp]
@@ -76,7 +78,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_counts_closed",
+EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_averaging",
+            "wlc_counts_closed",
             "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
@@ -128,6 +131,10 @@ def wlc_plan_index(plan, tri, rows, distinct):
     _check(lib.wlc_plan_index(plan, tri, rows, distinct))
 
 
+def wlc_plan_averaging(plan, off, legs, ell, w):
+    _check(lib.wlc_plan_averaging(plan, off, legs, ell, w))
+
+
 def wlc_counts_closed(plan, n_modes, n_tri):
     _check(lib.wlc_counts_closed(plan, n_modes, n_tri))
 
@@ -158,11 +165,12 @@ def wlc_snr2_structured(plan, ws_run, ws, stream):
 
 # ---------------------------------------------------------------- helpers
 def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False, ngins=False,
-                ssc_chi=False) -> wlc_config:
+                ssc_chi=False, n_sub=0) -> wlc_config:
     """wlc_config from a dict of scalars (n_z, n_ell, n_chi, n_k, n_m, ell_min,
     ell_max, f_sky, sigma_eps, n_gal_arcmin2, sigma_b2, k_max, rho_mean and
     optionally ell_cut); ngins adds the B.B, P.T and P.B terms, ssc_chi
-    resolves the super-sample term along the line of sight."""
+    resolves the super-sample term along the line of sight, n_sub > 1
+    averages every polyspectrum over n_sub sub-bins per ell-bin."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     flags = (WLC_FLAG_NOCHECK if nocheck else 0) | (WLC_FLAG_NGINS if ngins else 0) | \
         (WLC_FLAG_SSC_CHI if ssc_chi else 0)
@@ -172,7 +180,8 @@ def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False, ngins=
                       ell_min=float(cfg["ell_min"]), ell_max=float(cfg["ell_max"]),
                       ell_cut=float(cfg.get("ell_cut", 0.0) or 0.0), f_sky=float(cfg["f_sky"]),
                       sigma_eps=float(cfg["sigma_eps"]), n_gal_arcmin2=float(cfg["n_gal_arcmin2"]),
-                      sigma_b2=float(cfg["sigma_b2"]), k_max=float(cfg["k_max"]), rho_mean=float(cfg["rho_mean"]))
+                      sigma_b2=float(cfg["sigma_b2"]), k_max=float(cfg["k_max"]), rho_mean=float(cfg["rho_mean"]),
+                      n_sub=int(n_sub))
 
 
 def _ptr(t):
@@ -190,11 +199,11 @@ class Problem:
     u, n_m, optional b1, b2, n_tri) to float64 arrays (numpy or torch)."""
 
     def __init__(self, cfg: dict, arrays: dict, precision="fp64", tomo="paper", device="cuda:0",
-                 nocheck=False, ngins=False, ssc_chi=False):
+                 nocheck=False, ngins=False, ssc_chi=False, n_sub=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.config = make_config(cfg, precision, tomo, nocheck, ngins, ssc_chi)
+        self.config = make_config(cfg, precision, tomo, nocheck, ngins, ssc_chi, n_sub)
         self.plan = wlc_plan_create(self.config)
         self.sizes = wlc_plan_sizes(self.plan)
         self._tabs = {}

@@ -170,3 +170,41 @@ def test_chi_resolved_ssc_sizes():
         w.wlc_sigma_w2(plan, w.wlc_tables(), None, None)
     assert e.value.code == w.WLC_EINVAL
     w.wlc_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("preset,S", [("tiny", 1), ("tiny", 2), ("tiny", 3), ("mid", 2), ("large10", 3)])
+def test_averaging_lists_vs_oracle(preset, S):
+    """The plan's bin-averaging lists: the same entries (bit-exact legs) as
+    the oracle's, weights to 1e-13 (Gauss-Legendre nodes computed
+    independently on both sides)."""
+    t = dict(synth.PRESETS[preset]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 1e11
+    plan = w.wlc_plan_create(w.make_config(t, "fp64", n_sub=S))
+    s = w.wlc_plan_sizes(plan)
+    off = np.zeros(s.n_cfg + 1, np.int32)
+    legs = np.zeros((s.n_avg, 3), np.int32)
+    ell = np.zeros(s.n_ell_used * S, np.float64)
+    wt = np.zeros(s.n_avg, np.float64)
+    w.wlc_plan_averaging(plan, *(a.ctypes.data_as(ct.c_void_p) for a in (off, legs, ell, wt)))
+    w.wlc_plan_destroy(plan)
+    edges, centres, widths = oracle.ell_bins(t["ell_min"], t["ell_max"], t["n_ell"])
+    sub = oracle.sub_bin_centres(edges, centres, t["n_ell"], S)
+    tris = oracle.triangles(centres)
+    cl = [(b, b, -1) for b in range(t["n_ell"])] + [q[:3] for q in tris]
+    ref = oracle.averaging_lists([2] * t["n_ell"] + [3] * len(tris), cl, S, sub, widths)
+    assert np.allclose(ell, sub, rtol=1e-15, atol=0)
+    assert off[-1] == s.n_avg == sum(len(W) for _, W in ref)
+    for c, (L, W) in enumerate(ref):
+        mine = legs[off[c]:off[c + 1]]
+        if c < t["n_ell"]:
+            assert np.array_equal(mine[:, :2], L[:, :2]) and np.all(mine[:, 2] == -1)
+        else:
+            assert np.array_equal(mine, L)
+        assert np.allclose(wt[off[c]:off[c + 1]], W, rtol=1e-13, atol=0)
+
+
+def test_averaging_arguments():
+    t = dict(synth.PRESETS["tiny"]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 1e11
+    for bad in (dict(n_sub=9), dict(n_sub=-1), dict(n_sub=2, ngins=True)):
+        with pytest.raises(w.WlcError) as e:
+            w.wlc_plan_create(w.make_config(t, "fp64", **bad))
+        assert e.value.code == w.WLC_EINVAL
