@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--chi-steps", type=int, default=1,
                     help="steps of the FP64 path with the one-halo term factorised along chi (0: skip)")
+    ap.add_argument("--n-sub", type=int, default=3,
+                    help="sub-bins per side of the bin-averaged leg (<= 1 skips it)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=12,
@@ -349,6 +351,21 @@ def main():
         del ps
         torch.cuda.empty_cache()
 
+    # the FP64 step with every polyspectrum averaged over 3 x 3 sub-bins per
+    # bin (the average the paper replaces by the bin centres)
+    subbin = None
+    if args.chi_steps > 0 and args.n_sub > 1:
+        log("fp64 chi path with bin averaging (n_sub=%d)" % args.n_sub)
+        pb = wl.Problem(cfg, t.arrays(), precision="fp64_chi", device="cuda:0", n_sub=args.n_sub)
+        dtb, phb, snrb, _ = timed_steps(pb, args.chi_steps, 1, torch, wl, structured=True)
+        ref_snr = fp64["snr2"] if fp64 else snr_mixed
+        subbin = dict(n_sub=args.n_sub, n_avg=int(pb.sizes.n_avg), ms_per_step=dtb / args.chi_steps * 1e3,
+                      phases_ms=phb, snr2=snrb[-1], snr2_bin_centres=ref_snr)
+        log("fp64 chi + bin averaging (structured S/N): %.1f ms/step  phases %s  (S/N)^2 %.6e (centres: %.6e)" % (
+            subbin["ms_per_step"], {k: round(v, 2) for k, v in phb.items()}, snrb[-1], ref_snr))
+        del pb
+        torch.cuda.empty_cache()
+
     # roofline of the dominant kernel of the step: the one-halo Gram (one
     # launch per step) or the Cholesky block update (many launches per step,
     # timed one by one with HIP events on the run's stream)
@@ -412,6 +429,7 @@ def main():
         "fp64_chi_path": chi,
         "fp64_chi_ngins_path": ngins,
         "fp64_chi_ssc_chi_path": sscc,
+        "fp64_chi_subbin_path": subbin,
         "serving": srv,
     }
     print(json.dumps(out), flush=True)
