@@ -636,6 +636,38 @@ class Oracle:
             raise MemoryError("oracle S/N allocation failed")
         return out.value
 
+    @staticmethod
+    def chol_y(C, d):
+        """y = L^-1 d with C = L L^T (the forward substitution of eq. SNprim)."""
+        C = np.ascontiguousarray(C, np.float64)
+        d = np.ascontiguousarray(d, np.float64)
+        y = np.zeros(len(d))
+        rc = lib().or_chol_y(ct.c_int(len(d)), _p(C), _p(d), _p(y))
+        if rc == -1:
+            raise np.linalg.LinAlgError("covariance is not positive definite")
+        if rc != 0:
+            raise MemoryError("oracle allocation failed")
+        return y
+
+    def lmax_order(self):
+        """Data-vector rows ordered by the largest ell-bin among their legs
+        (stable), and the number of rows whose largest bin is <= b for each
+        bin b.  The leading rows up to bin b are the data vector cut at an
+        ell_max between bins b and b + 1 (eq. eq:SN)."""
+        top = np.where(self.rows["kind"] == 2, self.rows["lbin"][:, 0], np.max(self.rows["lbin"], axis=1))
+        order = np.argsort(top, kind="stable")
+        ends = np.array([np.count_nonzero(top <= b) for b in range(self.n_ell)], np.int64)
+        return order, ends
+
+    def snr2_lmax(self, C, d):
+        """(S/N)^2 of the data vector cut at every ell_max (eq. eq:SN): the
+        covariance of a cut vector is a principal submatrix of C, so with the
+        rows in lmax_order one Cholesky gives all cuts as prefix sums of y^2."""
+        order, ends = self.lmax_order()
+        y = self.chol_y(np.asarray(C)[np.ix_(order, order)], np.asarray(d)[order])
+        cs = np.cumsum(y * y)
+        return cs[ends - 1]
+
     def run(self, ntri=None, ngins=False, ssc="rank1"):
         d, r = self.data_vector()
         C = self.covariance(ntri, ngins, ssc)

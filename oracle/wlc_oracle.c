@@ -598,9 +598,9 @@ void or_ssc_chi_pairs(const or_tables *T, const double *sw, const double *R, con
 /* --------------------------------------------------------------------
  * Signal-to-noise, eq. SNprim (Sec. 5): (S/N)^2 = D^T C^{-1} D, through the
  * Cholesky-Banachiewicz factorisation C = L L^T (row by row) and forward
- * substitution y = L^{-1} D, (S/N)^2 = y^T y.  Returns -1 if C is not
- * positive definite. */
-int or_snr2(int n, const double *C, const double *D, double *snr2) {
+ * substitution y = L^{-1} D, (S/N)^2 = y^T y.  or_chol_y returns y; both
+ * return -1 if C is not positive definite. */
+int or_chol_y(int n, const double *C, const double *D, double *y) {
   double *L = (double *)calloc((size_t)n * n, sizeof(double));
   if (!L) return -2;
   for (int i = 0; i < n; ++i) {
@@ -617,18 +617,25 @@ int or_snr2(int n, const double *C, const double *D, double *snr2) {
       }
     }
   }
-  double acc = 0.0;
-  double *y = (double *)malloc(sizeof(double) * (size_t)n);
   for (int i = 0; i < n; ++i) {
     double s = D[i];
     for (int q = 0; q < i; ++q) s -= L[(size_t)i * n + q] * y[q];
     y[i] = s / L[(size_t)i * n + i];
-    acc += y[i] * y[i];
   }
-  free(y);
   free(L);
-  *snr2 = acc;
   return 0;
+}
+
+int or_snr2(int n, const double *C, const double *D, double *snr2) {
+  double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!y) return -2;
+  int rc = or_chol_y(n, C, D, y);
+  double acc = 0.0;
+  if (rc == 0)
+    for (int i = 0; i < n; ++i) acc += y[i] * y[i];
+  free(y);
+  *snr2 = acc;
+  return rc;
 }
 
 /* --------------------------------------------------------------------

@@ -509,3 +509,22 @@ def test_bispectrum_symmetric_under_leg_permutation():
         for X, R in vals[1:]:
             assert X == pytest.approx(X0, rel=1e-13)
             assert R == pytest.approx(R0, rel=1e-13)
+
+
+@pytest.mark.parametrize("preset", ["tiny", "mid"])
+def test_snr_lmax_curve_matches_cut_vectors(preset):
+    """(S/N)^2(ell_max) from one Cholesky in ell_max order equals, at every
+    cut, the S/N of a separately planned data vector cut at that ell_max
+    (its own enumeration, covariance and Cholesky)."""
+    t = synth.make_tables(preset)
+    o = oracle.Oracle(t)
+    ref = o.run()
+    curve = o.snr2_lmax(ref["C"], ref["d"])
+    assert abs(curve[-1] - ref["snr2"]) <= 1e-12 * ref["snr2"]
+    assert np.all(np.diff(curve) > 0)
+    c = o.centres
+    for b in range(o.n_ell - 1):
+        tb = synth.make_tables(preset, ell_cut=0.5 * (c[b] + c[b + 1]))
+        ob = oracle.Oracle(tb)
+        assert ob.n_ell == b + 1
+        assert abs(curve[b] - ob.run()["snr2"]) <= 1e-10 * curve[b]
