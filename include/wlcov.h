@@ -228,6 +228,17 @@ int wlc_sigma_w2(wlc_plan plan, const wlc_tables *tables, double *sw, void *stre
 int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
              double *snr2_host, void *stream);
 
+/* The cumulative (S/N)^2(ell_max) of eq. eq:SN: into snr2_host[n_ell_used]
+ * (HOST), entry b is d^T C^-1 d over the rows whose legs all lie in ell-bins
+ * 0..b, i.e. the data vector cut at an ell_max between bins b and b + 1; the
+ * last entry is the full (S/N)^2.  The covariance of a cut vector is a
+ * principal submatrix of C, so the rows are taken in ell_max order (stable
+ * by their largest bin) and one bordered FP64 Cholesky gives every cut as a
+ * prefix sum of y^2, y = L^-1 d.  Arguments, workspace (ws_snr_bytes) and
+ * errors as wlc_snr2; synchronises the stream. */
+int wlc_snr2_lmax(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
+                  double *snr2_host, void *stream);
+
 /* The same (S/N)^2 through the distinct rows, for PAPER tomography.
  * With C = C_G + E M E^T (C_G the Gaussian term, block-diagonal over
  * ell-configurations; E the map from data-vector rows to their distinct

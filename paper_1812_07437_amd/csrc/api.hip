@@ -134,7 +134,10 @@ size_t run_ws_bytes(const Plan &p) { return run_layout(p).total; }
 
 size_t snr_ws_bytes(const Plan &p) {
   const int64_t n = p.n_out, ld = snr_ld(n);
-  return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(chol_scratch_bytes(n), 256) + 256 + 256;
+  // bordered matrix, Cholesky scratch, flag, result; then the ell_max order,
+  // its group ends, group sums and the curve (wlc_snr2_lmax)
+  return align_up((size_t)(n + 1) * ld * 8, 256) + align_up(chol_scratch_bytes(n), 256) + 256 + 256 +
+         align_up((size_t)n * 4, 256) + 3 * align_up((size_t)p.n_ell * 8, 256);
 }
 
 size_t snr_structured_ws_bytes(const Plan &p) {
@@ -404,7 +407,7 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
 }
 
 int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const double *d, void *ws, hipStream_t s,
-                PhaseHooks *hooks, KernelProbe *probe, int32_t **flag_dev, double **out_dev) {
+                PhaseHooks *hooks, KernelProbe *probe, int32_t **flag_dev, double **out_dev, bool lmax) {
   const int64_t n = p.n_out, ld = snr_ld(n);
   char *base = static_cast<char *>(ws);
   double *Wm = reinterpret_cast<double *>(base);
@@ -414,16 +417,34 @@ int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const dou
   int32_t *flag = reinterpret_cast<int32_t *>(base + o);
   o += 256;
   double *out = reinterpret_cast<double *>(base + o);
+  o += 256;
+  int32_t *perm = reinterpret_cast<int32_t *>(base + o);
+  o += align_up((size_t)n * 4, 256);
+  int32_t *ends = reinterpret_cast<int32_t *>(base + o);
+  o += align_up((size_t)p.n_ell * 8, 256);
+  double *part = reinterpret_cast<double *>(base + o);
+  o += align_up((size_t)p.n_ell * 8, 256);
+  double *curve = reinterpret_cast<double *>(base + o);
+  if (lmax) {
+    int rc = hip_check(hipMemcpyAsync(perm, p.lmax_perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "perm upload");
+    if (!rc)
+      rc = hip_check(hipMemcpyAsync(ends, p.lmax_ends.data(), (size_t)p.n_ell * 4, hipMemcpyHostToDevice, s),
+                     "ends upload");
+    if (rc) return rc;
+  }
   if (hooks) hooks->begin(WLC_PHASE_SNR_PREP);
   launch_fill_i32(flag, 1, 0, s);
-  launch_chol_prep(C, !prec_f64(p.cfg.precision), row_exp2, d, n, ld, Wm, s);
+  launch_chol_prep(C, !prec_f64(p.cfg.precision), row_exp2, d, n, ld, Wm, s, lmax ? perm : nullptr);
   if (hooks) hooks->end(WLC_PHASE_SNR_PREP);
   if (hooks) hooks->begin(WLC_PHASE_CHOL);
   chol_factor(Wm, n, ld, scratch, flag, s, probe);
-  launch_sumsq_row(Wm, n, ld, out, s);
+  if (lmax)
+    launch_sumsq_groups(Wm, n, ld, ends, p.n_ell, part, curve, s);
+  else
+    launch_sumsq_row(Wm, n, ld, out, s);
   if (hooks) hooks->end(WLC_PHASE_CHOL);
   *flag_dev = flag;
-  *out_dev = out;
+  *out_dev = lmax ? curve : out;
   return hip_check(hipGetLastError(), "snr launch");
 }
 
@@ -638,6 +659,28 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
   if (rc) return rc;
   if (h.flag) return fail(WLC_ENOTPD, "covariance is not positive definite");
   *snr2_host = h.v;
+  return WLC_OK;
+}
+
+int wlc_snr2_lmax(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
+                  double *snr2_host, void *stream) {
+  if (!plan || !C || !row_exp2 || !d || !ws || !snr2_host) return fail(WLC_EINVAL, "null argument");
+  if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "workspace must be 256-byte aligned");
+  const Plan &p = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  plan->recorded[WLC_PHASE_SNR_PREP] = plan->recorded[WLC_PHASE_CHOL] = false;
+  PlanTimer tm(plan, s);
+  const bool timed = plan->timing && plan->events_ready;
+  int32_t *flag = nullptr;
+  double *out = nullptr;
+  int rc = snr_enqueue(p, C, row_exp2, d, ws, s, timed ? &tm : nullptr, nullptr, &flag, &out, true);
+  if (rc) return rc;
+  int32_t hflag = 0;
+  rc = hip_check(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "snr copy");
+  if (!rc) rc = hip_check(hipMemcpyAsync(snr2_host, out, (size_t)p.n_ell * 8, hipMemcpyDeviceToHost, s), "snr copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "snr sync");
+  if (rc) return rc;
+  if (hflag) return fail(WLC_ENOTPD, "covariance is not positive definite");
   return WLC_OK;
 }
 

@@ -32,8 +32,10 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
 
 // Enqueue the S/N factorisation (no synchronisation).  On completion
 // *flag_dev != 0 marks a non-positive pivot and *out_dev holds (S/N)^2.
+// With lmax, the rows are taken in ell_max order and *out_dev holds the
+// (S/N)^2 of every ell_max cut, one per used ell-bin (wlc_snr2_lmax).
 int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const double *d, void *ws, hipStream_t s,
-                PhaseHooks *hooks, KernelProbe *probe, int32_t **flag_dev, double **out_dev);
+                PhaseHooks *hooks, KernelProbe *probe, int32_t **flag_dev, double **out_dev, bool lmax = false);
 
 // The same (S/N)^2 through the distinct rows, from the run workspace of a
 // completed wlc_run (PAPER tomography only): the bordered Cholesky of

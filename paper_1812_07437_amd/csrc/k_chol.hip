@@ -26,24 +26,29 @@ constexpr int64_t PART_ROWS = 524288;  // split-k scratch: slices x rows of 256 
 // Lower triangle of M from the scaled covariance (f32 or f64) and d.
 template <typename InT>
 __global__ void k_chol_prep(const InT *__restrict__ C, const int32_t *__restrict__ t, const double *__restrict__ d,
-                            int64_t n, int64_t ld, int64_t row_off, double *__restrict__ Wm) {
+                            const int32_t *__restrict__ perm, int64_t n, int64_t ld, int64_t row_off,
+                            double *__restrict__ Wm) {
   const int64_t i = row_off + blockIdx.y;  // row of M, 0..n
   if (i > n) return;
+  const int64_t pi = perm && i < n ? perm[i] : i;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= i && j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
-    Wm[i * ld + j] = i < n ? (double)C[i * n + j] : ldexp(d[j], t[j]);
+    const int64_t pj = perm ? perm[j] : j;
+    Wm[i * ld + j] = i < n ? (double)C[pi * n + pj] : ldexp(d[pj], t[pj]);
   }
 }
 
 void launch_chol_prep(const void *C, int c_f32, const int32_t *row_exp2, const double *d, int64_t n, int64_t ld,
-                      double *Wm, hipStream_t s) {
+                      double *Wm, hipStream_t s, const int32_t *perm) {
   for (int64_t r0 = 0; r0 <= n; r0 += 65535) {
     const int64_t rows = std::min<int64_t>(65535, n + 1 - r0);
     const dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 512), (unsigned)rows);
     if (c_f32)
-      hipLaunchKernelGGL(k_chol_prep<float>, grid, dim3(256), 0, s, (const float *)C, row_exp2, d, n, ld, r0, Wm);
+      hipLaunchKernelGGL(k_chol_prep<float>, grid, dim3(256), 0, s, (const float *)C, row_exp2, d, perm, n, ld, r0,
+                         Wm);
     else
-      hipLaunchKernelGGL(k_chol_prep<double>, grid, dim3(256), 0, s, (const double *)C, row_exp2, d, n, ld, r0, Wm);
+      hipLaunchKernelGGL(k_chol_prep<double>, grid, dim3(256), 0, s, (const double *)C, row_exp2, d, perm, n, ld,
+                         r0, Wm);
   }
 }
 
@@ -258,6 +263,41 @@ __global__ void k_sumsq_row(const double *__restrict__ Wm, int64_t n, int64_t ld
 
 void launch_sumsq_row(const double *Wm, int64_t n, int64_t ld, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_sumsq_row, dim3(1), dim3(256), 0, s, Wm, n, ld, out);
+}
+
+// Prefix sums of y^2 (the last row of the bordered factor) at the group ends
+// ends[0] <= ... <= ends[ng-1] = n: one block sums each group, then one
+// thread accumulates the groups in order.
+__global__ void k_sumsq_groups(const double *__restrict__ Wm, int64_t n, int64_t ld, const int32_t *__restrict__ ends,
+                               double *__restrict__ part) {
+  __shared__ double red[256];
+  const int g = blockIdx.x;
+  const int64_t lo = g == 0 ? 0 : ends[g - 1], hi = ends[g];
+  const double *y = Wm + n * ld;
+  double s = 0.0;
+  for (int64_t j = lo + threadIdx.x; j < hi; j += 256) s += y[j] * y[j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[g] = red[0];
+}
+
+__global__ void k_prefix(const double *__restrict__ part, int ng, double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    s += part[g];
+    out[g] = s;
+  }
+}
+
+void launch_sumsq_groups(const double *Wm, int64_t n, int64_t ld, const int32_t *ends, int ng, double *part,
+                         double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq_groups, dim3((unsigned)ng), dim3(256), 0, s, Wm, n, ld, ends, part);
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(64), 0, s, part, ng, out);
 }
 
 }  // namespace wlc

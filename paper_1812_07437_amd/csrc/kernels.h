@@ -92,8 +92,9 @@ void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hi
 void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s);
 
 // ---- signal-to-noise (k_chol.hip)
+// perm (optional): row/column a of the bordered matrix is row perm[a] of C
 void launch_chol_prep(const void *C, int c_f32, const int32_t *row_exp2, const double *d, int64_t n, int64_t ld,
-                      double *Wm, hipStream_t s);
+                      double *Wm, hipStream_t s, const int32_t *perm = nullptr);
 // Optional per-launch timing of the trailing-update kernel: event pairs are
 // recorded around each launch while count < cap; flops accumulates the
 // algorithmic flops of every launch.
@@ -112,6 +113,10 @@ int64_t chol_part_rows(int64_t n);
 void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1,
                     double *part, int64_t part_rows, hipStream_t s, KernelProbe *probe = nullptr);
 void launch_sumsq_row(const double *Wm, int64_t n, int64_t ld, double *out, hipStream_t s);
+// out[g] = sum of y_j^2 over j < ends[g] (y: the last row of the bordered
+// factor); part: ng doubles of scratch
+void launch_sumsq_groups(const double *Wm, int64_t n, int64_t ld, const int32_t *ends, int ng, double *part,
+                         double *out, hipStream_t s);
 
 // ---- S/N through the distinct rows (k_woodbury.hip)
 // Distinct rows are grouped by configuration: nl power-spectrum blocks of sp

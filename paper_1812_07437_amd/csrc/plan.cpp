@@ -192,6 +192,23 @@ int build_plan(const wlc_config &c, Plan &p) {
   if (p.n_out > (int64_t)std::numeric_limits<int32_t>::max() / 2)
     return fail(WLC_EINVAL, "data vector too long");
 
+  // ell_max order (eq. eq:SN): the data vector cut at an ell_max between
+  // bins b and b + 1 is the set of rows whose legs all lie in bins <= b, so
+  // with rows sorted by their largest bin every cut is a leading block
+  {
+    std::vector<int32_t> top((size_t)p.n_out);
+    for (int64_t a = 0; a < p.n_out; ++a) {
+      const int32_t *r = &p.rowO[8 * a];
+      top[a] = std::max(r[5], std::max(r[6], r[7]));
+    }
+    p.lmax_perm.resize((size_t)p.n_out);
+    for (int64_t a = 0; a < p.n_out; ++a) p.lmax_perm[a] = (int32_t)a;
+    std::stable_sort(p.lmax_perm.begin(), p.lmax_perm.end(), [&](int32_t x, int32_t y) { return top[x] < top[y]; });
+    p.lmax_ends.assign(nl, 0);
+    for (int64_t a = 0; a < p.n_out; ++a)
+      for (int b = top[a]; b < nl; ++b) ++p.lmax_ends[b];
+  }
+
   // bin averaging: sub-bins of equal width; a power-spectrum bin averages
   // over its sub-bins with weights proportional to their number of modes
   // (2 l dl f_sky, Sec. 3.2.2), a triangle bin over the cells of sub-bin

@@ -39,6 +39,10 @@ struct Plan {
   std::vector<double> sub_centres;
   std::vector<int32_t> sub_off, sub_leg;
   std::vector<double> sub_w;
+  // rows in ell_max order (stable by the largest ell-bin of their legs) and,
+  // per used bin b, the number of rows whose largest bin is <= b
+  std::vector<int32_t> lmax_perm;
+  std::vector<int32_t> lmax_ends;
   double omega = 0.0;                       // 4 pi f_sky
   double noise = 0.0;                       // sigma_eps^2 / n_i
   // sizes

@@ -70,6 +70,7 @@ def _load():
     L.wlc_sigma_w2.argtypes = [vp, ct.POINTER(wlc_tables), vp, vp]
     L.wlc_snr2.argtypes = [vp, vp, vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_snr2_structured.argtypes = [vp, vp, vp, ct.POINTER(ct.c_double), vp]
+    L.wlc_snr2_lmax.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
     L.wlc_plan_timings.argtypes = [vp, vp]
     L.wlc_plan_kernel_stats.argtypes = [vp, vp, vp, vp, vp]
@@ -80,7 +81,7 @@ lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_averaging",
             "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_lmax", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
@@ -155,6 +156,13 @@ def wlc_snr2(plan, C, row_exp2, d, ws, stream):
     out = ct.c_double()
     _check(lib.wlc_snr2(plan, C, row_exp2, d, ws, ct.byref(out), stream))
     return out.value
+
+
+def wlc_snr2_lmax(plan, C, row_exp2, d, ws, stream, n_ell):
+    import numpy as np
+    out = np.zeros(int(n_ell), np.float64)
+    _check(lib.wlc_snr2_lmax(plan, C, row_exp2, d, ws, out.ctypes.data_as(ct.c_void_p), stream))
+    return out
 
 
 def wlc_snr2_structured(plan, ws_run, ws, stream):
@@ -250,6 +258,13 @@ class Problem:
             self.ws_snr = self.torch.empty(int(self.sizes.ws_snr_bytes), dtype=self.torch.uint8, device=self.device)
         return wlc_snr2(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(self.ws_snr),
                         _stream_handle(stream))
+
+    def snr2_lmax(self, stream=None):
+        """(S/N)^2 of the data vector cut after each ell-bin (numpy array)."""
+        if self.ws_snr is None:
+            self.ws_snr = self.torch.empty(int(self.sizes.ws_snr_bytes), dtype=self.torch.uint8, device=self.device)
+        return wlc_snr2_lmax(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(self.ws_snr),
+                             _stream_handle(stream), self.sizes.n_ell_used)
 
     def snr2_structured(self, stream=None):
         """(S/N)^2 through the distinct rows, from this problem's last run."""

@@ -175,3 +175,20 @@ def test_large10_ssc_chi_sampled(wl, ref):
     pc.close()
     del pc
     torch.cuda.empty_cache()
+
+
+def test_large10_snr2_lmax(wl, ref):
+    """The ell_max curve at full size (bf16x3 covariance, FP64 Cholesky):
+    increasing, and its last entry is the (S/N)^2 of wlc_snr2."""
+    t = ref["t"]
+    _say("case large10 bf16x3 snr2_lmax")
+    pm = wl.Problem(t.cfg, t.arrays(), precision="bf16x3")
+    pm.run()
+    snr = pm.snr2()
+    curve = pm.snr2_lmax()
+    _say("  curve %s" % np.array2string(curve, precision=4))
+    assert len(curve) == 15 and np.all(np.diff(curve) > 0)
+    assert abs(curve[-1] - snr) / snr < 1e-6  # the same C factored in another row order
+    pm.close()
+    del pm
+    torch.cuda.empty_cache()

@@ -251,3 +251,20 @@ def test_ngins_full_parity(wl, preset, tomo, precision):
     with pytest.raises(wl.WlcError):
         prob.snr2_structured()
     prob.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp64_chi", 1e-10), ("bf16x3", 1e-4)])
+@pytest.mark.parametrize("preset,tomo", [("tiny", "paper"), ("tiny", "sorted"), ("mid", "paper")])
+def test_snr2_lmax_curve(wl, preset, tomo, precision, tol):
+    """(S/N)^2 at every ell_max cut from one Cholesky in ell_max order,
+    against the oracle's curve (itself pinned to separately planned cut
+    vectors)."""
+    _say("case snr2_lmax %s %s %s" % (precision, preset, tomo))
+    t, o, ref = _oracle_full(preset, tomo)
+    want = o.snr2_lmax(ref["C"], ref["d"])
+    prob, snr2 = _run(wl, t, precision, tomo)
+    got = prob.snr2_lmax()
+    assert got.shape == want.shape
+    assert np.max(np.abs(got - want) / want) < tol
+    assert abs(got[-1] - snr2) / snr2 < (1e-12 if precision != "bf16x3" else 1e-6)
+    prob.close()
