@@ -668,6 +668,46 @@ class Oracle:
         cs = np.cumsum(y * y)
         return cs[ends - 1]
 
+    @staticmethod
+    def pca(C, d, vectors=True):
+        """Principal components of the covariance (Sec. 6): C = sum_a lambda_a
+        S_a S_a^T (eq. SNPCA), the new observables D^_a = S_a . D (eq. NewObs)
+        and their (S/N)^2_a = D^_a^2 / lambda_a (eq. SNperEign).  Returns the
+        eigenvalues ascending, the (S/N)^2 of each mode in that order, the
+        cumulative (S/N)^2 over the modes taken by decreasing (S/N)^2 (eq.
+        CumulSN in the order of the paper's second PCA figure) and, with
+        vectors, S with row a the unit eigenvector of mode a (sign: its
+        largest entry in magnitude is positive).
+
+        The eigenvalues span tens of decades, and a symmetric eigensolver
+        resolves only those above about 1e-16 of the largest.  So the
+        eigenpairs come from LAPACK's preconditioned Jacobi SVD (dgejsv),
+        which keeps relative accuracy on graded matrices: with Delta the
+        powers of two that bring the diagonal of Delta^-1 C Delta^-1 to
+        [1, 4) and Delta^-1 C Delta^-1 = L L^T, C = G^T G for G = L^T Delta,
+        whose singular values are sqrt(lambda) and whose right singular
+        vectors are the eigenvectors of C."""
+        from scipy.linalg import lapack
+        C = np.asarray(C, np.float64)
+        d = np.asarray(d, np.float64)
+        delta = np.ldexp(1.0, np.frexp(np.sqrt(np.diag(C)))[1])
+        L = np.linalg.cholesky(C / np.outer(delta, delta))
+        G = np.ascontiguousarray(L.T * delta[None, :])
+        sva, _, v, work, _, info = lapack.dgejsv(G, joba=2, jobu=3, jobv=0)
+        if info != 0:
+            raise np.linalg.LinAlgError("dgejsv failed (%d)" % info)
+        lam = (sva * (work[0] / work[1])) ** 2
+        S = v.T.copy()
+        o = np.argsort(lam, kind="stable")
+        lam, S = lam[o], S[o]
+        snr2 = (S @ d) ** 2 / lam
+        cum = np.cumsum(np.sort(snr2)[::-1])
+        if not vectors:
+            return lam, snr2, cum
+        big = np.argmax(np.abs(S), axis=1)
+        S *= np.sign(S[np.arange(len(S)), big])[:, None]
+        return lam, snr2, cum, S
+
     def run(self, ntri=None, ngins=False, ssc="rank1"):
         d, r = self.data_vector()
         C = self.covariance(ntri, ngins, ssc)
