@@ -37,7 +37,8 @@ enum {
   WLC_ENOMEM = -3,  /* host allocation failed                                      */
   WLC_ENOTPD = -4,  /* covariance not positive definite (Cholesky pivot <= 0)      */
   WLC_EDEVICE = -5, /* HIP runtime error                                           */
-  WLC_EBUSY = -6    /* serving: request refused by memory admission               */
+  WLC_EBUSY = -6,   /* serving: request refused by memory admission               */
+  WLC_ENOCONV = -7  /* an iteration did not converge within its sweep limit        */
 };
 
 /* ---- data-vector tomography convention (Sec. 5, ordering of eq. eq:SN2)
@@ -141,6 +142,7 @@ typedef struct {
   size_t ws_snr_structured_bytes; /* ... by wlc_snr2_structured (0: not available
                                      for this plan: SORTED tomography or n_z > 32) */
   int64_t n_avg;       /* entries of the bin-averaging lists (n_cfg at n_sub <= 1) */
+  size_t ws_pca_bytes; /* device workspace needed by wlc_pca (0: n_data > 65472) */
 } wlc_sizes;
 
 typedef struct wlc_plan_s *wlc_plan;
@@ -238,6 +240,29 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
  * errors as wlc_snr2; synchronises the stream. */
 int wlc_snr2_lmax(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
                   double *snr2_host, void *stream);
+
+/* Principal components of the joint covariance (Sec. 6): the eigen-
+ * decomposition C_true = sum_a lambda_a S_a S_a^T (eq. SNPCA), the new
+ * observables D^_a = S_a . d (eq. NewObs), their (S/N)^2_a = D^_a^2 /
+ * lambda_a (eq. SNperEign) and the cumulative curve (eq. CumulSN).
+ * The eigenvalues span tens of decades, so they come from one-sided Jacobi
+ * on the graded Cholesky factor (C_true = G^T G, G = L^T 2^-t with L the
+ * FP64 Cholesky factor of the scaled C), which keeps relative accuracy; the
+ * rotations run in blocks of 32 columns on FP64 MFMA until no pair of
+ * columns has |cos| above 8 sqrt(n_pad) eps, at most 40 sweeps.
+ * Inputs as wlc_snr2 (DEVICE C, row_exp2, d).  Outputs (HOST, n_data each):
+ *   lambda     eigenvalues of C_true, ascending;
+ *   snr2_mode  (S/N)^2 of each mode, in the order of lambda;
+ *   cum_desc   cumulative (S/N)^2 over the modes sorted by decreasing
+ *              (S/N)^2 (its last entry is d^T C^-1 d);
+ *   sweeps     (may be NULL) sweeps used.
+ * S (DEVICE [n_data][n_data], may be NULL to skip the eigenvectors): row a
+ * is the unit eigenvector of lambda[a], its largest entry in magnitude made
+ * positive.  ws: DEVICE workspace of ws_pca_bytes.  Synchronises the stream
+ * once per sweep.  WLC_ENOTPD if C is not positive definite, WLC_ENOCONV
+ * without convergence, WLC_EINVAL if ws_pca_bytes is 0. */
+int wlc_pca(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws, double *lambda,
+            double *snr2_mode, double *cum_desc, int32_t *sweeps, double *S, void *stream);
 
 /* The same (S/N)^2 through the distinct rows, for PAPER tomography.
  * With C = C_G + E M E^T (C_G the Gaussian term, block-diagonal over

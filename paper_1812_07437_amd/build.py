@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libwlcov.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["plan.cpp", "api.hip", "k_tables.hip", "k_gram.hip", "k_assemble.hip", "k_chol.hip", "k_update.hip",
-           "k_lattice.hip", "k_chifact.hip", "k_woodbury.hip", "k_window.hip", "server.hip"]
+           "k_lattice.hip", "k_chifact.hip", "k_woodbury.hip", "k_window.hip", "k_pca.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

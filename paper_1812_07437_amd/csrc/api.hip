@@ -140,6 +140,17 @@ size_t snr_ws_bytes(const Plan &p) {
          align_up((size_t)n * 4, 256) + 3 * align_up((size_t)p.n_ell * 8, 256);
 }
 
+// PCA workspace: the S/N workspace (bordered Cholesky), then X and V
+// [n_pad][n_pad], y [n_pad], per-mode arrays and the convergence word.
+static int64_t pca_pad(const Plan &p) { return round_up(p.n_out, 64); }
+
+size_t pca_ws_bytes(const Plan &p) {
+  const int64_t np = pca_pad(p), n = p.n_out;
+  if (np > 65535) return 0;
+  return align_up(snr_ws_bytes(p), 256) + 2 * align_up((size_t)np * np * 8, 256) + align_up((size_t)np * 8, 256) +
+         5 * align_up((size_t)n * 8, 256) + 2 * align_up((size_t)n * 4, 256) + 256;
+}
+
 size_t snr_structured_ws_bytes(const Plan &p) {
   if (p.cfg.tomo_mode != WLC_TOMO_PAPER || p.cfg.n_z > WOOD_NZ_MAX || (p.cfg.flags & WLC_FLAG_NGINS)) return 0;
   const int64_t n = p.n_R, ldw = snr_ld(n), ldt = round_up(n, 8);
@@ -552,6 +563,7 @@ int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out) {
   out->ws_snr_bytes = p.ws_snr;
   out->ws_snr_structured_bytes = snr_structured_ws_bytes(p);
   out->n_avg = (int64_t)p.sub_w.size();
+  out->ws_pca_bytes = pca_ws_bytes(p);
   return WLC_OK;
 }
 
@@ -682,6 +694,69 @@ int wlc_snr2_lmax(wlc_plan plan, const void *C, const int32_t *row_exp2, const d
   if (rc) return rc;
   if (hflag) return fail(WLC_ENOTPD, "covariance is not positive definite");
   return WLC_OK;
+}
+
+int wlc_pca(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws, double *lambda,
+            double *snr2_mode, double *cum_desc, int32_t *sweeps, double *S, void *stream) {
+  if (!plan || !C || !row_exp2 || !d || !ws || !lambda || !snr2_mode || !cum_desc)
+    return fail(WLC_EINVAL, "null argument");
+  if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "workspace must be 256-byte aligned");
+  const Plan &p = plan->p;
+  if (pca_ws_bytes(p) == 0) return fail(WLC_EINVAL, "the PCA supports at most 65472 data-vector rows");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = p.n_out, np = pca_pad(p), ld = snr_ld(n);
+  char *base = static_cast<char *>(ws);
+  size_t o = align_up(snr_ws_bytes(p), 256);
+  auto take = [&](size_t bytes) {
+    char *q = base + o;
+    o += align_up(bytes, 256);
+    return q;
+  };
+  double *X = reinterpret_cast<double *>(take((size_t)np * np * 8));
+  double *V = reinterpret_cast<double *>(take((size_t)np * np * 8));
+  double *y = reinterpret_cast<double *>(take((size_t)np * 8));
+  double *lam = reinterpret_cast<double *>(take((size_t)n * 8));
+  double *snr = reinterpret_cast<double *>(take((size_t)n * 8));
+  double *lam_out = reinterpret_cast<double *>(take((size_t)n * 8));
+  double *snr_out = reinterpret_cast<double *>(take((size_t)n * 8));
+  double *desc = reinterpret_cast<double *>(take((size_t)n * 8));
+  int32_t *rank_lam = reinterpret_cast<int32_t *>(take((size_t)n * 4));
+  int32_t *rank_snr = reinterpret_cast<int32_t *>(take((size_t)n * 4));
+  double *conv = reinterpret_cast<double *>(take(256));
+  // the bordered Cholesky: L of the scaled C and y = L^-1 2^t d
+  int32_t *flag = nullptr;
+  double *unused = nullptr;
+  int rc = snr_enqueue(p, C, row_exp2, d, ws, s, nullptr, nullptr, &flag, &unused);
+  if (rc) return rc;
+  int32_t hflag = 0;
+  rc = hip_check(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "pca copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "pca sync");
+  if (rc) return rc;
+  if (hflag) return fail(WLC_ENOTPD, "covariance is not positive definite");
+  double *Vr = S ? V : nullptr;
+  launch_pca_init(reinterpret_cast<const double *>(ws), ld, row_exp2, n, np, X, Vr, y, s);
+  const double tol = 8.0 * std::sqrt((double)np) * 2.220446049250313e-16;
+  const int n_blk = (int)(np / 32);
+  int used = 0;
+  bool converged = false;
+  for (int sweep = 0; sweep < 40 && !converged; ++sweep) {
+    launch_fill_i32(reinterpret_cast<int32_t *>(conv), 2, 0, s);
+    for (int r = 0; r < n_blk - 1; ++r) launch_pca_round(X, Vr, np, r, tol, 30, conv, s);
+    double hconv = 0.0;
+    rc = hip_check(hipMemcpyAsync(&hconv, conv, 8, hipMemcpyDeviceToHost, s), "pca copy");
+    if (!rc) rc = hip_check(hipStreamSynchronize(s), "pca sync");
+    if (rc) return rc;
+    used = sweep + 1;
+    converged = !(hconv > tol);
+  }
+  if (sweeps) *sweeps = used;
+  if (!converged) return fail(WLC_ENOCONV, "the PCA Jacobi sweeps did not converge");
+  launch_pca_finish(X, y, Vr, n, np, lam, snr, rank_lam, rank_snr, lam_out, snr_out, desc, S, s);
+  rc = hip_check(hipMemcpyAsync(lambda, lam_out, (size_t)n * 8, hipMemcpyDeviceToHost, s), "pca copy");
+  if (!rc) rc = hip_check(hipMemcpyAsync(snr2_mode, snr_out, (size_t)n * 8, hipMemcpyDeviceToHost, s), "pca copy");
+  if (!rc) rc = hip_check(hipMemcpyAsync(cum_desc, desc, (size_t)n * 8, hipMemcpyDeviceToHost, s), "pca copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(s), "pca sync");
+  return rc;
 }
 
 int wlc_snr2_structured(wlc_plan plan, const void *ws_run, void *ws, double *snr2_host, void *stream) {

@@ -158,6 +158,16 @@ struct WoodArgs {
 constexpr int WOOD_NZ_MAX = 32;
 void launch_woodbury(const WoodArgs &w, hipStream_t s);
 
+// ---- principal components (k_pca.hip): one-sided block Jacobi on the rows
+// of X (n_pad x n_pad, n_pad a multiple of 64 and at most 65535)
+void launch_pca_init(const double *Wm, int64_t ld, const int32_t *t, int64_t n, int64_t n_pad, double *X, double *V,
+                     double *y, hipStream_t s);
+void launch_pca_round(double *X, double *V, int64_t n_pad, int r, double tol, int max_inner, double *conv,
+                      hipStream_t s);
+void launch_pca_finish(const double *X, const double *y, const double *Vr, int64_t n, int64_t n_pad, double *lam,
+                       double *snr2, int32_t *rank_lam, int32_t *rank_snr, double *lam_out, double *snr2_out,
+                       double *desc, double *S, hipStream_t s);
+
 // ---- lattice counts (k_lattice.hip); thr_max = largest threshold used
 void launch_lattice(const int64_t *thr_dev, int64_t thr_max, int n_ell, const int32_t *tri, int n_tri,
                     uint64_t *modes, uint64_t *tris, hipStream_t s);

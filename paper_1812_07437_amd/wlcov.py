@@ -17,7 +17,7 @@ import torch  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwlcov.so")
 
-WLC_OK, WLC_EINVAL, WLC_ERANGE, WLC_ENOMEM, WLC_ENOTPD, WLC_EDEVICE, WLC_EBUSY = 0, -1, -2, -3, -4, -5, -6
+WLC_OK, WLC_EINVAL, WLC_ERANGE, WLC_ENOMEM, WLC_ENOTPD, WLC_EDEVICE, WLC_EBUSY, WLC_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 WLC_TOMO_PAPER, WLC_TOMO_SORTED = 0, 1
 WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32, WLC_FP64_CHI = 0, 1, 2, 3, 4
 WLC_FLAG_NOCHECK, WLC_FLAG_NGINS, WLC_FLAG_SSC_CHI = 1, 2, 4
@@ -49,7 +49,7 @@ class wlc_sizes(ct.Structure):
     _fields_ = [("n_data", ct.c_int64), ("n_distinct", ct.c_int64), ("n_p", ct.c_int64), ("n_tri", ct.c_int64),
                 ("n_cfg", ct.c_int64), ("n_ell_used", ct.c_int64), ("k_len", ct.c_int64),
                 ("c_elem_bytes", ct.c_size_t), ("ws_run_bytes", ct.c_size_t), ("ws_snr_bytes", ct.c_size_t),
-                ("ws_snr_structured_bytes", ct.c_size_t), ("n_avg", ct.c_int64)]
+                ("ws_snr_structured_bytes", ct.c_size_t), ("n_avg", ct.c_int64), ("ws_pca_bytes", ct.c_size_t)]
 
 
 def _load():
@@ -71,6 +71,7 @@ def _load():
     L.wlc_snr2.argtypes = [vp, vp, vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_snr2_structured.argtypes = [vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_snr2_lmax.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.wlc_pca.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
     L.wlc_plan_timings.argtypes = [vp, vp]
     L.wlc_plan_kernel_stats.argtypes = [vp, vp, vp, vp, vp]
@@ -81,7 +82,7 @@ lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_averaging",
             "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_lmax", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
@@ -163,6 +164,15 @@ def wlc_snr2_lmax(plan, C, row_exp2, d, ws, stream, n_ell):
     out = np.zeros(int(n_ell), np.float64)
     _check(lib.wlc_snr2_lmax(plan, C, row_exp2, d, ws, out.ctypes.data_as(ct.c_void_p), stream))
     return out
+
+
+def wlc_pca(plan, C, row_exp2, d, ws, n, S, stream):
+    """Returns (lambda, snr2_mode, cum_desc, sweeps) as numpy arrays / int."""
+    import numpy as np
+    lam = np.zeros(int(n)); snr = np.zeros(int(n)); cum = np.zeros(int(n)); sw = ct.c_int32(0)
+    _check(lib.wlc_pca(plan, C, row_exp2, d, ws, lam.ctypes.data_as(ct.c_void_p), snr.ctypes.data_as(ct.c_void_p),
+                       cum.ctypes.data_as(ct.c_void_p), ct.byref(sw), S, stream))
+    return lam, snr, cum, sw.value
 
 
 def wlc_snr2_structured(plan, ws_run, ws, stream):
@@ -265,6 +275,20 @@ class Problem:
             self.ws_snr = self.torch.empty(int(self.sizes.ws_snr_bytes), dtype=self.torch.uint8, device=self.device)
         return wlc_snr2_lmax(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(self.ws_snr),
                              _stream_handle(stream), self.sizes.n_ell_used)
+
+    def pca(self, vectors=True, stream=None):
+        """Principal components of this problem's covariance: (lambda,
+        snr2_mode, cum_desc, sweeps, S or None), S a device tensor."""
+        n = int(self.sizes.ws_pca_bytes)
+        if n == 0:
+            raise WlcError(WLC_EINVAL, "PCA not available for this plan size")
+        ws = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        N = int(self.sizes.n_data)
+        S = self.torch.empty((N, N), dtype=self.torch.float64, device=self.device) if vectors else None
+        lam, snr, cum, sw = wlc_pca(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(ws), N,
+                                    _ptr(S), _stream_handle(stream))
+        del ws
+        return lam, snr, cum, sw, S
 
     def snr2_structured(self, stream=None):
         """(S/N)^2 through the distinct rows, from this problem's last run."""
