@@ -39,6 +39,9 @@ def parse():
                     help="steps of the FP64 path with the one-halo term factorised along chi (0: skip)")
     ap.add_argument("--n-sub", type=int, default=3,
                     help="sub-bins per side of the bin-averaged leg (<= 1 skips it)")
+    ap.add_argument("--pca-workload", default="euclid5",
+                    help="workload of the PCA leg (FP64 covariance, then wlc_pca; empty: skip)")
+    ap.add_argument("--pca-only", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=12,
@@ -82,6 +85,51 @@ def gram_flops(n_r, k_len, precision):
     three MFMA products per entry."""
     f = n_r * (n_r + 1) * k_len
     return f * (3 if precision == "bf16x3" else 1)
+
+
+def pca_leg(args, torch, wl):
+    """Principal components (Sec. 6) of the FP64 joint covariance of the
+    Euclid-like workload: eigenvalues over tens of decades, per-mode and
+    cumulative S/N, the share of modes holding 99 % of (S/N)^2 and the
+    observables with |S_ai| >= 0.05 in the modes holding 95 %."""
+    import numpy as np
+    import synth
+    log("pca on %s (FP64 covariance)" % args.pca_workload)
+    tp = synth.make_tables(args.pca_workload)
+    pp = wl.Problem(tp.cfg, tp.arrays(), precision="fp64", device="cuda:0")
+    pp.run()
+    snr_p = pp.snr2()
+    torch.cuda.synchronize()
+    pp.free_snr_workspace()
+    pp.pca(vectors=True)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, snr_m, cum, sweeps, S = pp.pca(vectors=True)
+    torch.cuda.synchronize()
+    t_pca = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pp.pca(vectors=False)
+    torch.cuda.synchronize()
+    t_pca_nov = time.perf_counter() - t0
+    npca = len(lam)
+    k99 = int(np.searchsorted(cum, 0.99 * cum[-1]) + 1)
+    k95 = int(np.searchsorted(cum, 0.95 * cum[-1]) + 1)
+    top95 = torch.as_tensor(np.argsort(-snr_m, kind="stable")[:k95], device=S.device)
+    involved = int(torch.count_nonzero(torch.any(torch.abs(S[top95]) >= 0.05, dim=0)).item())
+    pca = dict(workload=args.pca_workload, n=npca, seconds=t_pca, seconds_without_vectors=t_pca_nov,
+               sweeps=sweeps, lambda_min=float(lam[0]), lambda_max=float(lam[-1]),
+               decades=float(np.log10(lam[-1] / lam[0])), snr2_total=float(cum[-1]),
+               snr2_rel_vs_cholesky=abs(cum[-1] - snr_p) / snr_p,
+               modes_for_99pct=k99, frac_modes_for_99pct=k99 / npca, modes_for_95pct=k95,
+               observables_in_95pct_modes=involved,
+               flops_per_sweep_est=12.0 * (((npca + 63) // 64) * 64) ** 3)
+    log("pca %s: N=%d, %.2f s (%.2f s without vectors), %d sweeps, lambda %.2e..%.2e (%.1f decades), "
+        "99%% of (S/N)^2 in %d modes (%.1f %%), %d observables in the 95%% modes" % (
+            args.pca_workload, npca, t_pca, t_pca_nov, sweeps, lam[0], lam[-1], pca["decades"], k99,
+            100.0 * k99 / npca, involved))
+    del S, pp
+    torch.cuda.empty_cache()
+    return pca
 
 
 def timed_steps(prob, steps, warmup, torch, wl, structured=False):
@@ -229,6 +277,11 @@ def main():
     import synth
     from paper_1812_07437_amd import wlcov as wl
 
+    if args.pca_only:
+        print(json.dumps({"metric": "principal components of the joint covariance", "data": "synthetic",
+                          "pca": pca_leg(args, torch, wl)}), flush=True)
+        return
+
     if args.serve_only:
         srv = serving(args.serve_requests or 24, args.serve_budget_gb, args.serve_slots, ["bf16x3", "fp64"], torch)
         print(json.dumps({"metric": "serving p50/p99 latency (ms) and requests/s", "data": "synthetic",
@@ -366,6 +419,8 @@ def main():
         del pb
         torch.cuda.empty_cache()
 
+    pca = pca_leg(args, torch, wl) if args.pca_workload else None
+
     # roofline of the dominant kernel of the step: the one-halo Gram (one
     # launch per step) or the Cholesky block update (many launches per step,
     # timed one by one with HIP events on the run's stream)
@@ -430,6 +485,7 @@ def main():
         "fp64_chi_ngins_path": ngins,
         "fp64_chi_ssc_chi_path": sscc,
         "fp64_chi_subbin_path": subbin,
+        "pca": pca,
         "serving": srv,
     }
     print(json.dumps(out), flush=True)
