@@ -17,12 +17,12 @@
 // L, zero-padded to n_pad), and the columns of Q the rows of V, so every
 // vector the method touches is a contiguous row.  Rows are grouped in blocks
 // of 32; each round pairs all blocks (a round-robin tournament over n_blk =
-// n_pad / 32 blocks, n_blk - 1 rounds per sweep), and one workgroup per pair
-// (p, q) forms the 64 x 64 Gram matrix of its rows on FP64 MFMA, diagonalises
-// it by cyclic two-sided Jacobi in LDS (relative accuracy again: rotations
-// are driven by |M_jl| / sqrt(M_jj M_ll)), and applies the 64 x 64 rotation
-// to its rows of X and V on FP64 MFMA.  Sweeps repeat until no pair has a
-// scaled off-diagonal entry above tol.
+// n_pad / 32 blocks, n_blk - 1 rounds per sweep); for each pair (p, q) the
+// 64 x 64 Gram matrix of its rows is formed on FP64 MFMA, rotated towards
+// diagonal form by cyclic two-sided Jacobi in LDS (relative accuracy again:
+// rotations are driven by |M_jl| / sqrt(M_jj M_ll)), and the 64 x 64
+// rotation is applied to its rows of X and V on FP64 MFMA.  Sweeps repeat
+// until no pair has a scaled off-diagonal entry above tol.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -57,74 +57,94 @@ __device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
   atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-// One round: workgroup i handles the block pair at positions (i, n_blk-1-i).
-__global__ __launch_bounds__(256) void k_pca_round(double *__restrict__ X, double *__restrict__ V, int64_t n_pad,
-                                                   int n_blk, int r, double tol, int max_inner,
-                                                   double *__restrict__ conv) {
+// A round is three launches.  (a) k_pca_gram: partial 64 x 64 Gram matrices
+// of each block pair over KS column slices (FP64 MFMA); (b) k_pca_rot, one
+// workgroup per pair: sum the slices in fixed order, measure the largest
+// scaled off-diagonal entry, and unless it is below tol run Jacobi sweeps on
+// M in LDS and store Q (reordering the rotated columns by norm, as in
+// de Rijk's sorting, was measured to break the convergence of the cyclic
+// tournament here);
+// (c) k_pca_apply: rows of X (and V) <- Q^T rows, 64 columns per workgroup,
+// skipped for pairs that did not rotate.
+__device__ __forceinline__ int64_t pair_row(int bp, int bq, int j) {
+  return j < PB ? (int64_t)bp * PB + j : (int64_t)bq * PB + (j - PB);
+}
+
+__global__ __launch_bounds__(256) void k_pca_gram(const double *__restrict__ X, int64_t n_pad, int n_blk, int r,
+                                                  int64_t cols, double *__restrict__ part) {
+  __shared__ double stage[PR * GLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int pi = blockIdx.x, ks = blockIdx.y;
+  const int bp = rr_at(pi, r, n_blk), bq = rr_at(n_blk - 1 - pi, r, n_blk);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int64_t c0 = (int64_t)ks * cols, c1 = c0 + cols;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double pre[4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q, j = e / GK, k = e % GK;
+      pre[q] = X[pair_row(bp, bq, j) * n_pad + k0 + k];
+    }
+  };
+  gload(c0);
+  for (int64_t k0 = c0; k0 < c1; k0 += GK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      stage[(e / GK) * GLD + e % GK] = pre[q];
+    }
+    __syncthreads();
+    if (k0 + GK < c1) gload(k0 + GK);
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const int kc = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = stage[(wr + x * 16 + (lane & 15)) * GLD + kc];
+        b[x] = stage[(wc + x * 16 + (lane & 15)) * GLD + kc];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
+    }
+  }
+  // accumulator value v of lane l: row l / 16 + 4 v, column l % 16
+  double *P = part + ((int64_t)pi * gridDim.y + ks) * PR * PR;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        P[(wr + x * 16 + (lane >> 4) + 4 * v) * PR + wc + z * 16 + (lane & 15)] = acc[x][z][v];
+}
+
+__global__ __launch_bounds__(256) void k_pca_rot(const double *__restrict__ part, int n_ks, double tol, int max_inner,
+                                                 double *__restrict__ Qg, int32_t *__restrict__ rot,
+                                                 double *__restrict__ conv) {
   __shared__ double M[PR * PLD];
   __shared__ double Q[PR * PLD];
-  __shared__ double stage[PR * PLD];  // Gram stages, then 64 x 64 chunks of X and V
   __shared__ double cs_c[PR], cs_s[PR], cs_t[PR];
-  __shared__ int part[PR];
-  __shared__ double red[256];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bp = rr_at(blockIdx.x, r, n_blk), bq = rr_at(n_blk - 1 - blockIdx.x, r, n_blk);
-  auto grow = [&](int j) -> int64_t { return j < PB ? (int64_t)bp * PB + j : (int64_t)bq * PB + (j - PB); };
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-
-  // ---- 1. Gram matrix of the 64 rows: M = X_pq X_pq^T over n_pad columns
-  {
-    f64x4 acc[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double pre[4];
-    auto gload = [&](int64_t k0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q, j = e / GK, k = e % GK;
-        pre[q] = X[grow(j) * n_pad + k0 + k];
-      }
-    };
-    gload(0);
-    for (int64_t k0 = 0; k0 < n_pad; k0 += GK) {
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        stage[(e / GK) * GLD + e % GK] = pre[q];
-      }
-      __syncthreads();
-      if (k0 + GK < n_pad) gload(k0 + GK);
-#pragma unroll
-      for (int kk = 0; kk < GK; kk += 4) {
-        const int kc = kk + (lane >> 4);
-        double a[2], b[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          a[x] = stage[(wr + x * 16 + (lane & 15)) * GLD + kc];
-          b[x] = stage[(wc + x * 16 + (lane & 15)) * GLD + kc];
-        }
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
-      }
-    }
-    // accumulator value v of lane l: row l / 16 + 4 v, column l % 16
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int z = 0; z < 2; ++z)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          M[(wr + x * 16 + (lane >> 4) + 4 * v) * PLD + wc + z * 16 + (lane & 15)] = acc[x][z][v];
+    __shared__ double red[256];
+  const int tid = threadIdx.x, pi = blockIdx.x;
+  for (int e = tid; e < PR * PR; e += 256) {
+    const double *P = part + (int64_t)pi * n_ks * PR * PR + e;
+    double v = 0.0;
+    for (int k = 0; k < n_ks; ++k) v += P[(int64_t)k * PR * PR];
+    M[(e / PR) * PLD + e % PR] = v;
+    Q[(e / PR) * PLD + e % PR] = (e / PR == e % PR) ? 1.0 : 0.0;
   }
-  for (int e = tid; e < PR * PR; e += 256) Q[(e / PR) * PLD + e % PR] = (e / PR == e % PR) ? 1.0 : 0.0;
   __syncthreads();
-  // symmetrise from the lower triangle (both MFMA halves hold the same sums
-  // in another order) and measure the largest scaled off-diagonal entry
+  // symmetrise from the lower triangle and measure the largest scaled
+  // off-diagonal entry
   double off = 0.0;
   for (int e = tid; e < PR * PR; e += 256) {
     const int j = e / PR, l = e % PR;
@@ -142,11 +162,14 @@ __global__ __launch_bounds__(256) void k_pca_round(double *__restrict__ X, doubl
     __syncthreads();
   }
   const double off0 = red[0];
-  if (tid == 0) atomic_max_nonneg(conv, off0);
-  if (!(off0 > tol)) return;  // this pair is already orthogonal: nothing to rotate
+  if (tid == 0) {
+    atomic_max_nonneg(conv, off0);
+    rot[pi] = off0 > tol ? 1 : 0;
+  }
+  if (!(off0 > tol)) return;  // this pair is already orthogonal
   __syncthreads();
 
-  // ---- 2. cyclic two-sided Jacobi on M (in place), Q accumulates J
+  // cyclic two-sided Jacobi on M (in place), Q accumulates the rotations
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     double inner = 0.0;
     for (int ir = 0; ir < PR - 1; ++ir) {
@@ -154,25 +177,25 @@ __global__ __launch_bounds__(256) void k_pca_round(double *__restrict__ X, doubl
         const int j = rr_at(tid, ir, PR), l = rr_at(PR - 1 - tid, ir, PR);
         const double mjj = M[j * PLD + j], mll = M[l * PLD + l], mjl = M[j * PLD + l];
         const double den = sqrt(mjj * mll);
-        double c = 1.0, s = 0.0, tt = 0.0;
+        double c = 1.0, sn = 0.0, tt = 0.0;
         if (den > 0.0 && fabs(mjl) > tol * den) {
           inner = fmax(inner, fabs(mjl) / den);
           const double th = (mll - mjj) / (2.0 * mjl);
           tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
           c = 1.0 / sqrt(1.0 + tt * tt);
-          s = c * tt;
+          sn = c * tt;
         }
         // x_j' = c x_j - s x_l, x_l' = s x_j + c x_l
-        cs_c[j] = c; cs_s[j] = -s; cs_t[j] = -tt; part[j] = l;
-        cs_c[l] = c; cs_s[l] = s;  cs_t[l] = tt;  part[l] = j;
+        cs_c[j] = c; cs_s[j] = -sn; cs_t[j] = -tt;
+        cs_c[l] = c; cs_s[l] = sn;  cs_t[l] = tt;
       }
       __syncthreads();
-      // 2 x 2 blocks (pair of i) x (pair of k); each of the 32 x 32 blocks by one thread
+      // 2 x 2 blocks (pair of i) x (pair of k), one per thread and step
       for (int bidx = tid; bidx < (PR / 2) * (PR / 2); bidx += 256) {
-        const int pi = bidx / (PR / 2), pk = bidx % (PR / 2);
-        const int i0 = rr_at(pi, ir, PR), i1 = rr_at(PR - 1 - pi, ir, PR);
-        const int k0 = rr_at(pk, ir, PR), k1 = rr_at(PR - 1 - pk, ir, PR);
-        if (pi == pk) {
+        const int qi = bidx / (PR / 2), qk = bidx % (PR / 2);
+        const int i0 = rr_at(qi, ir, PR), i1 = rr_at(PR - 1 - qi, ir, PR);
+        const int k0 = rr_at(qk, ir, PR), k1 = rr_at(PR - 1 - qk, ir, PR);
+        if (qi == qk) {
           // the pair's own block: exact diagonal update, zero off-diagonal
           const double m01 = M[i0 * PLD + i1];
           if (cs_s[i0] != 0.0) {
@@ -184,22 +207,21 @@ __global__ __launch_bounds__(256) void k_pca_round(double *__restrict__ X, doubl
         } else {
           const double a00 = M[i0 * PLD + k0], a01 = M[i0 * PLD + k1], a10 = M[i1 * PLD + k0],
                        a11 = M[i1 * PLD + k1];
-          // x_i' = c_i x_i + s_i x_i' (partner), both sides
+          // x_i' = c_i x_i + s_i x_(partner of i), on both sides
           const double ci0 = cs_c[i0], si0 = cs_s[i0], ci1 = cs_c[i1], si1 = cs_s[i1];
           const double ck0 = cs_c[k0], sk0 = cs_s[k0], ck1 = cs_c[k1], sk1 = cs_s[k1];
-          // rows first: r(i0) = c a(i0) + s a(i1), r(i1) = c a(i1) + s a(i0)
           const double r00 = ci0 * a00 + si0 * a10, r01 = ci0 * a01 + si0 * a11;
           const double r10 = ci1 * a10 + si1 * a00, r11 = ci1 * a11 + si1 * a01;
-          const double n00 = ck0 * r00 + sk0 * r01, n01 = ck1 * r01 + sk1 * r00;
-          const double n10 = ck0 * r10 + sk0 * r11, n11 = ck1 * r11 + sk1 * r10;
-          M[i0 * PLD + k0] = n00; M[i0 * PLD + k1] = n01;
-          M[i1 * PLD + k0] = n10; M[i1 * PLD + k1] = n11;
+          M[i0 * PLD + k0] = ck0 * r00 + sk0 * r01;
+          M[i0 * PLD + k1] = ck1 * r01 + sk1 * r00;
+          M[i1 * PLD + k0] = ck0 * r10 + sk0 * r11;
+          M[i1 * PLD + k1] = ck1 * r11 + sk1 * r10;
         }
       }
-      // Q <- Q J: columns of each pair, row by row
+      // Q <- Q J: the two columns of each pair, row by row
       for (int e = tid; e < PR * (PR / 2); e += 256) {
-        const int row = e / (PR / 2), pi = e % (PR / 2);
-        const int i0 = rr_at(pi, ir, PR), i1 = rr_at(PR - 1 - pi, ir, PR);
+        const int row = e / (PR / 2), qi = e % (PR / 2);
+        const int i0 = rr_at(qi, ir, PR), i1 = rr_at(PR - 1 - qi, ir, PR);
         if (cs_s[i0] == 0.0) continue;
         const double q0 = Q[row * PLD + i0], q1 = Q[row * PLD + i1];
         Q[row * PLD + i0] = cs_c[i0] * q0 + cs_s[i0] * q1;
@@ -219,48 +241,58 @@ __global__ __launch_bounds__(256) void k_pca_round(double *__restrict__ X, doubl
     __syncthreads();
     if (done) break;
   }
+  double *out = Qg + (int64_t)pi * PR * PR;
+  for (int e = tid; e < PR * PR; e += 256) out[e] = Q[(e / PR) * PLD + e % PR];
+}
 
-  // ---- 3. rows of X (and V) <- Q^T rows, in 64-column chunks on FP64 MFMA
-  for (int op = 0; op < (V ? 2 : 1); ++op) {
-    double *Y = op == 0 ? X : V;
-    for (int64_t c0 = 0; c0 < n_pad; c0 += PR) {
-      __syncthreads();
-      for (int e = tid; e < PR * PR; e += 256) {
-        const int j = e / PR, k = e % PR;
-        stage[j * PLD + k] = Y[grow(j) * n_pad + c0 + k];
-      }
-      __syncthreads();
-      f64x4 acc[2][2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
-      // out[j][c] = sum_l Q[l][j] stage[l][c]
-#pragma unroll 4
-      for (int kk = 0; kk < PR; kk += 4) {
-        const int l = kk + (lane >> 4);
-        double a[2], b[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          a[x] = Q[l * PLD + wr + x * 16 + (lane & 15)];
-          b[x] = stage[l * PLD + wc + x * 16 + (lane & 15)];
-        }
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
-      }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int z = 0; z < 2; ++z)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int j = wr + x * 16 + (lane >> 4) + 4 * v, c = wc + z * 16 + (lane & 15);
-            Y[grow(j) * n_pad + c0 + c] = acc[x][z][v];
-          }
-    }
+__global__ __launch_bounds__(256) void k_pca_apply(double *__restrict__ X, double *__restrict__ V, int64_t n_pad,
+                                                   int n_blk, int r, const double *__restrict__ Qg,
+                                                   const int32_t *__restrict__ rot) {
+  __shared__ double Q[PR * PLD];
+  __shared__ double stage[PR * PLD];
+  const int pi = blockIdx.x;
+  if (!rot[pi]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bp = rr_at(pi, r, n_blk), bq = rr_at(n_blk - 1 - pi, r, n_blk);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  double *Y = blockIdx.z == 0 ? X : V;
+  const int64_t c0 = (int64_t)blockIdx.y * PR;
+  const double *q = Qg + (int64_t)pi * PR * PR;
+  for (int e = tid; e < PR * PR; e += 256) {
+    const int j = e / PR, k = e % PR;
+    Q[j * PLD + k] = q[e];
+    stage[j * PLD + k] = Y[pair_row(bp, bq, j) * n_pad + c0 + k];
   }
+  __syncthreads();
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // out[j][c] = sum_l Q[l][j] stage[l][c]
+#pragma unroll 4
+  for (int kk = 0; kk < PR; kk += 4) {
+    const int l = kk + (lane >> 4);
+    double a[2], b[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      a[x] = Q[l * PLD + wr + x * 16 + (lane & 15)];
+      b[x] = stage[l * PLD + wc + x * 16 + (lane & 15)];
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = wr + x * 16 + (lane >> 4) + 4 * v, c = wc + z * 16 + (lane & 15);
+        Y[pair_row(bp, bq, j) * n_pad + c0 + c] = acc[x][z][v];
+      }
 }
 
 // Per mode a < n: lambda_a = |x_a|^2 and (S/N)^2_a = (x_a . y)^2 / lambda_a.
@@ -358,11 +390,23 @@ void launch_pca_init(const double *Wm, int64_t ld, const int32_t *t, int64_t n, 
   hipLaunchKernelGGL(k_pca_init, grid, dim3(256), 0, s, Wm, ld, t, n, n_pad, X, V, y);
 }
 
+// Column slices of the Gram: enough workgroups to cover the chip, each
+// slice a multiple of 64 columns.
+int pca_slices(int64_t n_pad) {
+  const int pairs = (int)(n_pad / PB) / 2;
+  int ks = 1;
+  while (pairs * ks * 2 <= 1024 && n_pad % ((int64_t)ks * 2 * PR) == 0 && n_pad / (ks * 2) >= 256) ks *= 2;
+  return ks;
+}
+
 void launch_pca_round(double *X, double *V, int64_t n_pad, int r, double tol, int max_inner, double *conv,
-                      hipStream_t s) {
-  const int n_blk = (int)(n_pad / PB);
-  hipLaunchKernelGGL(k_pca_round, dim3((unsigned)(n_blk / 2)), dim3(256), 0, s, X, V, n_pad, n_blk, r, tol,
-                     max_inner, conv);
+                      double *part, double *Qg, int32_t *rot, hipStream_t s) {
+  const int n_blk = (int)(n_pad / PB), pairs = n_blk / 2, ks = pca_slices(n_pad);
+  hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
+                     n_pad / ks, part);
+  hipLaunchKernelGGL(k_pca_rot, dim3((unsigned)pairs), dim3(256), 0, s, part, ks, tol, max_inner, Qg, rot, conv);
+  hipLaunchKernelGGL(k_pca_apply, dim3((unsigned)pairs, (unsigned)(n_pad / PR), V ? 2u : 1u), dim3(256), 0, s, X, V,
+                     n_pad, n_blk, r, Qg, rot);
 }
 
 void launch_pca_finish(const double *X, const double *y, const double *Vr, int64_t n, int64_t n_pad, double *lam,

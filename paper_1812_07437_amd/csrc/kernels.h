@@ -162,8 +162,11 @@ void launch_woodbury(const WoodArgs &w, hipStream_t s);
 // of X (n_pad x n_pad, n_pad a multiple of 64 and at most 65535)
 void launch_pca_init(const double *Wm, int64_t ld, const int32_t *t, int64_t n, int64_t n_pad, double *X, double *V,
                      double *y, hipStream_t s);
+// one round r of the tournament; part: [pairs][pca_slices][64][64], Qg:
+// [pairs][64][64] doubles, rot: [pairs] int32 of scratch
+int pca_slices(int64_t n_pad);
 void launch_pca_round(double *X, double *V, int64_t n_pad, int r, double tol, int max_inner, double *conv,
-                      hipStream_t s);
+                      double *part, double *Qg, int32_t *rot, hipStream_t s);
 void launch_pca_finish(const double *X, const double *y, const double *Vr, int64_t n, int64_t n_pad, double *lam,
                        double *snr2, int32_t *rank_lam, int32_t *rank_snr, double *lam_out, double *snr2_out,
                        double *desc, double *S, hipStream_t s);
