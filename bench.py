@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=180.0)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-serve-fp64", action="store_true",
+                    help="serve the stream in the headline precision only (default: also the plain FP64 path)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (to scale HBM byte counters)")
     return ap.parse_args()
@@ -193,6 +195,11 @@ def cpu_baseline(tables, seconds, n_data):
     return dict(value=total / est_step, unit="cov entries/s", cores=cores, kind="oracle",
                 sample="data vector + %d seeded covariance entries (%.1f s); S/N Cholesky not included" %
                 (done, t_setup + t_pairs))
+
+
+def serve_precisions(args):
+    """The headline precision, then the plain FP64 path for comparison."""
+    return [args.precision] + ([] if args.no_serve_fp64 or args.precision == "fp64" else ["fp64"])
 
 
 def serving(n_req, budget_gb, slots, precisions, torch):
@@ -459,7 +466,7 @@ def main():
     srv = None
     if args.serve_requests > 0:
         log("serving stream (%d requests)" % args.serve_requests)
-        srv = serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, [args.precision], torch)
+        srv = serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, serve_precisions(args), torch)
 
     cpu = None
     if not args.no_cpu:

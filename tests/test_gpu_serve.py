@@ -109,3 +109,24 @@ def test_memory_admission(env):
         srv.release(t)
     assert snrs[0] == snrs[1] == snrs[2]
     srv.close()
+
+
+def test_server_fp64_matches_direct(env):
+    """The plain FP64 path through the server: bitwise the direct result."""
+    serve, wl, fid, reqs = env
+    q = min(reqs, key=lambda r: (r["n_z"], r["ell_max"]))
+    _say("case serve fp64 vs direct n_z=%d l_max=%g" % (q["n_z"], q["ell_max"]))
+    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=8 << 30, max_inflight=2, precision="fp64")
+    t = srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+    res, d, r, C, tt = srv.fetch(t)
+    assert res.status == 0
+    tab = synth.request_tables(fid, q)
+    prob = wl.Problem(tab.cfg, tab.arrays(), precision="fp64")
+    prob.run()
+    snr2 = prob.snr2()
+    torch.cuda.synchronize()
+    assert torch.equal(prob.d, d) and torch.equal(prob.C, C) and torch.equal(prob.row_exp2, tt)
+    assert res.snr2 == snr2
+    srv.release(t)
+    srv.close()
+    prob.close()
