@@ -6,7 +6,12 @@ Inputs are the directories rocprofv3 writes with ``--output-format csv``:
 * ``--trace DIR``  from ``--kernel-trace --stats`` (``*_kernel_trace.csv``);
 * ``--fetch DIR``  from ``--pmc FETCH_SIZE``;
 * ``--write DIR``  from ``--pmc WRITE_SIZE``;
-* ``--hit DIR``    from ``--pmc TCC_HIT_sum TCC_MISS_sum`` (optional).
+* ``--hit DIR``    from ``--pmc TCC_HIT_sum TCC_MISS_sum`` (optional);
+* ``--mfma DIR``   from ``--pmc MfmaUtil MfmaFlopsBF16 MfmaFlopsF64`` (optional):
+  MfmaUtil is the share of SIMD cycles with the matrix core busy
+  (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE times the SIMD count), per
+  dispatch; the MfmaFlops counters count 512 flops per MFMA operation, and
+  are divided by the dispatch's own duration.
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  They are scaled
 by what the same counters read for a plain device copy of known size: the
@@ -57,6 +62,21 @@ def kernel_times(trace_dir):
     return out
 
 
+def dispatch_times(d, name):
+    """kernel name -> list of dispatch durations (ms) of a counter run, in the
+    order counters() lists that counter's values."""
+    per = collections.OrderedDict()
+    for r in _csv(d, "_counter_collection.csv"):
+        if r["Counter_Name"] != name:
+            continue
+        key = (r["Kernel_Name"], r["Dispatch_Id"])
+        per.setdefault(key, (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    out = collections.OrderedDict()
+    for (k, _), v in per.items():
+        out.setdefault(k, []).append(v)
+    return out
+
+
 def counters(d, name):
     """kernel name -> list of per-dispatch counter values (summed over the
     dimension rows rocprofv3 may emit for one dispatch)."""
@@ -89,6 +109,7 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--hit")
+    ap.add_argument("--mfma")
     ap.add_argument("--out", required=True)
     ap.add_argument("--title", required=True)
     ap.add_argument("--command", required=True)
@@ -128,6 +149,28 @@ def main():
         for k in order[:a.top]:
             if k in h and k in m and sum(h[k]) + sum(m[k]) > 0:
                 lines.append("| `%s` | %.3f |" % (_short(k), sum(h[k]) / (sum(h[k]) + sum(m[k]))))
+    if a.mfma:
+        util = counters(a.mfma, "MfmaUtil")
+        fb, fd = counters(a.mfma, "MfmaFlopsBF16"), counters(a.mfma, "MfmaFlopsF64")
+        mt = dispatch_times(a.mfma, "MfmaUtil")
+        lines += ["", "Matrix-core activity (`--pmc MfmaUtil MfmaFlopsBF16 MfmaFlopsF64`, one run): MfmaUtil is "
+                  "the share of SIMD cycles with the MFMA unit busy, averaged over dispatches weighted by "
+                  "duration; the MFMA flop rates use the counted operations and each dispatch's duration in "
+                  "that run.", "",
+                  "| kernel | dispatches | MfmaUtil % | bf16 MFMA TFLOP/s | f64 MFMA TFLOP/s |",
+                  "|---|---:|---:|---:|---:|"]
+        for k in order[:a.top]:
+            if k not in util:
+                continue
+            dur = mt.get(k, [])
+            u = util[k]
+            if dur and len(dur) == len(u):
+                uw = sum(x * t for x, t in zip(u, dur)) / sum(dur)
+                tb = sum(fb.get(k, [0.0])) / (sum(dur) * 1e-3) / 1e12
+                td = sum(fd.get(k, [0.0])) / (sum(dur) * 1e-3) / 1e12
+            else:
+                uw, tb, td = sum(u) / len(u), float("nan"), float("nan")
+            lines.append("| `%s` | %d | %.1f | %.1f | %.1f |" % (_short(k), len(u), uw, tb, td))
     # every kernel whose name is the recorded one (all template instances)
     # counts as one kernel: launches, time and bytes are summed over them
     recs = []
