@@ -127,15 +127,17 @@ __global__ __launch_bounds__(256) void k_pca_gram(const double *__restrict__ X, 
         P[(wr + x * 16 + (lane >> 4) + 4 * v) * PR + wc + z * 16 + (lane & 15)] = acc[x][z][v];
 }
 
-__global__ __launch_bounds__(256) void k_pca_rot(const double *__restrict__ part, int n_ks, double tol, int max_inner,
+constexpr int RT = 1024;  // threads of the rotation kernel: one 2 x 2 block each per inner step
+
+__global__ __launch_bounds__(RT) void k_pca_rot(const double *__restrict__ part, int n_ks, double tol, int max_inner,
                                                  double *__restrict__ Qg, int32_t *__restrict__ rot,
                                                  double *__restrict__ conv) {
   __shared__ double M[PR * PLD];
   __shared__ double Q[PR * PLD];
   __shared__ double cs_c[PR], cs_s[PR], cs_t[PR];
-    __shared__ double red[256];
+    __shared__ double red[RT];
   const int tid = threadIdx.x, pi = blockIdx.x;
-  for (int e = tid; e < PR * PR; e += 256) {
+  for (int e = tid; e < PR * PR; e += RT) {
     const double *P = part + (int64_t)pi * n_ks * PR * PR + e;
     double v = 0.0;
     for (int k = 0; k < n_ks; ++k) v += P[(int64_t)k * PR * PR];
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(256) void k_pca_rot(const double *__restrict__ part
   // symmetrise from the lower triangle and measure the largest scaled
   // off-diagonal entry
   double off = 0.0;
-  for (int e = tid; e < PR * PR; e += 256) {
+  for (int e = tid; e < PR * PR; e += RT) {
     const int j = e / PR, l = e % PR;
     if (l < j) {
       const double mjl = M[j * PLD + l];
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void k_pca_rot(const double *__restrict__ part
   }
   red[tid] = off;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = RT / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
     __syncthreads();
   }
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(256) void k_pca_rot(const double *__restrict__ part
       }
       __syncthreads();
       // 2 x 2 blocks (pair of i) x (pair of k), one per thread and step
-      for (int bidx = tid; bidx < (PR / 2) * (PR / 2); bidx += 256) {
+      for (int bidx = tid; bidx < (PR / 2) * (PR / 2); bidx += RT) {
         const int qi = bidx / (PR / 2), qk = bidx % (PR / 2);
         const int i0 = rr_at(qi, ir, PR), i1 = rr_at(PR - 1 - qi, ir, PR);
         const int k0 = rr_at(qk, ir, PR), k1 = rr_at(PR - 1 - qk, ir, PR);
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(256) void k_pca_rot(const double *__restrict__ part
         }
       }
       // Q <- Q J: the two columns of each pair, row by row
-      for (int e = tid; e < PR * (PR / 2); e += 256) {
+      for (int e = tid; e < PR * (PR / 2); e += RT) {
         const int row = e / (PR / 2), qi = e % (PR / 2);
         const int i0 = rr_at(qi, ir, PR), i1 = rr_at(PR - 1 - qi, ir, PR);
         if (cs_s[i0] == 0.0) continue;
@@ -242,8 +244,10 @@ __global__ __launch_bounds__(256) void k_pca_rot(const double *__restrict__ part
     if (done) break;
   }
   double *out = Qg + (int64_t)pi * PR * PR;
-  for (int e = tid; e < PR * PR; e += 256) out[e] = Q[(e / PR) * PLD + e % PR];
+  for (int e = tid; e < PR * PR; e += RT) out[e] = Q[(e / PR) * PLD + e % PR];
 }
+
+constexpr int AC = 4;  // 64-column chunks per apply workgroup (Q read once for all)
 
 __global__ __launch_bounds__(256) void k_pca_apply(double *__restrict__ X, double *__restrict__ V, int64_t n_pad,
                                                    int n_blk, int r, const double *__restrict__ Qg,
@@ -256,43 +260,47 @@ __global__ __launch_bounds__(256) void k_pca_apply(double *__restrict__ X, doubl
   const int bp = rr_at(pi, r, n_blk), bq = rr_at(n_blk - 1 - pi, r, n_blk);
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   double *Y = blockIdx.z == 0 ? X : V;
-  const int64_t c0 = (int64_t)blockIdx.y * PR;
   const double *q = Qg + (int64_t)pi * PR * PR;
-  for (int e = tid; e < PR * PR; e += 256) {
-    const int j = e / PR, k = e % PR;
-    Q[j * PLD + k] = q[e];
-    stage[j * PLD + k] = Y[pair_row(bp, bq, j) * n_pad + c0 + k];
-  }
-  __syncthreads();
-  f64x4 acc[2][2];
+  for (int e = tid; e < PR * PR; e += 256) Q[(e / PR) * PLD + e % PR] = q[e];
+  for (int ci = 0; ci < AC; ++ci) {
+    const int64_t c0 = ((int64_t)blockIdx.y * AC + ci) * PR;
+    if (c0 >= n_pad) break;
+    __syncthreads();  // Q is in place, and the previous chunk's reads of stage are done
+    for (int e = tid; e < PR * PR; e += 256) {
+      const int j = e / PR, k = e % PR;
+      stage[j * PLD + k] = Y[pair_row(bp, bq, j) * n_pad + c0 + k];
+    }
+    __syncthreads();
+    f64x4 acc[2][2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // out[j][c] = sum_l Q[l][j] stage[l][c]
+      for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // out[j][c] = sum_l Q[l][j] stage[l][c]
 #pragma unroll 4
-  for (int kk = 0; kk < PR; kk += 4) {
-    const int l = kk + (lane >> 4);
-    double a[2], b[2];
+    for (int kk = 0; kk < PR; kk += 4) {
+      const int l = kk + (lane >> 4);
+      double a[2], b[2];
 #pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      a[x] = Q[l * PLD + wr + x * 16 + (lane & 15)];
-      b[x] = stage[l * PLD + wc + x * 16 + (lane & 15)];
+      for (int x = 0; x < 2; ++x) {
+        a[x] = Q[l * PLD + wr + x * 16 + (lane & 15)];
+        b[x] = stage[l * PLD + wc + x * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
+      for (int z = 0; z < 2; ++z)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = wr + x * 16 + (lane >> 4) + 4 * v, c = wc + z * 16 + (lane & 15);
+          Y[pair_row(bp, bq, j) * n_pad + c0 + c] = acc[x][z][v];
+        }
   }
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int z = 0; z < 2; ++z)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = wr + x * 16 + (lane >> 4) + 4 * v, c = wc + z * 16 + (lane & 15);
-        Y[pair_row(bp, bq, j) * n_pad + c0 + c] = acc[x][z][v];
-      }
 }
 
 // Per mode a < n: lambda_a = |x_a|^2 and (S/N)^2_a = (x_a . y)^2 / lambda_a.
@@ -404,8 +412,9 @@ void launch_pca_round(double *X, double *V, int64_t n_pad, int r, double tol, in
   const int n_blk = (int)(n_pad / PB), pairs = n_blk / 2, ks = pca_slices(n_pad);
   hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
                      n_pad / ks, part);
-  hipLaunchKernelGGL(k_pca_rot, dim3((unsigned)pairs), dim3(256), 0, s, part, ks, tol, max_inner, Qg, rot, conv);
-  hipLaunchKernelGGL(k_pca_apply, dim3((unsigned)pairs, (unsigned)(n_pad / PR), V ? 2u : 1u), dim3(256), 0, s, X, V,
+  hipLaunchKernelGGL(k_pca_rot, dim3((unsigned)pairs), dim3(RT), 0, s, part, ks, tol, max_inner, Qg, rot, conv);
+  hipLaunchKernelGGL(k_pca_apply, dim3((unsigned)pairs, (unsigned)((n_pad / PR + AC - 1) / AC), V ? 2u : 1u),
+                     dim3(256), 0, s, X, V,
                      n_pad, n_blk, r, Qg, rot);
 }
 
