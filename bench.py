@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--pca-workload", default="euclid5",
                     help="workload of the PCA leg (FP64 covariance, then wlc_pca; empty: skip)")
     ap.add_argument("--pca-only", action="store_true")
+    ap.add_argument("--no-pca-tomography", dest="pca_tomography", action="store_false",
+                    help="skip the PCA of the paper's 14-bin binning with 1, 2 and 5 redshift bins")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=12,
@@ -131,6 +133,28 @@ def pca_leg(args, torch, wl):
             100.0 * k99 / npca, involved))
     del S, pp
     torch.cuda.empty_cache()
+    # the paper's PCA study: its 14 ell-bins over 10-5000 with 1, 2 and 5
+    # redshift bins (joint vectors of 144, 818 and 10000 rows); the share of
+    # modes holding 99 % of (S/N)^2 as the tomography grows
+    if args.pca_tomography:
+        rows = []
+        for nz in (1, 2, 5):
+            tz = synth.make_tables("paper14", n_z=nz)
+            pz = wl.Problem(tz.cfg, tz.arrays(), precision="fp64", device="cuda:0")
+            pz.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lz, sz, cz, swz, _ = pz.pca(vectors=False)
+            torch.cuda.synchronize()
+            dtz = time.perf_counter() - t0
+            k = int(np.searchsorted(cz, 0.99 * cz[-1]) + 1)
+            rows.append(dict(n_z=nz, n=len(lz), seconds=dtz, sweeps=swz, decades=float(np.log10(lz[-1] / lz[0])),
+                             modes_for_99pct=k, frac_modes_for_99pct=k / len(lz)))
+            log("pca paper binning n_z=%d: N=%d, %.2f s, %d sweeps, %.1f decades, 99%% of (S/N)^2 in %d modes "
+                "(%.1f %%)" % (nz, len(lz), dtz, swz, rows[-1]["decades"], k, 100.0 * k / len(lz)))
+            del pz
+            torch.cuda.empty_cache()
+        pca["paper_tomography"] = rows
     return pca
 
 

@@ -51,6 +51,9 @@ PRESETS = {
     "mid":     dict(n_z=3, n_ell=7, ell_min=50.0, ell_max=2000.0, n_chi=96, n_m=48, n_k=768),
     "euclid5": dict(n_z=5, n_ell=10, ell_min=20.0, ell_max=3000.0, n_chi=256, n_m=128, n_k=768),
     "large10": dict(n_z=10, n_ell=15, ell_min=10.0, ell_max=5000.0, n_chi=512, n_m=256, n_k=768),
+    # the paper's own binning (14 log ell-bins over 10-5000, App. A) on the
+    # Euclid-like grid; n_z is chosen per use (1, 2 and 5 in its PCA study)
+    "paper14": dict(n_z=5, n_ell=14, ell_min=10.0, ell_max=5000.0, n_chi=256, n_m=128, n_k=768),
 }
 
 SURVEY_DEFAULTS = dict(f_sky=0.36, sigma_eps=0.3, n_gal_arcmin2=30.0,

@@ -105,3 +105,30 @@ def test_pca_euclid5_properties(wl):
                     prob.C[b, b].double() * torch.exp2(-2.0 * te[b].double()))
     assert torch.max(torch.abs(rec - Ct) / sc).item() < 1e-9
     prob.close()
+
+
+@pytest.mark.parametrize("n_z", [1, 2])
+def test_pca_paper_binning(wl, n_z):
+    """The paper's 14 ell-bins over 10-5000 with one and two redshift bins
+    (N = 144 and 818): eigenvalues against the oracle, and the number of
+    modes holding 99 % of (S/N)^2 the same on both sides unless the oracle's
+    own cumulative curve sits within 1e-8 of that threshold."""
+    _say("case pca paper binning n_z=%d" % n_z)
+    t = synth.make_tables("paper14", n_z=n_z)
+    r = oracle.Oracle(t).run()
+    lam0, snr0, cum0 = oracle.Oracle.pca(r["C"], r["d"], vectors=False)
+    prob = wl.Problem(t.cfg, t.arrays(), precision="fp64")
+    prob.run()
+    lam, snr, cum, sweeps, _ = prob.pca(vectors=False)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(lam / lam0 - 1.0))
+    _say("  N %d, sweeps %d, lambda max rel %.3e" % (len(lam), sweeps, err))
+    assert len(lam) == {1: 144, 2: 818}[n_z]
+    assert err < 1e-9
+    assert np.max(np.abs(cum - cum0)) < 1e-9 * cum0[-1]
+    thr = 0.99 * cum0[-1]
+    k0 = int(np.searchsorted(cum0, thr) + 1)
+    k = int(np.searchsorted(cum, 0.99 * cum[-1]) + 1)
+    near = np.min(np.abs(cum0[max(0, k0 - 2):k0 + 1] - thr)) < 1e-8 * cum0[-1]
+    assert k == k0 or near
+    prob.close()
