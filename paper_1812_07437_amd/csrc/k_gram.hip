@@ -13,8 +13,9 @@
 //
 // Work decomposition: a workgroup owns one output tile (I >= J) of the lower
 // triangle and one contiguous slice of K: 256 x 256 for the bf16 variants
-// (8 wavefronts), 128 x 128 for f32 / f64 (4 wavefronts, 2 x 2).  Operands
-// are staged through LDS with the next slice prefetched into registers.
+// (8 wavefronts), 128 x 128 for f32 / f64 (4 wavefronts, 2 x 2).  The bf16
+// operands are copied from global memory straight into LDS one stage ahead;
+// the f32 / f64 ones are staged through registers, the next slice prefetched.
 // Slices of K (split-K) are reduced in a fixed order by a second kernel, so
 // results are deterministic.  A 256-row tile halves the operand bytes per
 // flop against a 128-row one, which matters because tiles that share a panel
@@ -85,40 +86,86 @@ __device__ __forceinline__ bool gram_work(int64_t n_work, int n_split, int nt, i
 
 // ===================================================================== bf16
 // 256 x 256 output tile per workgroup of NW wavefronts on a 2 x (NW/2) grid:
-// NW = 4 gives 128 x 128 per wavefront (4 x 4 blocks of
-// v_mfma_f32_32x32x16_bf16, one wavefront per SIMD); NW = 8 gives 128 x 64
-// (two per SIMD).  Larger wavefront tiles read fewer LDS bytes per MFMA.  K advances
-// in stages of 32 through a double-buffered LDS tile ([256 rows][32 bf16] =
-// 64 B per row and operand); stage s + 2 is fetched into registers while
-// stage s is multiplied.  Chunk c (16 B) of row r sits at slot
-// c ^ (((r >> 1) ^ (r >> 3)) & 3): the 16 consecutive rows that one MFMA
-// operand read touches at a time then fall on 16 distinct 16-byte bank
-// groups (and any 8 consecutive rows on 8), so operand reads and staging
-// writes are free of bank conflicts.
+// NW = 8 gives 128 x 64 per wavefront (4 x 2 blocks of
+// v_mfma_f32_32x32x16_bf16, two wavefronts per SIMD).  K advances in stages
+// of 32 through two LDS buffers ([256 rows][32 bf16] = 64 B per row, operand
+// and side).  Chunk c (16 B) of row r sits at slot c ^ (((r >> 1) ^ (r >> 3))
+// & 3): the 16 consecutive rows that one MFMA operand read touches at a time
+// then fall on 16 distinct 16-byte bank groups (and any 8 consecutive rows on
+// 8), so operand reads are free of bank conflicts.
+//
+// Operands go straight from global memory into LDS (buffer loads with the
+// LDS flag: lane l of a wavefront writes 16 bytes at the wavefront's LDS base
+// + 16 l).  A is k-blocked (GRAM_KB = 32 columns per block), so one stage of
+// a 256-row panel is a contiguous 16 KB block, and each 1 KB wavefront copy
+// (16 rows) covers whole cache lines.  Lane l fills LDS slot l & 3 of row
+// l >> 2 and fetches the chunk that the swizzle puts there (the swizzle is an
+// XOR, its own inverse).  Stage s + 1 is copied while stage s is multiplied;
+// the two buffers are distinct arrays and the loop is unrolled by two, so the
+// compiler can tell the buffer being filled from the one being read and does
+// not wait for the copy before reading.
 constexpr int T2 = 256;
 constexpr int BK2 = 32;
+static_assert(BK2 == GRAM_KB, "a Gram stage is one k-block of A");
 constexpr int GRAM_NW = 8;  // measured faster than 4 at both precisions
 
 __device__ __forceinline__ int swz2(int r, int c) { return r * BK2 + ((c ^ (((r >> 1) ^ (r >> 3)) & 3)) << 3); }
 
+// Wavefront w copies the 1 KB blocks idx = w PERW + q, q < PERW, of a stage's
+// NOPS x 2 x 16 blocks (operand, side, 16-row group).  PERW divides 16, so a
+// wavefront's blocks share operand and side, and its source is one panel.
+template <int NOPS, int NW>
+struct GramDma {
+  static constexpr int PERW = NOPS * 2 * 16 / NW;
+  static_assert(16 % PERW == 0, "a wavefront's blocks must share operand and side");
+  uint32_t off[PERW];   // byte offset of this lane's chunk in the 16 KB panel stage
+  const char *panel;    // the wavefront's panel at stage 0 (wavefront-uniform)
+  int64_t stage_bytes;  // distance between consecutive k-blocks of A
+  int blk0;
+  __device__ __forceinline__ void init(const uint16_t *Ahi, const uint16_t *Alo, int64_t r_pad, int64_t row0,
+                                       int64_t col0, int wave, int lane) {
+    blk0 = wave * PERW;
+    const int op = blk0 >> 5, side = (blk0 >> 4) & 1;
+    panel = (const char *)((op == 0 ? Ahi : Alo) + (side == 0 ? row0 : col0) * BK2);
+    stage_bytes = r_pad * BK2 * 2;
+#pragma unroll
+    for (int q = 0; q < PERW; ++q) {
+      const int r = ((blk0 + q) & 15) * 16 + (lane >> 2);
+      const int c = (lane & 3) ^ (((r >> 1) ^ (r >> 3)) & 3);
+      off[q] = (uint32_t)(r * BK2 * 2 + 16 * c);
+    }
+  }
+  // copy k-block kblk of the panel into buf; the copies are issued before
+  // anything that follows (the scheduler would otherwise sink them below the
+  // products, next to the wait for them)
+  __device__ __forceinline__ void issue(int64_t kblk, void *buf) const {
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(panel + kblk * stage_bytes), 0, T2 * BK2 * 2, 0x00020000);
+#pragma unroll
+    for (int q = 0; q < PERW; ++q)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsrc, (__attribute__((address_space(3))) void *)((char *)buf + (blk0 + q) * 1024), 16, off[q], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+};
+
 template <bool X3, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
-                                                  int64_t k_pad, int64_t lda, int64_t k_split, int n_split,
+                                                  int64_t k_pad, int64_t r_pad, int64_t k_split, int n_split,
                                                   int nt, int64_t n_work, float *__restrict__ out, int64_t ld,
                                                   int64_t part_stride) {
   constexpr int NOPS = X3 ? 2 : 1;  // hi (and lo)
-  __shared__ __attribute__((aligned(16))) uint16_t lds[2][NOPS][2][T2 * BK2];  // [buffer][op][I/J side]
+  __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];  // [op][I/J side]
+  __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   int I, J, split;
   if (!gram_work(n_work, n_split, nt, I, J, split)) return;
   const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
   const int64_t kb = (int64_t)split * k_split;
   const int64_t ke = min(k_pad, kb + k_split);
-  constexpr int NT = 64 * NW;          // threads
-  constexpr int WCOLS = 512 / NW;      // wavefront tile columns
-  constexpr int BJ = WCOLS / 32;       // 32-column blocks per wavefront
-  constexpr int PER = 1024 / NT;       // 16-byte chunks per thread, operand side and stage
+  constexpr int WCOLS = 512 / NW;  // wavefront tile columns
+  constexpr int BJ = WCOLS / 32;   // 32-column blocks per wavefront
   const int wr = (wave / (NW / 2)) * 128, wc = (wave % (NW / 2)) * WCOLS;  // wavefront sub-tile origin
 
   f32x16 acc[4][BJ];
@@ -129,36 +176,7 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
 
-  // one stage of one operand side: 256 rows x 4 chunks = 1024 chunks, PER
-  // per thread; chunk q: row q >> 2, chunk q & 3
-  u32x4 pre[NOPS][2][PER];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int op = 0; op < NOPS; ++op) {
-      const uint16_t *src = op == 0 ? Ahi : Alo;
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        const int64_t r0 = side == 0 ? row0 : col0;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int ch = tid + NT * q;
-          pre[op][side][q] = *(const u32x4 *)(src + (r0 + (ch >> 2)) * lda + k0 + 8 * (ch & 3));
-        }
-      }
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int op = 0; op < NOPS; ++op)
-#pragma unroll
-      for (int side = 0; side < 2; ++side)
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int ch = tid + NT * q;
-          *(u32x4 *)(&lds[buf][op][side][swz2(ch >> 2, ch & 3)]) = pre[op][side][q];
-        }
-  };
-  auto compute = [&](int buf) {
+  auto compute = [&](uint16_t (*buf)[2][T2 * BK2]) {
 #pragma unroll
     for (int kk = 0; kk < BK2; kk += 16) {
       // lane holds 8 consecutive k of row (lane & 31), k offset 8 * (lane >> 5)
@@ -168,10 +186,10 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
       for (int op = 0; op < NOPS; ++op) {
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk)
-          a[op][blk] = *(const bf16x8 *)(&lds[buf][op][0][swz2(wr + blk * 32 + (lane & 31), cidx)]);
+          a[op][blk] = *(const bf16x8 *)(&buf[op][0][swz2(wr + blk * 32 + (lane & 31), cidx)]);
 #pragma unroll
         for (int blk = 0; blk < BJ; ++blk)
-          b[op][blk] = *(const bf16x8 *)(&lds[buf][op][1][swz2(wc + blk * 32 + (lane & 31), cidx)]);
+          b[op][blk] = *(const bf16x8 *)(&buf[op][1][swz2(wc + blk * 32 + (lane & 31), cidx)]);
       }
       // products outermost, so consecutive MFMAs use different accumulators
 #pragma unroll
@@ -185,22 +203,27 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
     }
   };
 
-  // stage s is fetched into registers two stages ahead, copied to LDS buffer
-  // s % 2 one stage ahead, and multiplied from there
-  const int64_t n_st = (ke - kb) / BK2;
-  if (n_st > 0) {
-    gload(kb);
-    lstore(0);
-    if (n_st > 1) gload(kb + BK2);
+  GramDma<NOPS, NW> dma;
+  dma.init(Ahi, Alo, r_pad, row0, col0, wave, lane);
+  const int64_t n_st = (ke - kb) / BK2, kb0 = kb / BK2;
+  if (n_st > 0) dma.issue(kb0, lds0);
+  int64_t st = 0;
+  for (; st + 1 < n_st; st += 2) {
+    // this wavefront's copy of stage st is complete; after the barrier every
+    // wavefront's is, and no wavefront still reads the buffer refilled next
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
+    dma.issue(kb0 + st + 1, lds1);
+    compute(lds0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (st + 2 < n_st) dma.issue(kb0 + st + 2, lds0);
+    compute(lds1);
   }
-  for (int64_t st = 0; st < n_st; ++st) {
-    compute((int)(st & 1));
-    if (st + 1 < n_st) {
-      lstore((int)((st + 1) & 1));  // that buffer was last read before the previous barrier
-      if (st + 2 < n_st) gload(kb + (st + 2) * BK2);
-    }
+  if (st < n_st) {  // odd stage count: the last stage sits in buffer 0
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
+    compute(lds0);
   }
   // 32x32 accumulator layout: value v of lane l is row 8 (v/4) + 4 (l/32) + v%4, column l % 32
   float *dst = out + (int64_t)split * part_stride;
@@ -404,12 +427,14 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
   const int nti = (int)nt;
   switch (prec) {
     case WLC_BF16:
-      hipLaunchKernelGGL((k_gram_bf16<false, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0, (const uint16_t *)A1, g.k_pad,
-                         g.lda, ksplit, ns, nti, n_work, (float *)dst, g.ld_out, pstride);
+      hipLaunchKernelGGL((k_gram_bf16<false, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
+                         (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)dst, g.ld_out,
+                         pstride);
       break;
     case WLC_BF16X3:
-      hipLaunchKernelGGL((k_gram_bf16<true, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0, (const uint16_t *)A1, g.k_pad,
-                         g.lda, ksplit, ns, nti, n_work, (float *)dst, g.ld_out, pstride);
+      hipLaunchKernelGGL((k_gram_bf16<true, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
+                         (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)dst, g.ld_out,
+                         pstride);
       break;
     case WLC_FP32:
       hipLaunchKernelGGL(k_gram_x4<float>, grid, dim3(256), 0, s, (const float *)A0, g.k_pad, g.lda, ksplit, ns, nti,

@@ -458,7 +458,7 @@ constexpr int AB_ROWS = 16;
 template <int FMT>
 __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
                                                const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
-                                               int64_t k_pad, int64_t lda, void *A0, void *A1) {
+                                               int64_t k_pad, int64_t lda, int64_t r_pad, void *A0, void *A1) {
   const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
   if (k0 >= k_pad) return;
   const int64_t k_len = (int64_t)n_chi * n_m;
@@ -501,7 +501,9 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = 0.0;
     }
-    const size_t off = (size_t)row * lda + k0;
+    const size_t off = FMT == 1 || FMT == 2
+                           ? ((size_t)(k0 / GRAM_KB) * r_pad + row) * GRAM_KB + k0 % GRAM_KB
+                           : (size_t)row * lda + k0;
     if constexpr (FMT == 0) {
       double *o = (double *)A0 + off;
 #pragma unroll
@@ -533,10 +535,10 @@ void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double 
   // r_pad is a multiple of AB_ROWS (rows are padded to the Gram tile)
   const dim3 grid((unsigned)((k_pad / 8 + 255) / 256), (unsigned)((r_pad + AB_ROWS - 1) / AB_ROWS));
   switch (fmt) {
-    case 0: hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
-    case 1: hipLaunchKernelGGL(k_abuild<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
-    case 2: hipLaunchKernelGGL(k_abuild<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
-    default: hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1); break;
+    case 0: hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
+    case 1: hipLaunchKernelGGL(k_abuild<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
+    case 2: hipLaunchKernelGGL(k_abuild<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
+    default: hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
   }
 }
 

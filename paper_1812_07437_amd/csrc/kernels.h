@@ -33,7 +33,12 @@ void launch_gfactor(const DevTables &T, const int32_t *cfgT, int n_cfg, const Su
                     hipStream_t s);
 void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT, int64_t n_R, const double *Gmax,
                     double *Ts, int32_t *sexp, hipStream_t s);
-// fmt: 0 = f64, 1 = bf16 (hi only), 2 = bf16 hi + lo, 3 = f32
+// fmt: 0 = f64, 1 = bf16 (hi only), 2 = bf16 hi + lo, 3 = f32.  f64 and f32
+// are row-major with row pitch lda; bf16 operands are k-blocked: element
+// (r, k) at ((k / GRAM_KB) r_pad + r) GRAM_KB + k % GRAM_KB, so that the
+// GRAM_KB columns of a run of rows (one Gram stage of a row panel) are one
+// contiguous block (k_pad is a multiple of GRAM_KB).
+constexpr int GRAM_KB = 32;
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
                    int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s);
 
@@ -52,7 +57,7 @@ struct GramShape {
   int64_t r_pad;   // padded rows (multiple of the tile)
   int64_t k_pad;   // padded contraction length
   int64_t ld_out;  // leading dimension of the output
-  int64_t lda;     // row pitch of A in elements (>= k_pad)
+  int64_t lda;     // row pitch of A in elements (>= k_pad); bf16 operands are k-blocked instead
 };
 size_t gram_partial_bytes(int prec, const GramShape &g);
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
