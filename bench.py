@@ -58,19 +58,20 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(*names):
+def measured_traffic(*names, per=None):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     runs (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the record
     is missing or the kernel's source has changed since the counters were
     taken.  Several names are summed over their launches and divided by the
-    launches of the first (a kernel and its helper timed as one launch)."""
+    launches of those named in per (default: the first), e.g. a kernel and
+    its helper timed as one launch."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    total, launches = 0.0, None
+    total = 0.0
     for n in names:
         r = rec.get(n)
         if r is None or r.get("fetch_bytes_per_launch") is None or r.get("write_bytes_per_launch") is None:
@@ -79,7 +80,7 @@ def measured_traffic(*names):
             if hashlib.sha256(f.read()).hexdigest() != r["source_sha256"]:
                 return None
         total += (r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"]) * r["launches"]
-        launches = launches or r["launches"]
+    launches = sum(rec[n]["launches"] for n in (per or names[:1]))
     return dict(bytes_per_launch=total / launches, summary=rec[names[0]]["summary"])
 
 
@@ -462,8 +463,11 @@ def main():
     upd_ms = upd["ms"] / max(upd_frac_timed, 1e-9)
     upd_tf = upd["flops"] / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else 0.0
     if upd_ms >= ph["gram"]:
-        tr = measured_traffic("k_update2", "k_update_reduce")
-        roof = dict(bound="mfma", kernel="k_update2 (FP64 Cholesky block update, incl. split-k reduce)",
+        # every block update is timed, on 128 x 256 tiles (k_update2d) or
+        # 128 x 128 ones (k_update2<4>), with its split-k reduction
+        tr = measured_traffic("k_update2d", "k_update2", "k_update_reduce", per=("k_update2d", "k_update2"))
+        roof = dict(bound="mfma", kernel="k_update2d + k_update2<4> (FP64 Cholesky block update, incl. split-k "
+                    "reduce)",
                     achieved=upd_tf, peak=PEAK_TFLOPS["fp64"], unit="TFLOP/s", frac=upd_tf / PEAK_TFLOPS["fp64"],
                     traffic=tr["bytes_per_launch"] / 1e9 if tr else None, launches=upd["launches"],
                     avg_launch_ms=upd_ms / max(upd["launches"], 1), flops_per_step=upd["flops"])

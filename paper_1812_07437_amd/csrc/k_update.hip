@@ -1,14 +1,14 @@
 // Block update of the FP64 Cholesky factorisation:
 //   W[i][j] -= sum_{q in [k0, k1)} W[i][q] W[j][q],  i in [c0, r1), j in [c0, c1), i >= j,
-// on tiles of 128 rows by TC = 32 NW columns: NW = 4 wavefronts for 128 x 128
-// tiles, NW = 8 for 128 x 256 tiles that span a whole 256-wide panel, so that
-// each row slice is read once per launch (21.3 instead of 16 flops per
-// operand byte).  Each wavefront computes 64 x 64 on v_mfma_f64_16x16x4
-// (lane l holds row l % 16, k l / 16 of each operand; the accumulator value v
-// of lane l is row l / 16 + 4 v, column l % 16).  Operand slices are staged
-// through a double-buffered LDS tile in 16-wide k steps: step s + 1 is
-// copied to LDS and step s + 2 fetched into registers, then step s is
-// multiplied, with one barrier per step.  The register budget is capped at
+// on tiles of 128 rows by 128 or 256 columns: 128 x 256 tiles (8 wavefronts,
+// k_update2d) span a whole 256-wide panel, so that each row slice is read
+// once per launch (21.3 instead of 16 flops per operand byte); other shapes
+// go on 128 x 128 tiles (4 wavefronts, k_update2<4>).  Each wavefront
+// computes 64 x 64 on v_mfma_f64_16x16x4 (the accumulator value v of lane l
+// is row l / 16 + 4 v, column l % 16).  K advances in 16-wide steps through
+// two LDS buffers with one barrier per step: the wide kernel copies operands
+// from global memory straight into LDS one step ahead, the narrow one stages
+// them through registers two steps ahead.  The register budget is capped at
 // two wavefronts per SIMD.  A long k range may be split into slices whose
 // partial products go to a scratch buffer and are subtracted in a fixed order
 // by a second kernel, so results do not depend on scheduling.
@@ -37,6 +37,8 @@ __device__ __forceinline__ void tile_of(int64_t t, int tri, int64_t tcols, int64
   }
 }
 
+// Register-staged form: in each 4-wide k step lane l holds row l % 16, k
+// l / 16 of each operand; the LDS rows are padded by one element.
 template <int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update2(
     double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1, int tri_grid,
@@ -149,6 +151,122 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       }
 }
 
+// The 128 x 256 update with operands copied from global memory straight into
+// LDS (buffer loads with the LDS flag: lane l of a wavefront writes 16 bytes
+// at the wavefront's LDS base + 16 l), two buffers, stage s + 1 copied while
+// stage s is multiplied.  A stage holds 16 k of the 128 row-side and 256
+// column-side rows, 128 B per row, unpadded; 16-byte chunk c of row r sits
+// at slot c ^ ((r >> 1) & 7).  A wavefront copy fills 8 rows, lane l taking
+// slot l & 7 of row l >> 3 and fetching the chunk that the swizzle puts there.
+// Rows past the matrix read as zero: each side's buffer descriptor ends at
+// its last valid row.  Within a stage, lane group g = l / 16 holds k = 4 g ..
+// 4 g + 3 of its row (two 16-byte reads, free of bank conflicts), and MFMA
+// step j takes k = 4 g + j from every group; both operands use the same map,
+// so the 16 k of the stage are each summed once.
+constexpr int DROWS = UT2 + 2 * UT2;  // row side, then column side
+
+__device__ __forceinline__ int dslot(int r, int c) { return r * UBK + 2 * (c ^ ((r >> 1) & 7)); }
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update2d(
+    double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1, int n_split,
+    int64_t k_split, double *__restrict__ part) {
+  __shared__ __attribute__((aligned(16))) double lds0[DROWS * UBK];
+  __shared__ __attribute__((aligned(16))) double lds1[DROWS * UBK];
+  const int64_t ti = blockIdx.x / n_split;
+  const int split = blockIdx.x % n_split;
+  const int64_t i0 = c0 + ti * UT2, j0 = c0;
+  const int64_t kb = k0 + (int64_t)split * k_split;
+  const int64_t ke = min(k1, kb + k_split);
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = (wave / 4) * 64, wc = (wave % 4) * 64;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // copies: wavefront w takes the 8-row groups q * 8 + w, q < 6 (groups 0-15
+  // are the row side, 16-47 the column side)
+  uint32_t off[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int r = (q * 8 + wave) * 8 + (lane >> 3);     // LDS row
+    const int rs = q < 2 ? r : r - UT2;                 // row within its side
+    const int c = (lane & 7) ^ ((r >> 1) & 7);
+    off[q] = (uint32_t)(rs * ld * 8 + 16 * c);
+  }
+  const int64_t nA = min((int64_t)UT2, r1 - i0), nB = min((int64_t)(2 * UT2), c1 - j0);
+  auto issue = [&](int64_t k, double *buf) {
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(Wm + i0 * ld + k), 0, (int)(nA * ld * 8), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(Wm + j0 * ld + k), 0, (int)(nB * ld * 8), 0x00020000);
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          q < 2 ? ra : rb, (__attribute__((address_space(3))) void *)(buf + (q * 8 + wave) * 8 * UBK), 16, off[q], 0,
+          0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto compute = [&](const double *buf) {
+    const int g = lane >> 4;
+    double a[4][4], b[4][4];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const int ra = wr + blk * 16 + (lane & 15), rb = UT2 + wc + blk * 16 + (lane & 15);
+      const double2 a0 = *(const double2 *)&buf[dslot(ra, 2 * g)], a1 = *(const double2 *)&buf[dslot(ra, 2 * g + 1)];
+      const double2 b0 = *(const double2 *)&buf[dslot(rb, 2 * g)], b1 = *(const double2 *)&buf[dslot(rb, 2 * g + 1)];
+      a[blk][0] = a0.x; a[blk][1] = a0.y; a[blk][2] = a1.x; a[blk][3] = a1.y;
+      b[blk][0] = b0.x; b[blk][1] = b0.y; b[blk][2] = b1.x; b[blk][3] = b1.y;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][j], b[y][j], acc[x][y], 0, 0, 0);
+  };
+
+  const int64_t n_st = (ke - kb) / UBK;  // the host passes whole stages only
+  if (n_st > 0) issue(kb, lds0);
+  int64_t st = 0;
+  for (; st + 1 < n_st; st += 2) {
+    // this wavefront's copy of stage st is complete; after the barrier every
+    // wavefront's is, and no wavefront still reads the buffer refilled next
+    __builtin_amdgcn_sched_barrier(0);  // the previous stage's products stay ahead of the wait
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    issue(kb + (st + 1) * UBK, lds1);
+    compute(lds0);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (st + 2 < n_st) issue(kb + (st + 2) * UBK, lds0);
+    compute(lds1);
+  }
+  if (st < n_st) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    compute(lds0);
+  }
+  const int64_t pcols = c1 - c0;
+  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pcols : nullptr;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + wr + x * 16 + (lane >> 4) + 4 * v;
+        const int64_t j = j0 + wc + y * 16 + (lane & 15);
+        if (i < r1 && j < c1 && i >= j) {
+          if (pdst) pdst[(i - c0) * pcols + (j - c0)] = acc[x][y][v];
+          else Wm[i * ld + j] -= acc[x][y][v];
+        }
+      }
+}
+
 // W[i][j] -= sum_s part[s][i - c0][j - c0] for the lower part of the block.
 __global__ void k_update_reduce(double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int n_split,
                                 const double *__restrict__ part) {
@@ -175,7 +293,12 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
   }
   if (timed) (void)hipEventRecord(probe->ev[2 * probe->count], s);
   // a whole 256-wide panel below its diagonal block goes on 128 x 256 tiles
-  const bool wide = c1 - c0 > UT2 && c1 - c0 <= 2 * UT2 && r1 - c0 > 2 * UT2;
+  // (k_update2d: whole 16-wide stages, 16-byte aligned rows and a 256-row
+  // side within a buffer descriptor's 31-bit range, which the factorisation's
+  // 64-multiple k ranges and 8-multiple row pitch always give); anything else
+  // on 128 x 128 tiles
+  const bool wide = c1 - c0 > UT2 && c1 - c0 <= 2 * UT2 && r1 - c0 > 2 * UT2 && (k1 - k0) % UBK == 0 &&
+                    k0 % 2 == 0 && ld % 2 == 0 && 2 * UT2 * ld * 8 < ((int64_t)1 << 31);
   const int64_t tcw = wide ? 2 * UT2 : UT2;
   const int64_t tr = (r1 - c0 + UT2 - 1) / UT2, tc = (c1 - c0 + tcw - 1) / tcw;
   const int tri = !wide && tr == tc;
@@ -204,8 +327,8 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
   }
   const int64_t ksplit = ((k1 - k0 + UBK - 1) / UBK + ns - 1) / ns * UBK;
   if (wide)
-    hipLaunchKernelGGL(k_update2<8>, dim3((unsigned)(tiles * ns)), dim3(512), 0, s, Wm, ld, c0, r1, c1, k0, k1, tri,
-                       tc, ns, ksplit, part);
+    hipLaunchKernelGGL(k_update2d, dim3((unsigned)(tiles * ns)), dim3(512), 0, s, Wm, ld, c0, r1, c1, k0, k1, ns,
+                       ksplit, part);
   else
     hipLaunchKernelGGL(k_update2<4>, dim3((unsigned)(tiles * ns)), dim3(256), 0, s, Wm, ld, c0, r1, c1, k0, k1, tri,
                        tc, ns, ksplit, part);
