@@ -29,6 +29,7 @@
 // tile fetching its own panels from HBM.
 #include <hip/hip_runtime.h>
 
+#include "f64tile.h"
 #include "kernels.h"
 
 namespace wlc {
@@ -360,6 +361,56 @@ __global__ void k_gram_reduce(const T *__restrict__ part, int n_split, int64_t p
   }
 }
 
+// FP64 Gram on 128 x 256 tiles with the tile product of f64tile.h: tile
+// (I, J) covers rows [128 I, 128 I + 128) and columns [256 J, 256 J + 256)
+// with J <= I / 2, which covers every 128 x 128 tile of the lower triangle
+// (the diagonal ones with some entries above it, which the mirror
+// overwrites).  Tiles are numbered by pairs of tile rows: rows 2m and 2m + 1
+// hold m + 1 tiles each, so pair m starts at tile m (m + 1).  The rows are a
+// multiple of 256, so every tile lies inside them.
+__device__ __forceinline__ void f64_gram_tile(int64_t t, int &I, int &J) {
+  int64_t m = (int64_t)((sqrt(4.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((m + 1) * (m + 2) <= t) ++m;
+  while (m * (m + 1) > t) --m;
+  const int64_t u = t - m * (m + 1);
+  I = (int)(2 * m + u / (m + 1));
+  J = (int)(u % (m + 1));
+}
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gram_f64(
+    const double *__restrict__ A, int64_t k_pad, int64_t lda, int64_t k_split, int n_split, int64_t n_work,
+    double *__restrict__ out, int64_t ld, int64_t part_stride) {
+  // XCD x takes work items [x per, (x + 1) per), as in gram_work
+  const int64_t per = (int64_t)gridDim.x / N_XCD;
+  const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
+  if (w >= n_work) return;
+  const int split = (int)(w % n_split);
+  int I, J;
+  f64_gram_tile(w / n_split, I, J);
+  const int64_t row0 = (int64_t)I * FT_R, col0 = (int64_t)J * FT_S;
+  const int64_t kb = (int64_t)split * k_split;
+  const int64_t ke = min(k_pad, kb + k_split);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave / 4) * 64, wc = (wave % 4) * 64;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  f64_tile_product(A + row0 * lda, A + col0 * lda, lda, FT_R, FT_S, kb, (ke - kb) / FT_K, acc);
+  double *dst = out + (int64_t)split * part_stride;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = row0 + wr + x * 16 + (lane >> 4) + 4 * v;
+        const int64_t c = col0 + wc + y * 16 + (lane & 15);
+        dst[r * ld + c] = acc[x][y][v];
+      }
+}
+
 // Mirror of the lower triangle onto the upper one in 64 x 64 tiles (I >= J):
 // tile (I, J) is read row by row, transposed through LDS and written as tile
 // (J, I), so both sides stay coalesced.  On a diagonal tile only the entries
@@ -403,11 +454,22 @@ static int pick_split(int64_t n_tiles, int64_t k_pad, int bk) {
 static bool is_bf16(int prec) { return prec == WLC_BF16 || prec == WLC_BF16X3; }
 static int gram_tile(int prec) { return is_bf16(prec) ? T2 : TILE; }
 static int gram_bk(int prec) { return prec == WLC_FP64 ? 16 : (prec == WLC_FP32 ? 32 : BK2); }
+// the FP64 tile product needs even row pitch (16-byte chunks) and a 256-row
+// panel within one buffer descriptor's 31-bit range
+static bool f64_tiles(int prec, const GramShape &g) {
+  return prec == WLC_FP64 && g.lda % 2 == 0 && (int64_t)FT_S * g.lda * 8 < ((int64_t)1 << 31) && g.r_pad % FT_S == 0;
+}
+static int64_t gram_tile_count(int prec, const GramShape &g) {
+  if (f64_tiles(prec, g)) {
+    const int64_t pairs = g.r_pad / FT_S;
+    return pairs * (pairs + 1);
+  }
+  const int64_t nt = g.r_pad / gram_tile(prec);
+  return nt * (nt + 1) / 2;
+}
 
 size_t gram_partial_bytes(int prec, const GramShape &g) {
-  const int64_t nt = g.r_pad / gram_tile(prec);
-  const int64_t tiles = nt * (nt + 1) / 2;
-  const int s = pick_split(tiles, g.k_pad, gram_bk(prec));
+  const int s = pick_split(gram_tile_count(prec, g), g.k_pad, gram_bk(prec));
   if (s <= 1) return 0;
   const size_t el = prec == WLC_FP64 ? 8 : 4;
   return (size_t)s * g.r_pad * g.ld_out * el;
@@ -416,7 +478,7 @@ size_t gram_partial_bytes(int prec, const GramShape &g) {
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
                  hipStream_t s) {
   const int64_t nt = g.r_pad / gram_tile(prec);
-  const int64_t tiles = nt * (nt + 1) / 2;
+  const int64_t tiles = gram_tile_count(prec, g);
   const int bk = gram_bk(prec);
   const int ns = pick_split(tiles, g.k_pad, bk);
   int64_t ksplit = (g.k_pad / bk + ns - 1) / ns * bk;
@@ -441,6 +503,11 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
                          n_work, (float *)dst, g.ld_out, pstride);
       break;
     default:
+      if (f64_tiles(prec, g)) {
+        hipLaunchKernelGGL(k_gram_f64, grid, dim3(512), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, n_work,
+                           (double *)dst, g.ld_out, pstride);
+        break;
+      }
       hipLaunchKernelGGL(k_gram_x4<double>, grid, dim3(256), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, nti,
                          n_work, (double *)dst, g.ld_out, pstride);
       break;

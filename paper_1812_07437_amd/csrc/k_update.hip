@@ -16,6 +16,7 @@
 
 #include <algorithm>
 
+#include "f64tile.h"
 #include "kernels.h"
 
 namespace wlc {
@@ -151,105 +152,27 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
       }
 }
 
-// The 128 x 256 update with operands copied from global memory straight into
-// LDS (buffer loads with the LDS flag: lane l of a wavefront writes 16 bytes
-// at the wavefront's LDS base + 16 l), two buffers, stage s + 1 copied while
-// stage s is multiplied.  A stage holds 16 k of the 128 row-side and 256
-// column-side rows, 128 B per row, unpadded; 16-byte chunk c of row r sits
-// at slot c ^ ((r >> 1) & 7).  A wavefront copy fills 8 rows, lane l taking
-// slot l & 7 of row l >> 3 and fetching the chunk that the swizzle puts there.
-// Rows past the matrix read as zero: each side's buffer descriptor ends at
-// its last valid row.  Within a stage, lane group g = l / 16 holds k = 4 g ..
-// 4 g + 3 of its row (two 16-byte reads, free of bank conflicts), and MFMA
-// step j takes k = 4 g + j from every group; both operands use the same map,
-// so the 16 k of the stage are each summed once.
-constexpr int DROWS = UT2 + 2 * UT2;  // row side, then column side
-
-__device__ __forceinline__ int dslot(int r, int c) { return r * UBK + 2 * (c ^ ((r >> 1) & 7)); }
-
+// The 128 x 256 update: the tile product of f64tile.h on the row slice
+// [i0, i0 + 128) and the panel's columns [c0, c0 + 256), then the subtraction
+// (or the split-k partial store).
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_update2d(
     double *__restrict__ Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1, int n_split,
     int64_t k_split, double *__restrict__ part) {
-  __shared__ __attribute__((aligned(16))) double lds0[DROWS * UBK];
-  __shared__ __attribute__((aligned(16))) double lds1[DROWS * UBK];
   const int64_t ti = blockIdx.x / n_split;
   const int split = blockIdx.x % n_split;
   const int64_t i0 = c0 + ti * UT2, j0 = c0;
   const int64_t kb = k0 + (int64_t)split * k_split;
   const int64_t ke = min(k1, kb + k_split);
-  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave / 4) * 64, wc = (wave % 4) * 64;
   f64x4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-
-  // copies: wavefront w takes the 8-row groups q * 8 + w, q < 6 (groups 0-15
-  // are the row side, 16-47 the column side)
-  uint32_t off[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    const int r = (q * 8 + wave) * 8 + (lane >> 3);     // LDS row
-    const int rs = q < 2 ? r : r - UT2;                 // row within its side
-    const int c = (lane & 7) ^ ((r >> 1) & 7);
-    off[q] = (uint32_t)(rs * ld * 8 + 16 * c);
-  }
-  const int64_t nA = min((int64_t)UT2, r1 - i0), nB = min((int64_t)(2 * UT2), c1 - j0);
-  auto issue = [&](int64_t k, double *buf) {
-    const __amdgpu_buffer_rsrc_t ra =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(Wm + i0 * ld + k), 0, (int)(nA * ld * 8), 0x00020000);
-    const __amdgpu_buffer_rsrc_t rb =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(Wm + j0 * ld + k), 0, (int)(nB * ld * 8), 0x00020000);
-#pragma unroll
-    for (int q = 0; q < 6; ++q)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          q < 2 ? ra : rb, (__attribute__((address_space(3))) void *)(buf + (q * 8 + wave) * 8 * UBK), 16, off[q], 0,
-          0, 0);
-    __builtin_amdgcn_sched_barrier(0);
-  };
-  auto compute = [&](const double *buf) {
-    const int g = lane >> 4;
-    double a[4][4], b[4][4];
-#pragma unroll
-    for (int blk = 0; blk < 4; ++blk) {
-      const int ra = wr + blk * 16 + (lane & 15), rb = UT2 + wc + blk * 16 + (lane & 15);
-      const double2 a0 = *(const double2 *)&buf[dslot(ra, 2 * g)], a1 = *(const double2 *)&buf[dslot(ra, 2 * g + 1)];
-      const double2 b0 = *(const double2 *)&buf[dslot(rb, 2 * g)], b1 = *(const double2 *)&buf[dslot(rb, 2 * g + 1)];
-      a[blk][0] = a0.x; a[blk][1] = a0.y; a[blk][2] = a1.x; a[blk][3] = a1.y;
-      b[blk][0] = b0.x; b[blk][1] = b0.y; b[blk][2] = b1.x; b[blk][3] = b1.y;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][j], b[y][j], acc[x][y], 0, 0, 0);
-  };
-
-  const int64_t n_st = (ke - kb) / UBK;  // the host passes whole stages only
-  if (n_st > 0) issue(kb, lds0);
-  int64_t st = 0;
-  for (; st + 1 < n_st; st += 2) {
-    // this wavefront's copy of stage st is complete; after the barrier every
-    // wavefront's is, and no wavefront still reads the buffer refilled next
-    __builtin_amdgcn_sched_barrier(0);  // the previous stage's products stay ahead of the wait
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    __syncthreads();
-    issue(kb + (st + 1) * UBK, lds1);
-    compute(lds0);
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);
-    __syncthreads();
-    if (st + 2 < n_st) issue(kb + (st + 2) * UBK, lds0);
-    compute(lds1);
-  }
-  if (st < n_st) {
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);
-    __syncthreads();
-    compute(lds0);
-  }
+  // the host passes whole 16-wide steps only
+  f64_tile_product(Wm + i0 * ld, Wm + j0 * ld, ld, min((int64_t)FT_R, r1 - i0), min((int64_t)FT_S, c1 - j0), kb,
+                   (ke - kb) / FT_K, acc);
   const int64_t pcols = c1 - c0;
   double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pcols : nullptr;
 #pragma unroll
