@@ -447,18 +447,20 @@ void launch_twoleg(const DevTables &T, int n_ell, const double *U, double *G2, d
 }
 
 // ------------------------------------------------------------- A build
-// A[row][k], k = n * n_m + m, row-major [r_pad][lda]; rows >= n_R and
-// k >= n_chi * n_m are zero.  A row of A is T_row(chi_n) G_cfg(chi_n, M_m),
-// and consecutive rows mostly share their configuration, so each block holds
-// 8 consecutive k of G_cfg per thread in registers and writes them, times
-// T_row, for AB_ROWS consecutive rows, reloading G only where the
-// configuration changes.  The write traffic is the kernel's whole HBM cost.
+// A[row][k], k = n * n_m + m; rows >= n_R and k >= n_chi * n_m are zero.  A
+// row of A is T_row(chi_n) G_cfg(chi_n, M_m).  The write traffic is the
+// kernel's whole HBM cost.
+//
+// Row-major f64 / f32 ([r_pad][lda]): consecutive rows mostly share their
+// configuration, so each block holds 8 consecutive k of G_cfg per thread in
+// registers and writes them, times T_row, for AB_ROWS consecutive rows,
+// reloading G only where the configuration changes.
 constexpr int AB_ROWS = 16;
 
 template <int FMT>
 __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
                                                const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
-                                               int64_t k_pad, int64_t lda, int64_t r_pad, void *A0, void *A1) {
+                                               int64_t k_pad, int64_t lda, void *A0, void *A1) {
   const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
   if (k0 >= k_pad) return;
   const int64_t k_len = (int64_t)n_chi * n_m;
@@ -501,9 +503,7 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = 0.0;
     }
-    const size_t off = FMT == 1 || FMT == 2
-                           ? ((size_t)(k0 / GRAM_KB) * r_pad + row) * GRAM_KB + k0 % GRAM_KB
-                           : (size_t)row * lda + k0;
+    const size_t off = (size_t)row * lda + k0;
     if constexpr (FMT == 0) {
       double *o = (double *)A0 + off;
 #pragma unroll
@@ -512,34 +512,104 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
       float *o = (float *)A0 + off;
       *(float4 *)o = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
       *(float4 *)(o + 4) = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
-    } else {
-      uint32_t hi[4], lo[4];
+    }
+  }
+}
+
+// k-blocked bf16 (hi, and lo for fmt 2; see launch_abuild): a 256-thread
+// block covers 64 rows and AB_KB consecutive 32-column k-blocks; in each,
+// lane l of a wavefront converts 8 consecutive k of row l / 4 (chunk l % 4),
+// so the wavefront writes 16 whole rows of the block, 1 KB contiguous per
+// operand.
+constexpr int AB_KB = 8;
+
+template <int FMT>
+__global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
+                                                   const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
+                                                   int64_t k_pad, int64_t r_pad, uint16_t *__restrict__ A0,
+                                                   uint16_t *__restrict__ A1) {
+  const int64_t row = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 2);
+  const int chunk = threadIdx.x & 3;
+  const int64_t k_len = (int64_t)n_chi * n_m;
+  const bool live = row < n_R;
+  const int c = live ? rowR[4 * row] : 0;
+  const double *Gc = G + (size_t)c * k_len;
+  const double *Tr = Ts + (size_t)(live ? row : 0) * n_chi;
+  const bool pairs = (k_len & 1) == 0;  // 16-byte aligned pairs of G
+  for (int q = 0; q < AB_KB; ++q) {
+    const int64_t kblk = (int64_t)blockIdx.x * AB_KB + q;
+    const int64_t k0 = kblk * GRAM_KB + 8 * chunk;
+    if (k0 >= k_pad) break;
+    float x[8];
+    if (live && k0 + 8 <= k_len) {
+      double g[8];
+      if (pairs) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float x0 = (float)v[2 * q], x1 = (float)v[2 * q + 1];
-        const uint16_t h0 = f32_to_bf16_rne(x0), h1 = f32_to_bf16_rne(x1);
-        hi[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-        if constexpr (FMT == 2) {
-          const uint16_t g0 = f32_to_bf16_rne(x0 - bf16_to_f32(h0)), g1 = f32_to_bf16_rne(x1 - bf16_to_f32(h1));
-          lo[q] = (uint32_t)g0 | ((uint32_t)g1 << 16);
+        for (int e = 0; e < 8; e += 2) {
+          const double2 t = *(const double2 *)(Gc + k0 + e);
+          g[e] = t.x;
+          g[e + 1] = t.y;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) g[e] = Gc[k0 + e];
+      }
+      // chi node of each k: one division, then a step across the node edge
+      int n = (int)(k0 / n_m), m = (int)(k0 % n_m);
+      double tn = Tr[n];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        x[e] = (float)(tn * g[e]);
+        if (++m == n_m && e < 7) {
+          m = 0;
+          ++n;
+          tn = Tr[n];  // k0 + e + 1 < k_len, so n < n_chi
         }
       }
-      *(u32x4 *)((uint16_t *)A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
-      if constexpr (FMT == 2) *(u32x4 *)((uint16_t *)A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t k = k0 + e;
+        x[e] = live && k < k_len ? (float)(Tr[k / n_m] * Gc[k]) : 0.0f;
+      }
     }
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint16_t h0 = f32_to_bf16_rne(x[2 * e]), h1 = f32_to_bf16_rne(x[2 * e + 1]);
+      hi[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      if constexpr (FMT == 2) {
+        const uint16_t g0 = f32_to_bf16_rne(x[2 * e] - bf16_to_f32(h0));
+        const uint16_t g1 = f32_to_bf16_rne(x[2 * e + 1] - bf16_to_f32(h1));
+        lo[e] = (uint32_t)g0 | ((uint32_t)g1 << 16);
+      }
+    }
+    const size_t off = ((size_t)kblk * r_pad + row) * GRAM_KB + 8 * chunk;
+    *(u32x4 *)(A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
+    if constexpr (FMT == 2) *(u32x4 *)(A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
   }
 }
 
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
                    int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s) {
+  if (fmt == 1 || fmt == 2) {
+    // r_pad is a multiple of 64 and k_pad of GRAM_KB (rows are padded to the
+    // Gram tile, columns to 64)
+    const dim3 grid((unsigned)((k_pad / GRAM_KB + AB_KB - 1) / AB_KB), (unsigned)(r_pad / 64));
+    if (fmt == 1)
+      hipLaunchKernelGGL(k_abuild_blk<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, r_pad,
+                         (uint16_t *)A0, (uint16_t *)A1);
+    else
+      hipLaunchKernelGGL(k_abuild_blk<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, r_pad,
+                         (uint16_t *)A0, (uint16_t *)A1);
+    return;
+  }
   // r_pad is a multiple of AB_ROWS (rows are padded to the Gram tile)
   const dim3 grid((unsigned)((k_pad / 8 + 255) / 256), (unsigned)((r_pad + AB_ROWS - 1) / AB_ROWS));
-  switch (fmt) {
-    case 0: hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
-    case 1: hipLaunchKernelGGL(k_abuild<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
-    case 2: hipLaunchKernelGGL(k_abuild<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
-    default: hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, r_pad, A0, A1); break;
-  }
+  if (fmt == 0)
+    hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1);
+  else
+    hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1);
 }
 
 }  // namespace wlc
