@@ -76,9 +76,12 @@ def measured_traffic(*names, per=None):
         r = rec.get(n)
         if r is None or r.get("fetch_bytes_per_launch") is None or r.get("write_bytes_per_launch") is None:
             return None
-        with open(os.path.join(ROOT, r["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != r["source_sha256"]:
-                return None
+        h = hashlib.sha256()
+        for src in r["source"].split("+"):  # several sources hash as one text
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != r["source_sha256"]:
+            return None
         total += (r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"]) * r["launches"]
     launches = sum(rec[n]["launches"] for n in (per or names[:1]))
     return dict(bytes_per_launch=total / launches, summary=rec[names[0]]["summary"])

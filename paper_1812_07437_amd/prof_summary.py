@@ -20,8 +20,9 @@ largest ``__amd_rocclr_copyBuffer`` dispatch of the run (the benchmark's
 
 ``--traffic-json`` records, for the kernels named with ``--record``, the
 scaled fetch and write bytes per launch together with the SHA-256 of the
-kernel's source file, so that a reader can tell whether the figures still
-describe the source as it stands.
+kernel's source files (several joined with ``+``, hashed in that order as
+one text), so that a reader can tell whether the figures still describe the
+source as it stands.
 
 Example (from the repository root, after the four profiling runs)::
 
@@ -98,9 +99,12 @@ def scale(vals):
     return 1048576.0 / max(vals[COPY])  # KiB in 1 GiB
 
 
-def sha256(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def sha256(paths):
+    h = hashlib.sha256()
+    for path in paths.split("+"):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def main():
