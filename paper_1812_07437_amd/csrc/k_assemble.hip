@@ -151,17 +151,23 @@ void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hi
 
 // 64 x 64 output tiles (I >= J); each thread computes 16 entries of one
 // column, the transposed copy goes through LDS so both halves are written
-// with contiguous rows.
+// with contiguous rows.  Tiles are numbered row-major over the triangle and
+// each XCD (workgroup b runs on XCD b mod 8, each XCD has its own L2) takes
+// a contiguous run of them, so the one-halo rows of a tile row are fetched
+// into one L2 instead of all eight.
 constexpr int AT = 64;
+constexpr int ASM_XCD = 8;
 
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__restrict__ row_exp2,
-                                                  OutT *__restrict__ C) {
+                                                  OutT *__restrict__ C, int64_t n_tiles) {
   __shared__ double tileT[AT][AT + 1];
   __shared__ int32_t rowA[AT][8], rowB[AT][8];
   __shared__ int32_t tA[AT], tB[AT], sA[AT], sB[AT];
   __shared__ double rA[AT], rB[AT];
-  const int64_t t = blockIdx.x;
+  const int64_t per = (int64_t)gridDim.x / ASM_XCD;
+  const int64_t t = (int64_t)(blockIdx.x % ASM_XCD) * per + blockIdx.x / ASM_XCD;
+  if (t >= n_tiles) return;  // grid padding (whole workgroup)
   int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
   while ((i + 1) * (i + 2) / 2 <= t) ++i;
   while (i * (i + 1) / 2 > t) --i;
@@ -220,10 +226,11 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__re
 void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s) {
   const int64_t nt = (a.n + AT - 1) / AT;
   const int64_t tiles = nt * (nt + 1) / 2;
+  const dim3 grid((unsigned)((tiles + ASM_XCD - 1) / ASM_XCD * ASM_XCD));
   if (c_f32)
-    hipLaunchKernelGGL(k_assemble<float>, dim3((unsigned)tiles), dim3(256), 0, s, a, row_exp2, (float *)C);
+    hipLaunchKernelGGL(k_assemble<float>, grid, dim3(256), 0, s, a, row_exp2, (float *)C, tiles);
   else
-    hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)tiles), dim3(256), 0, s, a, row_exp2, (double *)C);
+    hipLaunchKernelGGL(k_assemble<double>, grid, dim3(256), 0, s, a, row_exp2, (double *)C, tiles);
 }
 
 }  // namespace wlc

@@ -23,18 +23,24 @@ constexpr int NB_OUT = 256;  // outer panel width
 constexpr int64_t PART_ROWS = 524288;  // split-k scratch: slices x rows of 256 doubles
 
 // ------------------------------------------------------------- prepare
-// Lower triangle of M from the scaled covariance (f32 or f64) and d.
+// Lower triangle of M from the scaled covariance (f32 or f64) and d: one
+// block per row and PREP_COLS columns, blocks right of the row's end exit.
+constexpr int PREP_COLS = 2048;
 template <typename InT>
 __global__ void k_chol_prep(const InT *__restrict__ C, const int32_t *__restrict__ t, const double *__restrict__ d,
                             const int32_t *__restrict__ perm, int64_t n, int64_t ld, int64_t row_off,
                             double *__restrict__ Wm) {
   const int64_t i = row_off + blockIdx.y;  // row of M, 0..n
-  if (i > n) return;
+  const int64_t jb = (int64_t)blockIdx.x * PREP_COLS;
+  if (i > n || jb > i) return;  // the block lies right of the row's last entry
   const int64_t pi = perm && i < n ? perm[i] : i;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= i && j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t pj = perm ? perm[j] : j;
-    Wm[i * ld + j] = i < n ? (double)C[pi * n + pj] : ldexp(d[pj], t[pj]);
+#pragma unroll
+  for (int q = 0; q < PREP_COLS / 256; ++q) {
+    const int64_t j = jb + q * 256 + threadIdx.x;
+    if (j <= i && j < n) {
+      const int64_t pj = perm ? perm[j] : j;
+      Wm[i * ld + j] = i < n ? (double)C[pi * n + pj] : ldexp(d[pj], t[pj]);
+    }
   }
 }
 
@@ -42,7 +48,7 @@ void launch_chol_prep(const void *C, int c_f32, const int32_t *row_exp2, const d
                       double *Wm, hipStream_t s, const int32_t *perm) {
   for (int64_t r0 = 0; r0 <= n; r0 += 65535) {
     const int64_t rows = std::min<int64_t>(65535, n + 1 - r0);
-    const dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 512), (unsigned)rows);
+    const dim3 grid((unsigned)((n + PREP_COLS - 1) / PREP_COLS), (unsigned)rows);
     if (c_f32)
       hipLaunchKernelGGL(k_chol_prep<float>, grid, dim3(256), 0, s, (const float *)C, row_exp2, d, perm, n, ld, r0,
                          Wm);
