@@ -398,6 +398,109 @@ void launch_pca_init(const double *Wm, int64_t ld, const int32_t *t, int64_t n, 
   hipLaunchKernelGGL(k_pca_init, grid, dim3(256), 0, s, Wm, ld, t, n, n_pad, X, V, y);
 }
 
+// Direct-to-LDS form of the same product, for n_pad^2 8 < 2^31 (every row
+// offset fits a buffer load's 32-bit offset).  Q's fragments stay in
+// registers; the pair's 64 rows are copied from global memory straight into
+// LDS (buffer loads with the LDS flag: lane l of a wavefront writes 16 bytes
+// at the wavefront's LDS base + 16 l), one 64-column chunk ahead, into two
+// buffers of [64 rows][64 doubles], unpadded, with the 16-byte chunk s of
+// row l at slot s ^ (8 (l & 1)): the four rows one MFMA operand read touches
+// fall on alternate halves of the banks.  A wavefront copy fills two rows.
+constexpr int ACD = 8;  // 64-column chunks per workgroup
+
+__device__ __forceinline__ int apply_slot(int l, int col) { return l * PR + 2 * ((col >> 1) ^ (8 * (l & 1))) + (col & 1); }
+
+__global__ __launch_bounds__(256) void k_pca_apply_d(double *__restrict__ X, double *__restrict__ V, int64_t n_pad,
+                                                     int n_blk, int r, const double *__restrict__ Qg,
+                                                     const int32_t *__restrict__ rot) {
+  __shared__ __attribute__((aligned(16))) double st0[PR * PR];
+  __shared__ __attribute__((aligned(16))) double st1[PR * PR];
+  const int pi = blockIdx.x;
+  if (!rot[pi]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int bp = rr_at(pi, r, n_blk), bq = rr_at(n_blk - 1 - pi, r, n_blk);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  double *Y = blockIdx.z == 0 ? X : V;
+  // Q fragments: step kk, block x: Q[kk + lane / 16][wr + 16 x + lane % 16]
+  const double *q = Qg + (int64_t)pi * PR * PR;
+  double qa[PR / 4][2];
+#pragma unroll
+  for (int kk = 0; kk < PR / 4; ++kk)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) qa[kk][x] = q[(4 * kk + (lane >> 4)) * PR + wr + x * 16 + (lane & 15)];
+  // copies: wavefront w fills LDS rows 2 (8 i + w) + lane / 32 ... for i < 8
+  uint32_t off[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int l = 2 * (i * 4 + wave) + (lane >> 5);
+    const int sl = lane & 31;
+    off[i] = (uint32_t)((pair_row(bp, bq, l) * n_pad + 2 * (sl ^ (8 * (l & 1)))) * 8);
+  }
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)Y, 0, (int)(n_pad * n_pad * 8), 0x00020000);
+  const int64_t cbase = (int64_t)blockIdx.y * ACD * PR;
+  const int nch = (int)min((int64_t)ACD, (n_pad - cbase) / PR);
+  auto issue = [&](int ci, double *buf) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsrc, (__attribute__((address_space(3))) void *)(buf + (i * 4 + wave) * 2 * PR), 16, off[i],
+          (int)((cbase + (int64_t)ci * PR) * 8), 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto compute = [&](const double *buf, int ci) {
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // out[j][c] = sum_l Q[l][j] stage[l][c]
+#pragma unroll
+    for (int kk = 0; kk < PR / 4; ++kk) {
+      const int l = 4 * kk + (lane >> 4);
+      double b[2];
+#pragma unroll
+      for (int z = 0; z < 2; ++z) b[z] = buf[apply_slot(l, wc + z * 16 + (lane & 15))];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[kk][x], b[z], acc[x][z], 0, 0, 0);
+    }
+    const int64_t c0 = cbase + (int64_t)ci * PR;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int z = 0; z < 2; ++z)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = wr + x * 16 + (lane >> 4) + 4 * v, c = wc + z * 16 + (lane & 15);
+          Y[pair_row(bp, bq, j) * n_pad + c0 + c] = acc[x][z][v];
+        }
+  };
+  // the chunk written back is never one being copied (the copies run one
+  // chunk ahead, on other columns)
+  if (nch > 0) issue(0, st0);
+  int ci = 0;
+  for (; ci + 1 < nch; ci += 2) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's copy of chunk ci
+    __syncthreads();
+    issue(ci + 1, st1);
+    compute(st0, ci);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (ci + 2 < nch) issue(ci + 2, st0);
+    compute(st1, ci + 1);
+  }
+  if (ci < nch) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    compute(st0, ci);
+  }
+}
+
 // Column slices of the Gram: enough workgroups to cover the chip, each
 // slice a multiple of 64 columns.
 int pca_slices(int64_t n_pad) {
@@ -413,9 +516,12 @@ void launch_pca_round(double *X, double *V, int64_t n_pad, int r, double tol, in
   hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
                      n_pad / ks, part);
   hipLaunchKernelGGL(k_pca_rot, dim3((unsigned)pairs), dim3(RT), 0, s, part, ks, tol, max_inner, Qg, rot, conv);
-  hipLaunchKernelGGL(k_pca_apply, dim3((unsigned)pairs, (unsigned)((n_pad / PR + AC - 1) / AC), V ? 2u : 1u),
-                     dim3(256), 0, s, X, V,
-                     n_pad, n_blk, r, Qg, rot);
+  if (n_pad * n_pad * 8 < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(k_pca_apply_d, dim3((unsigned)pairs, (unsigned)((n_pad / PR + ACD - 1) / ACD), V ? 2u : 1u),
+                       dim3(256), 0, s, X, V, n_pad, n_blk, r, Qg, rot);
+  else
+    hipLaunchKernelGGL(k_pca_apply, dim3((unsigned)pairs, (unsigned)((n_pad / PR + AC - 1) / AC), V ? 2u : 1u),
+                       dim3(256), 0, s, X, V, n_pad, n_blk, r, Qg, rot);
 }
 
 void launch_pca_finish(const double *X, const double *y, const double *Vr, int64_t n, int64_t n_pad, double *lam,
