@@ -127,6 +127,91 @@ __global__ __launch_bounds__(256) void k_pca_gram(const double *__restrict__ X, 
         P[(wr + x * 16 + (lane >> 4) + 4 * v) * PR + wc + z * 16 + (lane & 15)] = acc[x][z][v];
 }
 
+// Direct-to-LDS form of the Gram, for n_pad^2 8 < 2^31: the pair's 64 rows
+// are copied one 64-column chunk ahead into two LDS buffers of [64 rows][64
+// doubles], unpadded, with the 16-byte chunk s of row l at slot s ^ (l & 15),
+// so the 16 consecutive rows one MFMA operand read touches at one column
+// fall on 16 distinct bank groups.  A wavefront copy fills two rows.
+__device__ __forceinline__ int gram_slot(int l, int k) { return l * PR + 2 * ((k >> 1) ^ (l & 15)) + (k & 1); }
+
+__global__ __launch_bounds__(256) void k_pca_gram_d(const double *__restrict__ X, int64_t n_pad, int n_blk, int r,
+                                                    int64_t cols, double *__restrict__ part) {
+  __shared__ __attribute__((aligned(16))) double st0[PR * PR];
+  __shared__ __attribute__((aligned(16))) double st1[PR * PR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int pi = blockIdx.x, ks = blockIdx.y;
+  const int bp = rr_at(pi, r, n_blk), bq = rr_at(n_blk - 1 - pi, r, n_blk);
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int64_t c0 = (int64_t)ks * cols;
+  const int nch = (int)(cols / PR);
+  uint32_t off[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int l = 2 * (i * 4 + wave) + (lane >> 5);
+    off[i] = (uint32_t)((pair_row(bp, bq, l) * n_pad + 2 * ((lane & 31) ^ (l & 15))) * 8);
+  }
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)X, 0, (int)(n_pad * n_pad * 8), 0x00020000);
+  auto issue = [&](int ci, double *buf) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rsrc, (__attribute__((address_space(3))) void *)(buf + (i * 4 + wave) * 2 * PR), 16, off[i],
+          (int)((c0 + (int64_t)ci * PR) * 8), 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto compute = [&](const double *buf) {
+#pragma unroll
+    for (int kk = 0; kk < PR; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = buf[gram_slot(wr + x * 16 + (lane & 15), k)];
+        b[x] = buf[gram_slot(wc + x * 16 + (lane & 15), k)];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
+    }
+  };
+  if (nch > 0) issue(0, st0);
+  int ci = 0;
+  for (; ci + 1 < nch; ci += 2) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's copy of chunk ci
+    __syncthreads();
+    issue(ci + 1, st1);
+    compute(st0);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (ci + 2 < nch) issue(ci + 2, st0);
+    compute(st1);
+  }
+  if (ci < nch) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    compute(st0);
+  }
+  // accumulator value v of lane l: row l / 16 + 4 v, column l % 16
+  double *P = part + ((int64_t)pi * gridDim.y + ks) * PR * PR;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        P[(wr + x * 16 + (lane >> 4) + 4 * v) * PR + wc + z * 16 + (lane & 15)] = acc[x][z][v];
+}
+
 constexpr int RT = 1024;  // threads of the rotation kernel: one 2 x 2 block each per inner step
 
 __global__ __launch_bounds__(RT) void k_pca_rot(const double *__restrict__ part, int n_ks, double tol, int max_inner,
@@ -513,8 +598,12 @@ int pca_slices(int64_t n_pad) {
 void launch_pca_round(double *X, double *V, int64_t n_pad, int r, double tol, int max_inner, double *conv,
                       double *part, double *Qg, int32_t *rot, hipStream_t s) {
   const int n_blk = (int)(n_pad / PB), pairs = n_blk / 2, ks = pca_slices(n_pad);
-  hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
-                     n_pad / ks, part);
+  if (n_pad * n_pad * 8 < ((int64_t)1 << 31))  // slices are multiples of 64 columns
+    hipLaunchKernelGGL(k_pca_gram_d, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
+                       n_pad / ks, part);
+  else
+    hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
+                       n_pad / ks, part);
   hipLaunchKernelGGL(k_pca_rot, dim3((unsigned)pairs), dim3(RT), 0, s, part, ks, tol, max_inner, Qg, rot, conv);
   if (n_pad * n_pad * 8 < ((int64_t)1 << 31))
     hipLaunchKernelGGL(k_pca_apply_d, dim3((unsigned)pairs, (unsigned)((n_pad / PR + ACD - 1) / ACD), V ? 2u : 1u),
