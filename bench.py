@@ -303,8 +303,8 @@ def serving(n_req, budget_gb, slots, precisions, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the covariance and "
+              "its Cholesky run on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
