@@ -287,19 +287,6 @@ struct WbArgs {
 constexpr int WK = 16;
 constexpr int WLD = WK + 1;
 
-__device__ __forceinline__ double lblk(const WbArgs &a, int64_t h, int64_t e) {
-  // L[h][e]: nonzero only inside one block, on or below its diagonal
-  const int ch = a.B.blk(h);
-  if (ch != a.B.blk(e) || h < e) return 0.0;
-  const int64_t b0 = a.B.start(ch);
-  return a.Gb[a.B.off(ch) + (h - b0) * a.B.size(ch) + (e - b0)];
-}
-
-__device__ __forceinline__ double mhat(const WbArgs &a, int64_t g, int64_t h) {
-  const double v = a.gm_f32 ? (double)((const float *)a.Gm)[g * a.ld_g + h] : ((const double *)a.Gm)[g * a.ld_g + h];
-  return ldexp(v, -(a.sexp[g] + a.sexp[h] + a.tau[g] + a.tau[h])) * a.inv_omega + a.sigma_b2 * a.rhat[g] * a.rhat[h];
-}
-
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
   __shared__ double lds[2][64 * WLD];
@@ -330,7 +317,34 @@ __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // Per loaded element j of this thread: its row r = q / WK of the tile is
+  // fixed, so the block facts of the L row (e in MODE 0, f in MODE 1) and
+  // the scale of the Mhat row f (MODE 0) are taken once here, and the k
+  // loop does no index division.
   double pa[4], pb[4];
+  int64_t lb0[4], lb1[4], lbase[4];  // block [lb0, lb1) holding the L row, Gb index of L[lb0][row]
+  int lsz[4];
+  double fscale[4], frh[4];          // MODE 0: 2^-(s_f + tau_f) / Omega and sigma_b^2 rhat_f
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = (tid + 256 * j) / WK;
+    const int64_t lr = (MODE == 0 ? e0 : f0) + r;  // the row whose L column is read
+    lb0[j] = lb1[j] = lbase[j] = 0;
+    lsz[j] = 0;
+    if (lr < nR) {
+      const int c = a.B.blk(lr);
+      lb0[j] = a.B.start(c);
+      lsz[j] = a.B.size(c);
+      lb1[j] = lb0[j] + lsz[j];
+      lbase[j] = a.B.off(c) + (lr - lb0[j]);
+    }
+    fscale[j] = frh[j] = 0.0;
+    if (MODE == 0 && f0 + r < nR) {
+      const int64_t f = f0 + r;
+      fscale[j] = ldexp(a.inv_omega, -(a.sexp[f] + a.tau[f]));
+      frh[j] = a.sigma_b2 * a.rhat[f];
+    }
+  }
   auto gload = [&](int64_t kq) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -338,14 +352,21 @@ __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
       const int r = q / WK;
       const int64_t k = kq + q % WK;
       const int64_t e = e0 + r, f = f0 + r;
+      const int64_t lr = MODE == 0 ? e : f;
+      // L[k][lr]: nonzero only inside lr's block, on or below its diagonal
+      const double lv = (k >= lr && k < lb1[j]) ? a.Gb[lbase[j] + (k - lb0[j]) * lsz[j]] : 0.0;
       double va = 0.0, vb = 0.0;
       if (k < k1) {
         if (MODE == 0) {
-          if (e < nR) va = lblk(a, k, e);
-          if (f < nR) vb = mhat(a, f, k);
+          va = lv;
+          if (f < nR) {
+            const double g = a.gm_f32 ? (double)((const float *)a.Gm)[f * a.ld_g + k]
+                                      : ((const double *)a.Gm)[f * a.ld_g + k];
+            vb = ldexp(g * fscale[j], -(a.sexp[k] + a.tau[k])) + frh[j] * a.rhat[k];
+          }
         } else {
           if (e < nR) va = a.T[e * a.ld_t + k];
-          if (f < nR) vb = lblk(a, k, f);
+          vb = lv;
         }
       }
       pa[j] = va;
