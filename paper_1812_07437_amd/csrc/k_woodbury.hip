@@ -346,11 +346,19 @@ __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
     }
   }
   auto gload = [&](int64_t kq) {
+    // every element of this thread sits in column k = kq + tid % WK of the
+    // stage, so the column's Mhat factors are loaded once
+    const int64_t k = kq + tid % WK;
+    int sk = 0;
+    double rk = 0.0;
+    if (MODE == 0 && k < k1) {
+      sk = a.sexp[k] + a.tau[k];
+      rk = a.rhat[k];
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = tid + 256 * j;
       const int r = q / WK;
-      const int64_t k = kq + q % WK;
       const int64_t e = e0 + r, f = f0 + r;
       const int64_t lr = MODE == 0 ? e : f;
       // L[k][lr]: nonzero only inside lr's block, on or below its diagonal
@@ -362,7 +370,7 @@ __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
           if (f < nR) {
             const double g = a.gm_f32 ? (double)((const float *)a.Gm)[f * a.ld_g + k]
                                       : ((const double *)a.Gm)[f * a.ld_g + k];
-            vb = ldexp(g * fscale[j], -(a.sexp[k] + a.tau[k])) + frh[j] * a.rhat[k];
+            vb = ldexp(g * fscale[j], -sk) + frh[j] * rk;
           }
         } else {
           if (e < nR) va = a.T[e * a.ld_t + k];
