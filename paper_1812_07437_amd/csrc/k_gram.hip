@@ -75,14 +75,31 @@ __device__ __forceinline__ void sb_tile(int64_t t, int nt, int &I, int &J) {
 }
 
 // Workgroup -> (tile, split) for a grid padded to a multiple of N_XCD: XCD x
-// takes work items [x per, (x + 1) per).  Returns false for padding.
+// takes work items [x per, (x + 1) per).  With split K, work items run over
+// groups of GS consecutive tiles (super-block order), slice-outer within a
+// group, so the workgroups resident on an XCD together multiply the same k
+// slice of a few shared panels; shorter work items also keep them closer in
+// step, so the panels are shared through L2.  Returns false for padding.
+constexpr int GS = 32;
+
 __device__ __forceinline__ bool gram_work(int64_t n_work, int n_split, int nt, int &I, int &J, int &split) {
   const int64_t per = (int64_t)gridDim.x / N_XCD;
   const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
   if (w >= n_work) return false;
-  split = (int)(w % n_split);
-  sb_tile(w / n_split, nt, I, J);
+  const int64_t n_tiles = n_work / n_split;
+  const int64_t grp = w / ((int64_t)GS * n_split), base = grp * GS;
+  const int64_t gsz = n_tiles - base < GS ? n_tiles - base : GS;
+  const int64_t u = w - grp * GS * n_split;
+  split = (int)(u / gsz);
+  sb_tile(base + u % gsz, nt, I, J);
   return true;
+}
+
+// Slice 0 of a split-K product goes straight to the output, slice s > 0 to
+// partial buffer s - 1; the reduction adds the partials in slice order.
+template <typename T>
+__device__ __forceinline__ T *gram_dst(T *out, T *partial, int split, int64_t part_stride) {
+  return split == 0 ? out : partial + (int64_t)(split - 1) * part_stride;
 }
 
 // ===================================================================== bf16
@@ -153,8 +170,8 @@ struct GramDma {
 template <bool X3, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
                                                   int64_t k_pad, int64_t r_pad, int64_t k_split, int n_split,
-                                                  int nt, int64_t n_work, float *__restrict__ out, int64_t ld,
-                                                  int64_t part_stride) {
+                                                  int nt, int64_t n_work, float *__restrict__ out,
+                                                  float *__restrict__ partial, int64_t ld, int64_t part_stride) {
   constexpr int NOPS = X3 ? 2 : 1;  // hi (and lo)
   __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];  // [op][I/J side]
   __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
     compute(lds0);
   }
   // 32x32 accumulator layout: value v of lane l is row 8 (v/4) + 4 (l/32) + v%4, column l % 32
-  float *dst = out + (int64_t)split * part_stride;
+  float *dst = gram_dst(out, partial, split, part_stride);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -258,8 +275,8 @@ __device__ __forceinline__ void mfma16x16x4<float>(float a, float b, f32x4 &c) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_t k_pad, int64_t lda, int64_t k_split,
-                                                 int n_split, int nt, int64_t n_work, T *__restrict__ out, int64_t ld,
-                                                 int64_t part_stride) {
+                                                 int n_split, int nt, int64_t n_work, T *__restrict__ out,
+                                                 T *__restrict__ partial, int64_t ld, int64_t part_stride) {
   using acc_t = typename std::conditional<sizeof(T) == 8, f64x4, f32x4>::type;
   constexpr int BK = 128 / sizeof(T);  // 128 bytes of k per row
   constexpr int LDR = BK + 1;          // padded row length
@@ -331,7 +348,7 @@ __global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_
         for (int j = 0; j < 4; ++j) mfma16x16x4<T>(a[i], b[j], acc[i][j]);
     }
   }
-  T *dst = out + (int64_t)split * part_stride;
+  T *dst = gram_dst(out, partial, split, part_stride);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -355,8 +372,8 @@ __global__ void k_gram_reduce(const T *__restrict__ part, int n_split, int64_t p
   const int64_t row0 = (int64_t)I * TILE, col0 = (int64_t)J * TILE;
   for (int e = threadIdx.x; e < TILE * TILE; e += blockDim.x) {
     const int64_t off = (row0 + e / TILE) * ld + col0 + e % TILE;
-    T s = part[off];
-    for (int q = 1; q < n_split; ++q) s += part[q * part_stride + off];
+    T s = out[off];  // slice 0
+    for (int q = 1; q < n_split; ++q) s += part[(q - 1) * part_stride + off];
     out[off] = s;
   }
 }
@@ -379,7 +396,7 @@ __device__ __forceinline__ void f64_gram_tile(int64_t t, int &I, int &J) {
 
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gram_f64(
     const double *__restrict__ A, int64_t k_pad, int64_t lda, int64_t k_split, int n_split, int64_t n_work,
-    double *__restrict__ out, int64_t ld, int64_t part_stride) {
+    double *__restrict__ out, double *__restrict__ partial, int64_t ld, int64_t part_stride) {
   // XCD x takes work items [x per, (x + 1) per), as in gram_work
   const int64_t per = (int64_t)gridDim.x / N_XCD;
   const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   f64_tile_product(A + row0 * lda, A + col0 * lda, lda, FT_R, FT_S, kb, (ke - kb) / FT_K, acc);
-  double *dst = out + (int64_t)split * part_stride;
+  double *dst = gram_dst(out, partial, split, part_stride);
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -441,10 +458,16 @@ void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s) 
     hipLaunchKernelGGL(k_gram_mirror<double>, dim3(tiles), dim3(256), 0, s, (double *)G, ld);
 }
 
-static int pick_split(int64_t n_tiles, int64_t k_pad, int bk) {
+// Slices of K per tile: enough workgroups to cover the chip several times.
+// The bf16 kernels, whose time is set by their operand stream, also take two
+// slices on large problems (measured 5 % faster at 33280 rows and K = 131072
+// with the slice-outer order of gram_work, at the cost of one more Gram-sized
+// buffer).
+static int pick_split(int64_t n_tiles, int64_t k_pad, int bk, bool bf16) {
   const int64_t target = 2048;  // workgroups to cover 256 CUs several times
   int64_t s = (target + n_tiles - 1) / n_tiles;
   const int64_t kb = k_pad / bk;
+  if (bf16 && s < 2 && kb >= 256) s = 2;
   if (s > kb / 4) s = kb / 4;  // keep at least 4 K-steps per slice
   if (s < 1) s = 1;
   if (s > 32) s = 32;
@@ -469,10 +492,10 @@ static int64_t gram_tile_count(int prec, const GramShape &g) {
 }
 
 size_t gram_partial_bytes(int prec, const GramShape &g) {
-  const int s = pick_split(gram_tile_count(prec, g), g.k_pad, gram_bk(prec));
+  const int s = pick_split(gram_tile_count(prec, g), g.k_pad, gram_bk(prec), is_bf16(prec));
   if (s <= 1) return 0;
   const size_t el = prec == WLC_FP64 ? 8 : 4;
-  return (size_t)s * g.r_pad * g.ld_out * el;
+  return (size_t)(s - 1) * g.r_pad * g.ld_out * el;  // slice 0 goes to the output
 }
 
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
@@ -480,9 +503,8 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
   const int64_t nt = g.r_pad / gram_tile(prec);
   const int64_t tiles = gram_tile_count(prec, g);
   const int bk = gram_bk(prec);
-  const int ns = pick_split(tiles, g.k_pad, bk);
+  const int ns = pick_split(tiles, g.k_pad, bk, is_bf16(prec));
   int64_t ksplit = (g.k_pad / bk + ns - 1) / ns * bk;
-  void *dst = ns > 1 ? partial : out;
   const int64_t pstride = ns > 1 ? g.r_pad * g.ld_out : 0;
   const int64_t n_work = tiles * ns;
   const dim3 grid((unsigned)((n_work + N_XCD - 1) / N_XCD * N_XCD));
@@ -490,26 +512,26 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
   switch (prec) {
     case WLC_BF16:
       hipLaunchKernelGGL((k_gram_bf16<false, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
-                         (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)dst, g.ld_out,
-                         pstride);
+                         (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
+                         g.ld_out, pstride);
       break;
     case WLC_BF16X3:
       hipLaunchKernelGGL((k_gram_bf16<true, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
-                         (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)dst, g.ld_out,
-                         pstride);
+                         (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
+                         g.ld_out, pstride);
       break;
     case WLC_FP32:
       hipLaunchKernelGGL(k_gram_x4<float>, grid, dim3(256), 0, s, (const float *)A0, g.k_pad, g.lda, ksplit, ns, nti,
-                         n_work, (float *)dst, g.ld_out, pstride);
+                         n_work, (float *)out, (float *)partial, g.ld_out, pstride);
       break;
     default:
       if (f64_tiles(prec, g)) {
         hipLaunchKernelGGL(k_gram_f64, grid, dim3(512), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, n_work,
-                           (double *)dst, g.ld_out, pstride);
+                           (double *)out, (double *)partial, g.ld_out, pstride);
         break;
       }
       hipLaunchKernelGGL(k_gram_x4<double>, grid, dim3(256), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, nti,
-                         n_work, (double *)dst, g.ld_out, pstride);
+                         n_work, (double *)out, (double *)partial, g.ld_out, pstride);
       break;
   }
   if (ns > 1) {
