@@ -32,8 +32,6 @@ namespace wlc {
 constexpr int PB = 32;        // rows per block
 constexpr int PR = 2 * PB;    // rows per pair
 constexpr int PLD = PR + 1;   // padded LDS row
-constexpr int GK = 16;        // columns per Gram stage
-constexpr int GLD = GK + 1;
 
 // Round-robin tournament: position 0 is fixed, the others rotate by r.
 __device__ __forceinline__ int rr_at(int pos, int r, int n) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (n - 1); }
@@ -70,71 +68,14 @@ __device__ __forceinline__ int64_t pair_row(int bp, int bq, int j) {
   return j < PB ? (int64_t)bp * PB + j : (int64_t)bq * PB + (j - PB);
 }
 
-__global__ __launch_bounds__(256) void k_pca_gram(const double *__restrict__ X, int64_t n_pad, int n_blk, int r,
-                                                  int64_t cols, double *__restrict__ part) {
-  __shared__ double stage[PR * GLD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int pi = blockIdx.x, ks = blockIdx.y;
-  const int bp = rr_at(pi, r, n_blk), bq = rr_at(n_blk - 1 - pi, r, n_blk);
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int64_t c0 = (int64_t)ks * cols, c1 = c0 + cols;
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
-  double pre[4];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q, j = e / GK, k = e % GK;
-      pre[q] = X[pair_row(bp, bq, j) * n_pad + k0 + k];
-    }
-  };
-  gload(c0);
-  for (int64_t k0 = c0; k0 < c1; k0 += GK) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      stage[(e / GK) * GLD + e % GK] = pre[q];
-    }
-    __syncthreads();
-    if (k0 + GK < c1) gload(k0 + GK);
-#pragma unroll
-    for (int kk = 0; kk < GK; kk += 4) {
-      const int kc = kk + (lane >> 4);
-      double a[2], b[2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        a[x] = stage[(wr + x * 16 + (lane & 15)) * GLD + kc];
-        b[x] = stage[(wc + x * 16 + (lane & 15)) * GLD + kc];
-      }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
-    }
-  }
-  // accumulator value v of lane l: row l / 16 + 4 v, column l % 16
-  double *P = part + ((int64_t)pi * gridDim.y + ks) * PR * PR;
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int z = 0; z < 2; ++z)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        P[(wr + x * 16 + (lane >> 4) + 4 * v) * PR + wc + z * 16 + (lane & 15)] = acc[x][z][v];
-}
-
-// Direct-to-LDS form of the Gram, for n_pad^2 8 < 2^31: the pair's 64 rows
+// Gram of a pair, with the pair's 64 rows
 // are copied one 64-column chunk ahead into two LDS buffers of [64 rows][64
 // doubles], unpadded, with the 16-byte chunk s of row l at slot s ^ (l & 15),
 // so the 16 consecutive rows one MFMA operand read touches at one column
 // fall on 16 distinct bank groups.  A wavefront copy fills two rows.
 __device__ __forceinline__ int gram_slot(int l, int k) { return l * PR + 2 * ((k >> 1) ^ (l & 15)) + (k & 1); }
 
-__global__ __launch_bounds__(256) void k_pca_gram_d(const double *__restrict__ X, int64_t n_pad, int n_blk, int r,
+__global__ __launch_bounds__(256) void k_pca_gram(const double *__restrict__ X, int64_t n_pad, int n_blk, int r,
                                                     int64_t cols, double *__restrict__ part) {
   __shared__ __attribute__((aligned(16))) double st0[PR * PR];
   __shared__ __attribute__((aligned(16))) double st1[PR * PR];
@@ -144,19 +85,22 @@ __global__ __launch_bounds__(256) void k_pca_gram_d(const double *__restrict__ X
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int64_t c0 = (int64_t)ks * cols;
   const int nch = (int)(cols / PR);
+  // copy i of this wavefront: rows l0 = 2 (4 i + w) and l0 + 1 of the pair
+  // (one 32-row block, so consecutive rows of X), one descriptor per copy
+  const double *rows[8];
   uint32_t off[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int l = 2 * (i * 4 + wave) + (lane >> 5);
-    off[i] = (uint32_t)((pair_row(bp, bq, l) * n_pad + 2 * ((lane & 31) ^ (l & 15))) * 8);
+    const int l0 = 2 * (i * 4 + wave), l = l0 + (lane >> 5);
+    rows[i] = X + pair_row(bp, bq, l0) * n_pad;
+    off[i] = (uint32_t)(((lane >> 5) * n_pad + 2 * ((lane & 31) ^ (l & 15))) * 8);
   }
-  const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void *)X, 0, (int)(n_pad * n_pad * 8), 0x00020000);
   auto issue = [&](int ci, double *buf) {
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rsrc, (__attribute__((address_space(3))) void *)(buf + (i * 4 + wave) * 2 * PR), 16, off[i],
+          __builtin_amdgcn_make_buffer_rsrc((void *)rows[i], 0, (int)(2 * n_pad * 8), 0x00020000),
+          (__attribute__((address_space(3))) void *)(buf + (i * 4 + wave) * 2 * PR), 16, off[i],
           (int)((c0 + (int64_t)ci * PR) * 8), 0, 0);
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -332,62 +276,6 @@ __global__ __launch_bounds__(RT) void k_pca_rot(const double *__restrict__ part,
   for (int e = tid; e < PR * PR; e += RT) out[e] = Q[(e / PR) * PLD + e % PR];
 }
 
-constexpr int AC = 4;  // 64-column chunks per apply workgroup (Q read once for all)
-
-__global__ __launch_bounds__(256) void k_pca_apply(double *__restrict__ X, double *__restrict__ V, int64_t n_pad,
-                                                   int n_blk, int r, const double *__restrict__ Qg,
-                                                   const int32_t *__restrict__ rot) {
-  __shared__ double Q[PR * PLD];
-  __shared__ double stage[PR * PLD];
-  const int pi = blockIdx.x;
-  if (!rot[pi]) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bp = rr_at(pi, r, n_blk), bq = rr_at(n_blk - 1 - pi, r, n_blk);
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  double *Y = blockIdx.z == 0 ? X : V;
-  const double *q = Qg + (int64_t)pi * PR * PR;
-  for (int e = tid; e < PR * PR; e += 256) Q[(e / PR) * PLD + e % PR] = q[e];
-  for (int ci = 0; ci < AC; ++ci) {
-    const int64_t c0 = ((int64_t)blockIdx.y * AC + ci) * PR;
-    if (c0 >= n_pad) break;
-    __syncthreads();  // Q is in place, and the previous chunk's reads of stage are done
-    for (int e = tid; e < PR * PR; e += 256) {
-      const int j = e / PR, k = e % PR;
-      stage[j * PLD + k] = Y[pair_row(bp, bq, j) * n_pad + c0 + k];
-    }
-    __syncthreads();
-    f64x4 acc[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int z = 0; z < 2; ++z) acc[x][z] = f64x4{0.0, 0.0, 0.0, 0.0};
-    // out[j][c] = sum_l Q[l][j] stage[l][c]
-#pragma unroll 4
-    for (int kk = 0; kk < PR; kk += 4) {
-      const int l = kk + (lane >> 4);
-      double a[2], b[2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        a[x] = Q[l * PLD + wr + x * 16 + (lane & 15)];
-        b[x] = stage[l * PLD + wc + x * 16 + (lane & 15)];
-      }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int z = 0; z < 2; ++z) acc[x][z] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[z], acc[x][z], 0, 0, 0);
-    }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int z = 0; z < 2; ++z)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int j = wr + x * 16 + (lane >> 4) + 4 * v, c = wc + z * 16 + (lane & 15);
-          Y[pair_row(bp, bq, j) * n_pad + c0 + c] = acc[x][z][v];
-        }
-  }
-}
-
 // Per mode a < n: lambda_a = |x_a|^2 and (S/N)^2_a = (x_a . y)^2 / lambda_a.
 __global__ void k_pca_modes(const double *__restrict__ X, const double *__restrict__ y, int64_t n, int64_t n_pad,
                             double *__restrict__ lam, double *__restrict__ snr2) {
@@ -483,8 +371,7 @@ void launch_pca_init(const double *Wm, int64_t ld, const int32_t *t, int64_t n, 
   hipLaunchKernelGGL(k_pca_init, grid, dim3(256), 0, s, Wm, ld, t, n, n_pad, X, V, y);
 }
 
-// Direct-to-LDS form of the same product, for n_pad^2 8 < 2^31 (every row
-// offset fits a buffer load's 32-bit offset).  Q's fragments stay in
+// Rotation of a pair's rows.  Q's fragments stay in
 // registers; the pair's 64 rows are copied from global memory straight into
 // LDS (buffer loads with the LDS flag: lane l of a wavefront writes 16 bytes
 // at the wavefront's LDS base + 16 l), one 64-column chunk ahead, into two
@@ -495,7 +382,7 @@ constexpr int ACD = 8;  // 64-column chunks per workgroup
 
 __device__ __forceinline__ int apply_slot(int l, int col) { return l * PR + 2 * ((col >> 1) ^ (8 * (l & 1))) + (col & 1); }
 
-__global__ __launch_bounds__(256) void k_pca_apply_d(double *__restrict__ X, double *__restrict__ V, int64_t n_pad,
+__global__ __launch_bounds__(256) void k_pca_apply(double *__restrict__ X, double *__restrict__ V, int64_t n_pad,
                                                      int n_blk, int r, const double *__restrict__ Qg,
                                                      const int32_t *__restrict__ rot) {
   __shared__ __attribute__((aligned(16))) double st0[PR * PR];
@@ -514,22 +401,24 @@ __global__ __launch_bounds__(256) void k_pca_apply_d(double *__restrict__ X, dou
 #pragma unroll
     for (int x = 0; x < 2; ++x) qa[kk][x] = q[(4 * kk + (lane >> 4)) * PR + wr + x * 16 + (lane & 15)];
   // copies: wavefront w fills LDS rows 2 (8 i + w) + lane / 32 ... for i < 8
+  // copy i of this wavefront: rows l0 = 2 (4 i + w) and l0 + 1 of the pair
+  // (one 32-row block, so consecutive rows of Y), one descriptor per copy
+  const double *rows[8];
   uint32_t off[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int l = 2 * (i * 4 + wave) + (lane >> 5);
-    const int sl = lane & 31;
-    off[i] = (uint32_t)((pair_row(bp, bq, l) * n_pad + 2 * (sl ^ (8 * (l & 1)))) * 8);
+    const int l0 = 2 * (i * 4 + wave), l = l0 + (lane >> 5);
+    rows[i] = Y + pair_row(bp, bq, l0) * n_pad;
+    off[i] = (uint32_t)(((lane >> 5) * n_pad + 2 * ((lane & 31) ^ (8 * (l & 1)))) * 8);
   }
-  const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void *)Y, 0, (int)(n_pad * n_pad * 8), 0x00020000);
   const int64_t cbase = (int64_t)blockIdx.y * ACD * PR;
   const int nch = (int)min((int64_t)ACD, (n_pad - cbase) / PR);
   auto issue = [&](int ci, double *buf) {
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rsrc, (__attribute__((address_space(3))) void *)(buf + (i * 4 + wave) * 2 * PR), 16, off[i],
+          __builtin_amdgcn_make_buffer_rsrc((void *)rows[i], 0, (int)(2 * n_pad * 8), 0x00020000),
+          (__attribute__((address_space(3))) void *)(buf + (i * 4 + wave) * 2 * PR), 16, off[i],
           (int)((cbase + (int64_t)ci * PR) * 8), 0, 0);
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -598,19 +487,12 @@ int pca_slices(int64_t n_pad) {
 void launch_pca_round(double *X, double *V, int64_t n_pad, int r, double tol, int max_inner, double *conv,
                       double *part, double *Qg, int32_t *rot, hipStream_t s) {
   const int n_blk = (int)(n_pad / PB), pairs = n_blk / 2, ks = pca_slices(n_pad);
-  if (n_pad * n_pad * 8 < ((int64_t)1 << 31))  // slices are multiples of 64 columns
-    hipLaunchKernelGGL(k_pca_gram_d, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
-                       n_pad / ks, part);
-  else
-    hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
-                       n_pad / ks, part);
+  // slices are multiples of 64 columns
+  hipLaunchKernelGGL(k_pca_gram, dim3((unsigned)pairs, (unsigned)ks), dim3(256), 0, s, X, n_pad, n_blk, r,
+                     n_pad / ks, part);
   hipLaunchKernelGGL(k_pca_rot, dim3((unsigned)pairs), dim3(RT), 0, s, part, ks, tol, max_inner, Qg, rot, conv);
-  if (n_pad * n_pad * 8 < ((int64_t)1 << 31))
-    hipLaunchKernelGGL(k_pca_apply_d, dim3((unsigned)pairs, (unsigned)((n_pad / PR + ACD - 1) / ACD), V ? 2u : 1u),
-                       dim3(256), 0, s, X, V, n_pad, n_blk, r, Qg, rot);
-  else
-    hipLaunchKernelGGL(k_pca_apply, dim3((unsigned)pairs, (unsigned)((n_pad / PR + AC - 1) / AC), V ? 2u : 1u),
-                       dim3(256), 0, s, X, V, n_pad, n_blk, r, Qg, rot);
+  hipLaunchKernelGGL(k_pca_apply, dim3((unsigned)pairs, (unsigned)((n_pad / PR + ACD - 1) / ACD), V ? 2u : 1u),
+                     dim3(256), 0, s, X, V, n_pad, n_blk, r, Qg, rot);
 }
 
 void launch_pca_finish(const double *X, const double *y, const double *Vr, int64_t n, int64_t n_pad, double *lam,
