@@ -62,27 +62,29 @@ void launch_chol_prep(const void *C, int c_f32, const int32_t *row_exp2, const d
 // One workgroup of 256 threads on the jb x jb diagonal block at j0 (rows
 // beyond jb padded with the identity), held in registers: thread
 // t = 16 tj + ti owns rows 4 ti .. 4 ti + 3 and columns 4 tj .. 4 tj + 3.
-// The factorisation runs square-root free, as A = U D U^T with U unit lower:
-// at step k the owners of column k publish it in LDS as it stands (the
-// Schur complement column, d_k = its diagonal entry), and after one barrier
-// every thread applies -a[i][k] a[j][k] / d_k to its block.  Then
-// L = U D^1/2, i.e. L[i][k] = a[i][k] / sqrt(d_k), in one parallel pass.
-// X = L^-1 follows by forward substitution in the same order: the owners of
-// row q scale it by 1 / L[q][q] and publish it, and the rows below subtract
-// L[i][q] X[q][:].  Each step is a chain of dependent instructions, so it
-// holds no square root and one division, and the updates mask the
-// broadcast factors rather than each product; entries above the diagonal
-// of a thread's block take harmless updates and are never read.  The
-// published vectors alternate between two LDS buffers, so one barrier per
-// step suffices.  Writes L back and X to Linv (row-major, NB columns).
+// The factorisation runs square-root free, as A = U D U^T with U unit lower,
+// and inverts U in the same pass: at step k the owners of column k publish
+// it in LDS as it stands (the Schur complement column, d_k = its diagonal
+// entry, U[i][k] = a[i][k] / d_k), the owners of row k of V publish that
+// row (final after step k - 1), and after one barrier every thread applies
+// -a[i][k] a[j][k] / d_k to its block of A and -U[i][k] V[k][j] to its block
+// of V (V = I at the start, V = U^-1 at the end: forward substitution with
+// a unit diagonal).  Each step is one chain of dependent instructions with
+// no square root and one division; the updates mask the broadcast factors
+// rather than each product, and entries above the diagonal of a thread's
+// block take harmless updates that are never read.  The published vectors
+// alternate between two LDS buffers, so one barrier per step suffices.
+// Afterwards d_k is the diagonal of A, and in one parallel pass
+// L = U D^1/2 (L[i][k] = a[i][k] / sqrt(d_k)) goes back to the matrix and
+// X = L^-1 = D^-1/2 V to Linv (row-major, NB columns).
 __device__ __forceinline__ double pick4(const double (&v)[4], int c) {
   return c == 0 ? v[0] : c == 1 ? v[1] : c == 2 ? v[2] : v[3];
 }
 
 __global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ Wm, int64_t ld, int64_t j0, int jb,
                                                     double *__restrict__ Linv, int *__restrict__ flag) {
-  __shared__ double vec[2][NB];
-  __shared__ double Ls[NB][NB + 1];
+  __shared__ double vcol[2][NB];  // column k of the Schur complement
+  __shared__ double vrow[2][NB];  // row k of V
   __shared__ double dsq[NB], dinv[NB];  // sqrt(d_k) and its reciprocal
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -105,70 +107,54 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ Wm, int
     const int kb = k >> 2, kc = k & 3, buf = k & 1;
     if (tj == kb) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) vec[buf][i0 + r] = pick4(a[r], kc);
+      for (int r = 0; r < 4; ++r) vcol[buf][i0 + r] = pick4(a[r], kc);
+    }
+    if (ti == kb) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double col[4] = {x[0][c], x[1][c], x[2][c], x[3][c]};
+        vrow[buf][c0 + c] = pick4(col, kc);
+      }
     }
     __syncthreads();
-    const double dk = vec[buf][k];
+    const double dk = vcol[buf][k];
     const double rd = dk > 0.0 ? 1.0 / dk : 0.0;
-    double li[4], lj[4];
+    double li[4], lj[4], vk[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      li[q] = i0 + q > k ? vec[buf][i0 + q] : 0.0;
-      lj[q] = c0 + q > k ? vec[buf][c0 + q] * rd : 0.0;
+      li[q] = i0 + q > k ? vcol[buf][i0 + q] : 0.0;
+      lj[q] = c0 + q > k ? vcol[buf][c0 + q] * rd : 0.0;
+      vk[q] = vrow[buf][c0 + q];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r) {
+      const double u = li[r] * rd;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a[r][c] -= li[r] * lj[c];
-    if (tid == k) {
+      for (int c = 0; c < 4; ++c) {
+        a[r][c] -= li[r] * lj[c];
+        x[r][c] -= u * vk[c];
+      }
+    }
+  }
+  if (ti == tj) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double dk = a[r][r];
       if (!(dk > 0.0)) bad = 1;
       const double sq = sqrt(dk > 0.0 ? dk : 1.0);
-      dsq[k] = sq;
-      dinv[k] = 1.0 / sq;
+      dsq[i0 + r] = sq;
+      dinv[i0 + r] = 1.0 / sq;
     }
   }
   __syncthreads();
-  // L = U D^1/2 to LDS (and back to the matrix), then the inverse
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int i = i0 + r, j = c0 + c;
-      const double l = j < i ? a[r][c] * dinv[j] : (j == i ? dsq[j] : 0.0);
-      Ls[i][j] = l;
-      if (i < jb && j <= i) Wm[(j0 + i) * ld + j0 + j] = l;
+      if (i < jb && j <= i) Wm[(j0 + i) * ld + j0 + j] = j < i ? a[r][c] * dinv[j] : dsq[j];
+      Linv[i * NB + j] = j <= i ? x[r][c] * dinv[i] : 0.0;
     }
-  __syncthreads();
-  for (int q = 0; q < NB; ++q) {
-    const int qb = q >> 2, qc = q & 3, buf = q & 1;
-    if (ti == qb) {
-      const double rq = dinv[q];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r == qc) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            x[r][c] *= rq;
-            vec[buf][c0 + c] = x[r][c];
-          }
-        }
-    }
-    __syncthreads();
-    double xq[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) xq[c] = vec[buf][c0 + c];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double liq = i0 + r > q ? Ls[i0 + r][q] : 0.0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) x[r][c] -= liq * xq[c];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) Linv[(i0 + r) * NB + c0 + c] = x[r][c];
-  __syncthreads();
   if (tid == 0 && bad) atomicOr(flag, 1);
 }
 
