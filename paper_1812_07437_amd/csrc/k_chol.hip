@@ -103,6 +103,8 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ Wm, int
       x[r][c] = i == j ? 1.0 : 0.0;
     }
   if (tid == 0) bad = 0;
+  // unrolled by four so that the column within a thread's block is a constant
+#pragma unroll 4
   for (int k = 0; k < NB; ++k) {
     const int kb = k >> 2, kc = k & 3, buf = k & 1;
     if (tj == kb) {
@@ -117,14 +119,22 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ Wm, int
       }
     }
     __syncthreads();
+    // all reads first and unconditionally (masked afterwards), so that
+    // they overlap one another and the division
     const double dk = vcol[buf][k];
-    const double rd = dk > 0.0 ? 1.0 / dk : 0.0;
-    double li[4], lj[4], vk[4];
+    double ci[4], cj[4], vk[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      li[q] = i0 + q > k ? vcol[buf][i0 + q] : 0.0;
-      lj[q] = c0 + q > k ? vcol[buf][c0 + q] * rd : 0.0;
+      ci[q] = vcol[buf][i0 + q];
+      cj[q] = vcol[buf][c0 + q];
       vk[q] = vrow[buf][c0 + q];
+    }
+    const double rd = dk > 0.0 ? 1.0 / dk : 0.0;
+    double li[4], lj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      li[q] = i0 + q > k ? ci[q] : 0.0;
+      lj[q] = c0 + q > k ? cj[q] * rd : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
