@@ -95,11 +95,12 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double *__restrict__ Wm, int
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
+      // every load unconditional, from the block's lower triangle (the
+      // mirror position above the diagonal, clamped to the block), and
+      // masked arithmetically, so all are in flight at once
       const int i = i0 + r, j = c0 + c;
-      double v = 0.0;
-      if (i < jb && j <= i) v = Wm[(j0 + i) * ld + j0 + j];
-      else if (i >= jb && i == j) v = 1.0;
-      a[r][c] = v;
+      const double w = Wm[(j0 + min(max(i, j), jb - 1)) * ld + j0 + min(min(i, j), jb - 1)];
+      a[r][c] = w * ((i < jb && j <= i) ? 1.0 : 0.0) + ((i >= jb && i == j) ? 1.0 : 0.0);
       x[r][c] = i == j ? 1.0 : 0.0;
     }
   if (tid == 0) bad = 0;
@@ -178,10 +179,22 @@ __global__ __launch_bounds__(256) void k_trsm(double *__restrict__ Wm, int64_t l
   __shared__ double B[NB][NB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t rb = r0 + (int64_t)blockIdx.x * NB;
-  for (int q = tid; q < NB * NB; q += 256) {
-    const int i = q / NB, c = q % NB;
-    Li[i][c] = Linv[q];
-    B[i][c] = (rb + i < r1 && c < jb) ? Wm[(rb + i) * ld + j0 + c] : 0.0;
+  // all 32 loads of a thread in flight together: unconditional, from
+  // addresses clamped into the panel (entries below the diagonal block,
+  // finite), masked arithmetically afterwards
+  double lv[NB * NB / 256], bv[NB * NB / 256];
+#pragma unroll
+  for (int m = 0; m < NB * NB / 256; ++m) {
+    const int q = tid + 256 * m, i = q / NB, c = q % NB;
+    lv[m] = Linv[q];
+    const double w = Wm[min(rb + i, r1 - 1) * ld + j0 + min(c, jb - 1)];
+    bv[m] = w * ((rb + i < r1 && c < jb) ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int m = 0; m < NB * NB / 256; ++m) {
+    const int q = tid + 256 * m;
+    Li[q / NB][q % NB] = lv[m];
+    B[q / NB][q % NB] = bv[m];
   }
   __syncthreads();
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;

@@ -38,6 +38,43 @@ __device__ __forceinline__ void tile_of(int64_t t, int tri, int64_t tcols, int64
   }
 }
 
+// Write a wavefront's 64 x 64 result (rows i0 + wr.., columns j0 + wc..):
+// into the split-k scratch (rows and columns relative to c0), or subtracted
+// from W.  The subtraction reads W 16 entries at a time, all loads of a
+// batch in flight together and from clamped addresses inside the block
+// (their values are dropped where the entry is not written), instead of
+// one load and wait per entry.
+__device__ __forceinline__ void tile_epilogue(double *__restrict__ Wm, int64_t ld, int64_t i0, int64_t j0, int wr,
+                                              int wc, int lane, int64_t c0, int64_t r1, int64_t c1,
+                                              double *__restrict__ pdst, const f64x4 (&acc)[4][4]) {
+  const int64_t pcols = c1 - c0;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    double w[4][4];
+    if (!pdst) {
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t i = min(i0 + wr + x * 16 + (lane >> 4) + 4 * v, r1 - 1);
+          const int64_t j = min(j0 + wc + y * 16 + (lane & 15), c1 - 1);
+          w[y][v] = Wm[i * ld + j];
+        }
+    }
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + wr + x * 16 + (lane >> 4) + 4 * v;
+        const int64_t j = j0 + wc + y * 16 + (lane & 15);
+        if (i < r1 && j < c1 && i >= j) {
+          if (pdst) pdst[(i - c0) * pcols + (j - c0)] = acc[x][y][v];
+          else Wm[i * ld + j] = w[y][v] - acc[x][y][v];
+        }
+      }
+  }
+}
+
 // Register-staged form: in each 4-wide k step lane l holds row l % 16, k
 // l / 16 of each operand; the LDS rows are padded by one element.
 template <int NW>
@@ -135,21 +172,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
     compute((int)(st & 1));
     __syncthreads();
   }
-  const int64_t pcols = c1 - c0;
-  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pcols : nullptr;
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t i = i0 + wr + x * 16 + (lane >> 4) + 4 * v;
-        const int64_t j = j0 + wc + y * 16 + (lane & 15);
-        if (i < r1 && j < c1 && i >= j) {
-          if (pdst) pdst[(i - c0) * pcols + (j - c0)] = acc[x][y][v];
-          else Wm[i * ld + j] -= acc[x][y][v];
-        }
-      }
+  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * (c1 - c0) : nullptr;
+  tile_epilogue(Wm, ld, i0, j0, wr, wc, lane, c0, r1, c1, pdst, acc);
 }
 
 // The 128 x 256 update: the tile product of f64tile.h on the row slice
@@ -173,21 +197,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // the host passes whole 16-wide steps only
   f64_tile_product(Wm + i0 * ld, Wm + j0 * ld, ld, min((int64_t)FT_R, r1 - i0), min((int64_t)FT_S, c1 - j0), kb,
                    (ke - kb) / FT_K, acc);
-  const int64_t pcols = c1 - c0;
-  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * pcols : nullptr;
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t i = i0 + wr + x * 16 + (lane >> 4) + 4 * v;
-        const int64_t j = j0 + wc + y * 16 + (lane & 15);
-        if (i < r1 && j < c1 && i >= j) {
-          if (pdst) pdst[(i - c0) * pcols + (j - c0)] = acc[x][y][v];
-          else Wm[i * ld + j] -= acc[x][y][v];
-        }
-      }
+  double *pdst = n_split > 1 ? part + (int64_t)split * (r1 - c0) * (c1 - c0) : nullptr;
+  tile_epilogue(Wm, ld, i0, j0, wr, wc, lane, c0, r1, c1, pdst, acc);
 }
 
 // W[i][j] -= sum_s part[s][i - c0][j - c0] for the lower part of the block.
