@@ -196,6 +196,22 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__re
   const int cb = tid & 63;          // column within the tile
   const int rbase = (tid >> 6) * 16;
   const int64_t b = b0 + cb;
+  // the 16 one-halo values first, all loads in flight together (padding
+  // rows map to distinct row 0, so every index is valid)
+  double gv[16];
+  const int64_t eb = rowB[cb][1];
+  if (A.gm_f32) {
+    const float *G = (const float *)A.Gm;
+    float gf[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) gf[q] = G[rowA[rbase + q][1] * A.ld_g + eb];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) gv[q] = (double)gf[q];
+  } else {
+    const double *G = (const double *)A.Gm;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) gv[q] = G[rowA[rbase + q][1] * A.ld_g + eb];
+  }
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int ra = rbase + q;
@@ -204,7 +220,7 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__re
     const bool live = a < A.n && b < A.n && a >= b;
     if (live) {
       const int tt = tA[ra] + tB[cb];
-      const double g = gram_at(A, rowA[ra][1], rowB[cb][1]);
+      const double g = gv[q];
       double rest = A.sigma_b2 * rA[ra] * rB[cb] + gauss_entry(A, rowA[ra], rowB[cb]);
       if (A.ngins) rest += ngins_entry(A, rowA[ra], rowB[cb]);
       v = ldexp(g * A.inv_omega, tt - sA[ra] - sB[cb]) + ldexp(rest, tt);
