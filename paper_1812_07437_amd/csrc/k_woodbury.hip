@@ -347,38 +347,58 @@ __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
   }
   auto gload = [&](int64_t kq) {
     // every element of this thread sits in column k = kq + tid % WK of the
-    // stage, so the column's Mhat factors are loaded once
+    // stage, so the column's Mhat factors are loaded once.  All loads are
+    // unconditional, from indices clamped into range, and masked afterwards
+    // by multiplication (the values are finite), so they are in flight
+    // together instead of one branch and wait each.
     const int64_t k = kq + tid % WK;
+    const bool kin = k < k1;
+    const int64_t kc = kin ? k : k1 - 1;
     int sk = 0;
     double rk = 0.0;
-    if (MODE == 0 && k < k1) {
-      sk = a.sexp[k] + a.tau[k];
-      rk = a.rhat[k];
+    if (MODE == 0) {
+      sk = a.sexp[kc] + a.tau[kc];
+      rk = a.rhat[kc];
+    }
+    double lw[4], gw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t lr = (MODE == 0 ? e0 : f0) + (tid + 256 * j) / WK;
+      // L[k][lr]: nonzero only inside lr's block, on or below its diagonal;
+      // elsewhere the block's diagonal entry L[lr][lr] is read instead
+      const bool lin = k >= lr && k < lb1[j];
+      lw[j] = a.Gb[lbase[j] + ((lin ? k : lr) - lb0[j]) * lsz[j]];
+    }
+    if (MODE == 0) {
+      if (a.gm_f32) {
+        float gf[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          gf[j] = ((const float *)a.Gm)[min(f0 + (tid + 256 * j) / WK, nR - 1) * a.ld_g + kc];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gw[j] = (double)gf[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gw[j] = ((const double *)a.Gm)[min(f0 + (tid + 256 * j) / WK, nR - 1) * a.ld_g + kc];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gw[j] = a.T[min(e0 + (tid + 256 * j) / WK, nR - 1) * a.ld_t + kc];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int q = tid + 256 * j;
-      const int r = q / WK;
+      const int r = (tid + 256 * j) / WK;
       const int64_t e = e0 + r, f = f0 + r;
       const int64_t lr = MODE == 0 ? e : f;
-      // L[k][lr]: nonzero only inside lr's block, on or below its diagonal
-      const double lv = (k >= lr && k < lb1[j]) ? a.Gb[lbase[j] + (k - lb0[j]) * lsz[j]] : 0.0;
-      double va = 0.0, vb = 0.0;
-      if (k < k1) {
-        if (MODE == 0) {
-          va = lv;
-          if (f < nR) {
-            const double g = a.gm_f32 ? (double)((const float *)a.Gm)[f * a.ld_g + k]
-                                      : ((const double *)a.Gm)[f * a.ld_g + k];
-            vb = ldexp(g * fscale[j], -sk) + frh[j] * rk;
-          }
-        } else {
-          if (e < nR) va = a.T[e * a.ld_t + k];
-          vb = lv;
-        }
+      const double lv = lw[j] * ((k >= lr && k < lb1[j]) ? 1.0 : 0.0);
+      const double in = kin ? 1.0 : 0.0;
+      if (MODE == 0) {
+        pa[j] = lv * in;
+        pb[j] = (ldexp(gw[j] * fscale[j], -sk) + frh[j] * rk) * ((f < nR && kin) ? 1.0 : 0.0);
+      } else {
+        pa[j] = gw[j] * ((e < nR && kin) ? 1.0 : 0.0);
+        pb[j] = lv * in;
       }
-      pa[j] = va;
-      pb[j] = vb;
     }
   };
   gload(k0);
