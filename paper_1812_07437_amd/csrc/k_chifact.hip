@@ -115,14 +115,26 @@ __global__ __launch_bounds__(256) void k_chifact(const double *__restrict__ Ts, 
   // staging: 64 rows x CK nodes per side, 4 per thread; element q is row
   // q / CK, node q % CK
   double pa[4], pb[4];
+  // (loads unconditional, from indices clamped into range, and masked by
+  // multiplication afterwards: the factors are finite, and all 12 loads of
+  // a thread are in flight together)
   auto gload = [&](int n0) {
+    double ta[4], tb[4], hv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = tid + 256 * j;
-      const int r = q / CK, k = q % CK, n = n0 + k;
+      const int r = q / CK, n = min(n0 + q % CK, n_chi - 1);
+      ta[j] = Ts[(size_t)(A.e0 + min(r, A.cnt - 1)) * n_chi + n];
+      tb[j] = Ts[(size_t)(B.e0 + min(r, B.cnt - 1)) * n_chi + n];
+      hv[j] = h[n];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = tid + 256 * j;
+      const int r = q / CK, n = n0 + q % CK;
       const bool kin = n < n_chi;
-      pa[j] = (kin && r < A.cnt) ? Ts[(size_t)(A.e0 + r) * n_chi + n] * h[n] : 0.0;
-      pb[j] = (kin && r < B.cnt) ? Ts[(size_t)(B.e0 + r) * n_chi + n] : 0.0;
+      pa[j] = ta[j] * hv[j] * ((kin && r < A.cnt) ? 1.0 : 0.0);
+      pb[j] = tb[j] * ((kin && r < B.cnt) ? 1.0 : 0.0);
     }
   };
   gload(0);
