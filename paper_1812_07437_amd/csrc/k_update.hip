@@ -5,10 +5,11 @@
 // once per launch (21.3 instead of 16 flops per operand byte); other shapes
 // go on 128 x 128 tiles (4 wavefronts, k_update2<4>).  Each wavefront
 // computes 64 x 64 on v_mfma_f64_16x16x4 (the accumulator value v of lane l
-// is row l / 16 + 4 v, column l % 16).  K advances in 16-wide steps through
-// two LDS buffers with one barrier per step: the wide kernel copies operands
-// from global memory straight into LDS one step ahead, the narrow one stages
-// them through registers two steps ahead.  The register budget is capped at
+// is row l / 16 + 4 v, column l % 16).  K advances in 16-wide steps with one
+// barrier per step: the wide kernel copies operands from global memory
+// straight into three LDS buffers two steps ahead (the tile product of
+// f64tile.h), the narrow one stages them through registers two steps ahead
+// into two LDS buffers.  The register budget is capped at
 // two wavefronts per SIMD.  A long k range may be split into slices whose
 // partial products go to a scratch buffer and are subtracted in a fixed order
 // by a second kernel, so results do not depend on scheduling.
