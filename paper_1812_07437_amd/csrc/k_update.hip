@@ -230,10 +230,11 @@ void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, 
   // a whole 256-wide panel below its diagonal block goes on 128 x 256 tiles
   // (k_update2d: whole 16-wide stages, 16-byte aligned rows and a 256-row
   // side within a buffer descriptor's 31-bit range, which the factorisation's
-  // 64-multiple k ranges and 8-multiple row pitch always give); anything else
-  // on 128 x 128 tiles
+  // 64-multiple k ranges and 8-multiple row pitch always give); anything else,
+  // and a k range of one inner block (64), where a tile is mostly its fill
+  // and write-back and two workgroups per CU do better, on 128 x 128 tiles
   const bool wide = c1 - c0 > UT2 && c1 - c0 <= 2 * UT2 && r1 - c0 > 2 * UT2 && (k1 - k0) % UBK == 0 &&
-                    k0 % 2 == 0 && ld % 2 == 0 && 2 * UT2 * ld * 8 < ((int64_t)1 << 31);
+                    k0 % 2 == 0 && ld % 2 == 0 && 2 * UT2 * ld * 8 < ((int64_t)1 << 31) && k1 - k0 > 64;
   const int64_t tcw = wide ? 2 * UT2 : UT2;
   const int64_t tr = (r1 - c0 + UT2 - 1) / UT2, tc = (c1 - c0 + tcw - 1) / tcw;
   const int tri = !wide && tr == tc;
