@@ -44,6 +44,12 @@ def parse():
     ap.add_argument("--pca-only", action="store_true")
     ap.add_argument("--no-pca-tomography", dest="pca_tomography", action="store_false",
                     help="skip the PCA of the paper's 14-bin binning with 1, 2 and 5 redshift bins")
+    ap.add_argument("--precision-workload", default="euclid5",
+                    help="workload of the Gram precision report (bf16, bf16x3, fp32 vs FP64; empty: skip)")
+    ap.add_argument("--no-gram-variants", dest="gram_variants", action="store_false",
+                    help="skip timing the plain bf16 and FP32 Gram on the bench workload")
+    ap.add_argument("--lattice-workload", default="euclid5",
+                    help="workload of the timed lattice counts (empty: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=12,
@@ -87,12 +93,132 @@ def measured_traffic(*names, per=None):
     return dict(bytes_per_launch=total / launches, summary=rec[names[0]]["summary"])
 
 
-def gram_flops(n_r, k_len, precision):
+def gram_flops(n_r, k_len):
     """Useful flops of the one-halo Gram: each of the n_r (n_r + 1)/2 distinct
-    entries is a length-K dot product (2K flops); the split bf16 product does
-    three MFMA products per entry."""
-    f = n_r * (n_r + 1) * k_len
-    return f * (3 if precision == "bf16x3" else 1)
+    entries is a length-K dot product (2K flops), whatever the precision."""
+    return n_r * (n_r + 1) * k_len
+
+
+def gram_mfma_work(n_r, k_len, precision):
+    """Flops the matrix cores issue for the same entries: the split bf16
+    product does three products (hi hi, hi lo, lo hi) per entry."""
+    return gram_flops(n_r, k_len) * (3 if precision == "bf16x3" else 1)
+
+
+def gram_figures(ms, n_r, k_len, precision):
+    """Gram rate on useful flops and, separately, on issued MFMA work, each
+    against the peak of the precision's matrix-core type."""
+    useful = gram_flops(n_r, k_len) / (ms * 1e-3) / 1e12
+    work = gram_mfma_work(n_r, k_len, precision) / (ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    return dict(ms=ms, useful_tflops=useful, frac_peak_useful=useful / peak, mfma_work_tflops=work,
+                frac_peak_mfma_work=work / peak, peak_tflops=peak)
+
+
+def timed_runs(prob, runs, warmup, torch, wl):
+    """Phase times of wlc_run alone (no S/N), averaged over runs."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        prob.run(stream)
+    torch.cuda.synchronize()
+    wl.wlc_plan_set_timing(prob.plan, True)
+    phases = {p: 0.0 for p in wl.PHASES}
+    for _ in range(runs):
+        prob.run(stream)
+        for k, v in wl.wlc_plan_timings(prob.plan).items():
+            phases[k] += v
+    torch.cuda.synchronize()
+    wl.wlc_plan_set_timing(prob.plan, False)
+    return {k: v / runs for k, v in phases.items()}
+
+
+def true_cov(prob, torch):
+    """C_true = C 2^-(t_a + t_b) on the device, float64."""
+    t = prob.row_exp2.to(torch.int64)
+    return torch.ldexp(prob.C.double(), -(t[:, None] + t[None, :]).double())
+
+
+def precision_report(workload, torch, wl):
+    """The Gram precisions at one workload (the Euclid-like shape by
+    default): bf16, split bf16 x 3 and FP32 against the FP64 path on the same
+    tables -- Gram time, its useful-flop and issued-work fractions of peak,
+    diagonal max / median relative error, off-diagonal error relative to
+    sqrt(C_aa C_bb), and the (S/N)^2 error."""
+    import synth
+    t = synth.make_tables(workload)
+    out = {"workload": workload}
+    p64 = wl.Problem(t.cfg, t.arrays(), precision="fp64", device="cuda:0")
+    s = p64.sizes
+    NR, K = s.n_distinct, s.k_len
+    ph = timed_runs(p64, 2, 1, torch, wl)
+    snr64 = p64.snr2()
+    C64 = true_cov(p64, torch)
+    d64 = torch.diagonal(C64).clone()
+    out["fp64"] = dict(gram=gram_figures(ph["gram"], NR, K, "fp64"), snr2=snr64)
+    del p64
+    scale = torch.sqrt(torch.outer(d64, d64))
+    for prec in ("bf16", "bf16x3", "fp32"):
+        pm = wl.Problem(t.cfg, t.arrays(), precision=prec, device="cuda:0")
+        ph = timed_runs(pm, 2, 1, torch, wl)
+        snr = pm.snr2()
+        Cm = true_cov(pm, torch)
+        dm = torch.diagonal(Cm)
+        ed = torch.abs(dm - d64) / d64
+        off = torch.abs(Cm - C64) / scale
+        off.fill_diagonal_(0.0)
+        out[prec] = dict(gram=gram_figures(ph["gram"], NR, K, prec), diag_max_rel=float(ed.max()),
+                         diag_median_rel=float(ed.median()), offdiag_max_rel_sqrt_caa_cbb=float(off.max()),
+                         snr2_rel=abs(snr - snr64) / snr64)
+        log("precision %s %s: gram %.3f ms (useful %.1f %% of peak), diag max %.2e median %.2e, off %.2e, "
+            "snr %.2e" % (workload, prec, ph["gram"], 100 * out[prec]["gram"]["frac_peak_useful"],
+                          out[prec]["diag_max_rel"], out[prec]["diag_median_rel"],
+                          out[prec]["offdiag_max_rel_sqrt_caa_cbb"], out[prec]["snr2_rel"]))
+        del pm, Cm, off
+        torch.cuda.empty_cache()
+    del C64, scale
+    torch.cuda.empty_cache()
+    return out
+
+
+def gram_variants(cfg, arrays, torch, wl, precisions=("bf16", "fp32")):
+    """Gram time of the other precisions on the bench workload (wlc_run
+    only, one warm-up and one timed run each)."""
+    out = {}
+    for prec in precisions:
+        p = wl.Problem(cfg, arrays, precision=prec, device="cuda:0")
+        s = p.sizes
+        ph = timed_runs(p, 1, 1, torch, wl)
+        out[prec] = gram_figures(ph["gram"], s.n_distinct, s.k_len, prec)
+        out[prec]["run_ms"] = sum(ph[k] for k in ("tables", "abuild", "gram", "assemble"))
+        log("gram %s: %.1f ms, useful %.1f TFLOP/s (%.1f %% of its peak)" % (
+            prec, ph["gram"], out[prec]["useful_tflops"], 100 * out[prec]["frac_peak_useful"]))
+        del p
+        torch.cuda.empty_cache()
+    return out
+
+
+def lattice_leg(workload, torch, wl, reps=3):
+    """Integer lattice counts of modes and triangles (wlc_lattice_counts)
+    on a workload's binning, timed with events on the launch stream."""
+    import synth
+    t = synth.make_tables(workload)
+    p = wl.Problem(t.cfg, t.arrays(), precision="fp64_chi", device="cuda:0")
+    stream = torch.cuda.current_stream()
+    p.lattice_counts(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        modes, tris = p.lattice_counts(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out = dict(workload=workload, ms=ms, n_tri=int(p.sizes.n_tri), n_ell=int(p.sizes.n_ell_used),
+               modes_total=int(modes.sum()), pairs_total=int(tris.sum()))
+    log("lattice counts %s: %.2f ms (%d triangles, %.3e mode pairs)" % (workload, ms, out["n_tri"],
+                                                                        out["pairs_total"]))
+    del p
+    return out
 
 
 def pca_leg(args, torch, wl):
@@ -356,7 +482,7 @@ def main():
     if args.fp64_steps > 0 and args.precision != "fp64":
         log("fp64 path")
         p64 = wl.Problem(cfg, t.arrays(), precision="fp64", device="cuda:0")
-        dt64, ph64, snr64, _ = timed_steps(p64, args.fp64_steps, 0, torch, wl)
+        dt64, ph64, snr64, _ = timed_steps(p64, args.fp64_steps, 1, torch, wl)
         d64 = p64.C.diagonal().cpu().numpy()
         t64 = p64.row_exp2.cpu().numpy().astype(np.int64)
         diag64 = np.ldexp(d64, -2 * t64)
@@ -365,13 +491,17 @@ def main():
         fp64 = dict(ms_per_step=dt64 / args.fp64_steps * 1e3, value=entries / (dt64 / args.fp64_steps),
                     phases_ms=ph64, speedup_step=(dt64 / args.fp64_steps) / (dt / args.steps),
                     speedup_gram=ph64["gram"] / max(ph["gram"], 1e-9),
-                    gram_tflops=gram_flops(NR, K, "fp64") / (ph64["gram"] * 1e-3) / 1e12,
+                    gram=gram_figures(ph64["gram"], NR, K, "fp64"),
                     err_vs_fp64={"diag_max_rel": err_diag, "snr2_rel": err_snr})
         log("fp64: %.1f ms/step  gram %.1f ms  diag err %.2e  snr err %.2e" % (fp64["ms_per_step"], ph64["gram"],
                                                                            err_diag, err_snr))
         fp64["snr2"] = snr64[-1]
         del p64
         torch.cuda.empty_cache()
+
+    variants = gram_variants(cfg, t.arrays(), torch, wl) if args.gram_variants else None
+    prec_rep = precision_report(args.precision_workload, torch, wl) if args.precision_workload else None
+    lattice = lattice_leg(args.lattice_workload, torch, wl) if args.lattice_workload else None
 
     # FP64 path with the one-halo sum taken over M first and chi second
     # (exact; N_M times fewer one-halo operations than the flattened Gram)
@@ -459,7 +589,7 @@ def main():
     # roofline of the dominant kernel of the step: the one-halo Gram (one
     # launch per step) or the Cholesky block update (many launches per step,
     # timed one by one with HIP events on the run's stream)
-    gram_tf = gram_flops(NR, K, args.precision) / (ph["gram"] * 1e-3) / 1e12
+    gram_fig = gram_figures(ph["gram"], NR, K, args.precision)
     chol_flops = N ** 3 / 3.0
     chol_tf = chol_flops / (ph["chol"] * 1e-3) / 1e12
     upd_frac_timed = upd["timed"] / max(upd["launches"], 1)
@@ -476,16 +606,16 @@ def main():
                     avg_launch_ms=upd_ms / max(upd["launches"], 1), flops_per_step=upd["flops"])
     else:
         tr = measured_traffic("k_gram_bf16")
-        roof = dict(bound="mfma", kernel="k_gram_bf16<x3> (one-halo Gram)", achieved=gram_tf,
-                    peak=PEAK_TFLOPS[args.precision], unit="TFLOP/s", frac=gram_tf / PEAK_TFLOPS[args.precision],
-                    traffic=tr["bytes_per_launch"] / 1e9 if tr else None, launches=1, avg_launch_ms=ph["gram"],
-                    flops_per_step=gram_flops(NR, K, args.precision))
+        roof = dict(bound="mfma", kernel="k_gram_bf16 (one-halo Gram, useful flops)",
+                    achieved=gram_fig["useful_tflops"], peak=PEAK_TFLOPS[args.precision], unit="TFLOP/s",
+                    frac=gram_fig["frac_peak_useful"], traffic=tr["bytes_per_launch"] / 1e9 if tr else None,
+                    launches=1, avg_launch_ms=ph["gram"], flops_per_step=gram_flops(NR, K))
     roof["traffic_unit"] = "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["traffic_source"] = tr["summary"] if tr else None
     a_bytes = NR * K * {"bf16": 2, "bf16x3": 4, "fp32": 4, "fp64": 8}[args.precision]
     c_bytes = N * N * (8 if args.precision == "fp64" else 4)
     kernels = dict(
-        gram=dict(ms=ph["gram"], tflops=gram_tf, frac_peak=gram_tf / PEAK_TFLOPS[args.precision]),
+        gram=gram_fig,
         abuild=dict(ms=ph["abuild"], gbs=a_bytes / (ph["abuild"] * 1e-3) / 1e9,
                     frac_hbm=a_bytes / (ph["abuild"] * 1e-3) / 1e9 / HBM_PEAK_GBS),
         assemble=dict(ms=ph["assemble"], gbs=c_bytes / (ph["assemble"] * 1e-3) / 1e9,
@@ -519,6 +649,9 @@ def main():
         "distinct_entries_per_s": NR * (NR + 1) / 2 / (dt / args.steps),
         "snr": math.sqrt(snr_mixed) if snr_mixed > 0 else None,
         "fp64_path": fp64,
+        "gram_variants": variants,
+        "precision_report": prec_rep,
+        "lattice": lattice,
         "fp64_chi_path": chi,
         "fp64_chi_ngins_path": ngins,
         "fp64_chi_ssc_chi_path": sscc,

@@ -64,6 +64,10 @@ typedef struct {
 
 /* Create a server.  fiducial: DEVICE tables of the base configuration (W is
  * ignored; b1, b2, n_tri optional), kept alive by the caller until destroy.
+ * n_tri, if given, holds the counts of the base configuration's triangles;
+ * a request uses the leading entries (its triangles are a prefix of the
+ * base ones), and wlc_server_submit refuses one with more triangles
+ * (WLC_EINVAL).
  * hbm_budget: bytes of the arena reserved on the current device for request
  * workspaces and results.  max_inflight: execution slots (streams). */
 int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t hbm_budget, int32_t max_inflight,

@@ -267,10 +267,23 @@ static T *at(void *ws, const Layout &L, Buf b) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + L.off[b]);
 }
 
+struct Upload { Buf b; const void *src; size_t bytes; };
+
+static int upload(const Upload *ups, size_t n, void *ws, const Layout &L, hipStream_t s) {
+  for (size_t i = 0; i < n; ++i) {
+    const Upload &u = ups[i];
+    if (!u.bytes) continue;
+    int rc = hip_check(hipMemcpyAsync(at<char>(ws, L, u.b), u.src, u.bytes, hipMemcpyHostToDevice, s),
+                       "index upload");
+    if (rc) return rc;
+  }
+  return WLC_OK;
+}
+
 // Copy the plan's index tables into the workspace (the sources live in the
 // plan, which outlives every run using it).
 static int upload_index(const Plan &p, void *ws, const Layout &L, hipStream_t s) {
-  struct Up { Buf b; const void *src; size_t bytes; } ups[] = {
+  const Upload ups[] = {
       {B_ROWR, p.rowR.data(), p.rowR.size() * 4},
       {B_ROWO, p.rowO.data(), p.rowO.size() * 4},
       {B_CFGT, p.cfgT.data(), p.cfgT.size() * 4},
@@ -283,13 +296,7 @@ static int upload_index(const Plan &p, void *ws, const Layout &L, hipStream_t s)
       {B_THR, p.lattice_thr.data(), p.lattice_thr.size() * 8},
       {B_TRI, p.triT.data(), p.triT.size() * 4},
   };
-  for (const auto &u : ups) {
-    if (!u.bytes) continue;
-    int rc = hip_check(hipMemcpyAsync(at<char>(ws, L, u.b), u.src, u.bytes, hipMemcpyHostToDevice, s),
-                       "index upload");
-    if (rc) return rc;
-  }
-  return WLC_OK;
+  return upload(ups, sizeof(ups) / sizeof(ups[0]), ws, L, s);
 }
 
 static DevTables dev_tables(const Plan &p, const wlc_tables &tb, double rho = 0.0) {
@@ -620,7 +627,11 @@ int wlc_lattice_counts(wlc_plan plan, void *ws, uint64_t *modes, uint64_t *tris,
   const Plan &p = plan->p;
   hipStream_t s = (hipStream_t)stream;
   const Layout L = run_layout(p);
-  int rc = upload_index(p, ws, L, s);
+  // only the thresholds and the triangle legs: the workspace may hold the
+  // triangle counts of a completed run, which a later structured S/N reads
+  const Upload ups[] = {{B_THR, p.lattice_thr.data(), p.lattice_thr.size() * 8},
+                        {B_TRI, p.triT.data(), p.triT.size() * 4}};
+  int rc = upload(ups, 2, ws, L, s);
   if (rc) return rc;
   const int64_t thr_max = p.lattice_thr[p.n_ell];
   launch_lattice(at<int64_t>(ws, L, B_THR), thr_max, p.n_ell, at<int32_t>(ws, L, B_TRI), p.n_tri, modes, tris, s);

@@ -126,6 +126,11 @@ struct wlc_server_s {
   std::thread worker;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   int device = 0;
+  // triangles of the base configuration: a request's triangles are a prefix
+  // of them (ell-bins cut from the top; the largest bin is the slowest index
+  // of the triangle order), so the optional fiducial counts serve requests
+  // with at most this many
+  int64_t base_n_tri = 0;
 
   double now_ms() const {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -268,11 +273,21 @@ int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t
     return fail(WLC_EINVAL, "missing fiducial table");
   auto *h = new (std::nothrow) wlc_server_s();
   if (!h) return fail(WLC_ENOMEM, "host allocation failed");
+  int rc;
   h->base = *base;
   h->base.flags |= WLC_FLAG_NOCHECK;
   h->fid = *fiducial;
+  {
+    Plan bp;
+    rc = plan_build(h->base, bp);
+    if (rc) {
+      delete h;
+      return rc;
+    }
+    h->base_n_tri = bp.n_tri;
+  }
   (void)hipGetDevice(&h->device);
-  int rc = hip_check(hipMalloc((void **)&h->arena_base, hbm_budget), "arena allocation");
+  rc = hip_check(hipMalloc((void **)&h->arena_base, hbm_budget), "arena allocation");
   if (rc) {
     delete h;
     return rc;
@@ -319,6 +334,8 @@ int wlc_server_submit(wlc_server srv, const wlc_request *q, uint64_t *ticket) {
     std::lock_guard<std::mutex> lk(srv->mu);
     srv->plans[std::make_tuple(q->n_z, q->ell_max > 0.0 ? q->ell_max : 0.0, q->precision)] = plan;
   }
+  if (srv->fid.n_tri && plan->n_tri > srv->base_n_tri)
+    return fail(WLC_EINVAL, "the request has more triangles than the fiducial triangle counts cover");
   const int64_t n = plan->n_out;
   const size_t foot = a256(plan->ws_run) + a256(plan->ws_snr) + 2 * a256(n * 8) + a256(n * 4) +
                       a256((size_t)n * n * (prec_f64(q->precision) ? 8 : 4)) +

@@ -218,6 +218,22 @@ def make_tables(preset="tiny", omega_m=0.3, sigma8=0.8, chi_grid_om=None,
                   n_m=nm, z_edges=z_edges)
 
 
+def with_bias(t: Tables) -> Tables:
+    """The same tables with mass-dependent halo biases b1(M), b2(M).
+
+    b1 has the shape 0.7 + (M / 1e13)^0.45, normalised so that
+    sum_m w_m (M_m/rho) n_m b1_m = 1 (the beta = 1 case of the
+    mass-consistency relation, eq. BoundinMass); b2 follows the published
+    quadratic-bias fit of Lazeyras et al. (2016),
+    b2 = 0.412 - 2.143 b1 + 0.929 b1^2 + 0.008 b1^3, which is negative for
+    low-mass haloes and positive for massive ones."""
+    rho = t.cfg["rho_mean"]
+    shape = 0.7 + (t.m / 1e13) ** 0.45
+    b1 = shape / np.sum(t.w_m * (t.m / rho) * t.n_m * shape)
+    b2 = 0.412 - 2.143 * b1 + 0.929 * b1 ** 2 + 0.008 * b1 ** 3
+    return dataclasses.replace(t, b1=b1, b2=b2)
+
+
 def power_law_tables(n_z=2, n_ell=4, ell_min=100.0, ell_max=1000.0, n_chi=32, n_m=8,
                      n_k=256, alpha=-1.5, amp=1e4, w_const=1e-3, chi_max=3000.0):
     """Degenerate inputs with closed-form answers: P = amp k^alpha at every chi,

@@ -100,9 +100,14 @@ def test_fp64_euclid5_sampled(wl, precision):
     prob.close()
 
 
-@pytest.mark.parametrize("precision,tol_diag,tol_snr", [("bf16x3", 1e-5, 1e-4), ("fp32", 1e-5, 1e-4),
-                                                        ("bf16", 5e-3, 5e-2)])
-def test_mixed_precision_tiny_mid(wl, precision, tol_diag, tol_snr):
+@pytest.mark.parametrize("precision,tol_diag,tol_off,tol_snr", [("bf16x3", 1e-5, 1e-5, 1e-4),
+                                                                ("fp32", 1e-5, 1e-5, 1e-4),
+                                                                ("bf16", 5e-3, 6e-3, 5e-2)])
+def test_mixed_precision_tiny_mid(wl, precision, tol_diag, tol_off, tol_snr):
+    """Tolerances: the diagonal and S/N targets of the mixed-precision path;
+    off-diagonal entries relative to sqrt(C_aa C_bb), bounded by the relative
+    error of one product term plus the FP32 accumulation (the derivation is
+    in test_gpu_precision.py)."""
     for preset in ("tiny", "mid"):
         _say("case mixed %s %s" % (precision, preset))
         t, o, ref = _oracle_full(preset)
@@ -116,6 +121,7 @@ def test_mixed_precision_tiny_mid(wl, precision, tol_diag, tol_snr):
         _say("  %s %s: diag %.2e offdiag/sqrt(CaaCbb) %.2e snr %.2e" % (precision, preset, err_diag, err_off,
                                                                       err_snr))
         assert err_diag < tol_diag
+        assert err_off < tol_off
         assert err_snr < tol_snr
         assert _rel(prob.d.cpu().numpy(), ref["d"]) < 1e-10
         prob.close()

@@ -49,14 +49,20 @@ def test_alone_equals_mix(env):
     alone = _run_alone(srv, reqs)
     tickets = [srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
                for q in reqs]
-    overlapped = 0
+    spans = []
     for q, t, (s_a, d_a, C_a, t_a) in zip(reqs, tickets, alone):
         res, d, r, C, tt = srv.fetch(t)
         assert res.status == 0
         assert res.snr2 == s_a
         assert torch.equal(d.cpu(), d_a) and torch.equal(C.cpu(), C_a) and torch.equal(tt.cpu(), t_a)
+        spans.append((res.t_admit_ms, res.t_done_ms))
         srv.release(t)
-    # the mix really ran requests side by side
+    # the mix really ran requests side by side: some request was admitted
+    # before another one had finished
+    overlapped = sum(1 for i, (a0, d0) in enumerate(spans) for j, (a1, d1) in enumerate(spans)
+                     if i < j and a1 < d0 and a0 < d1)
+    _say("  overlapping request pairs: %d" % overlapped)
+    assert overlapped >= 1
     st = srv.stats()
     assert st.completed_total == 2 * len(reqs)
     srv.close()
