@@ -230,6 +230,25 @@ int wlc_sigma_w2(wlc_plan plan, const wlc_tables *tables, double *sw, void *stre
 int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,
              double *snr2_host, void *stream);
 
+/* wlc_snr2 without allocation and without synchronisation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The same FP64 bordered
+ * Cholesky as wlc_snr2 (same kernels, same split-k choices, so the same
+ * result bit for bit), with its workspace in a fixed device array of the
+ * library: 64 MiB per device, held by every device the library has run this
+ * entry point on until the process ends.  That bounds the data vector to
+ * about 2300 rows: WLC_EINVAL (nothing enqueued) when wlc_snr2's workspace,
+ * ws_snr_bytes, exceeds 64 MiB.
+ * Inputs as wlc_snr2 (DEVICE C, row_exp2, d).  Outputs (DEVICE): snr2_dev[0]
+ * = (S/N)^2, status_dev[0] = 0, or nonzero when a pivot was not positive
+ * (then snr2_dev is meaningless).  Asynchronous on the stream; no host
+ * synchronisation, no device allocation or free.  Every call on one device
+ * shares the one array and keeps it until its work is done: calls on one
+ * device whose work overlaps (different streams, or several host threads)
+ * race; serialise them on one stream. */
+int wlc_snr2_noalloc(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, double *snr2_dev,
+                     int32_t *status_dev, void *stream);
+
 /* The cumulative (S/N)^2(ell_max) of eq. eq:SN: into snr2_host[n_ell_used]
  * (HOST), entry b is d^T C^-1 d over the rows whose legs all lie in ell-bins
  * 0..b, i.e. the data vector cut at an ell_max between bins b and b + 1; the

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -473,6 +474,59 @@ int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const dou
   return hip_check(hipGetLastError(), "snr launch");
 }
 
+// ---- fixed device scratch of wlc_snr2_noalloc
+// One array per device, holding the bordered matrix, the Cholesky's split-k
+// partials, the pivot flag and the result of one S/N at a time.  Host code
+// never uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char snr_scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES] = {};
+
+static int noalloc_scratch(void **out) {
+  int dev = 0;
+  int rc = hip_check(hipGetDevice(&dev), "current device");
+  if (rc) return rc;
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(WLC_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    rc = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(snr_scratch)), "scratch address");
+    if (rc) return rc;
+    if (!ptr) return fail(WLC_EDEVICE, "scratch address is null");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return WLC_OK;
+}
+
+__global__ void k_copy_snr_result(const int32_t *flag, const double *out, int32_t *status, double *snr2) {
+  if (threadIdx.x == 0) {
+    status[0] = flag[0];
+    snr2[0] = out[0];
+  }
+}
+
+int snr_noalloc_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const double *d, double *snr2_dev,
+                        int32_t *status_dev, hipStream_t s) {
+  const size_t need = snr_ws_bytes(p);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(WLC_EINVAL, "the data vector is too long for the fixed S/N scratch (" +
+                                std::to_string(need >> 20) + " MiB needed, 64 MiB available)");
+  void *ws = nullptr;
+  int rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  int32_t *flag = nullptr;
+  double *out = nullptr;
+  rc = snr_enqueue(p, C, row_exp2, d, ws, s, nullptr, nullptr, &flag, &out);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_copy_snr_result, dim3(1), dim3(64), 0, s, flag, out, status_dev, snr2_dev);
+  return hip_check(hipGetLastError(), "snr launch");
+}
+
 int plan_build(const wlc_config &cfg, Plan &p) {
   int rc = build_plan(cfg, p);
   if (rc) return rc;
@@ -690,6 +744,12 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
   if (h.flag) return fail(WLC_ENOTPD, "covariance is not positive definite");
   *snr2_host = h.v;
   return WLC_OK;
+}
+
+int wlc_snr2_noalloc(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, double *snr2_dev,
+                     int32_t *status_dev, void *stream) {
+  if (!plan || !C || !row_exp2 || !d || !snr2_dev || !status_dev) return fail(WLC_EINVAL, "null argument");
+  return snr_noalloc_enqueue(plan->p, C, row_exp2, d, snr2_dev, status_dev, (hipStream_t)stream);
 }
 
 int wlc_snr2_lmax(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, void *ws,

@@ -256,9 +256,11 @@ int chol_factor(double *Wm, int64_t n, int64_t ld, double *scratch, int *flag, h
   return 0;
 }
 
-// Split-k scratch rows for an n x n factorisation: slices never exceed 64 and
-// rows never exceed n + 1, so small matrices reserve little.
-int64_t chol_part_rows(int64_t n) { return std::min<int64_t>(PART_ROWS, 64 * (n + 1)); }
+// Split-k scratch rows for an n x n factorisation: the long panel updates
+// have k ranges below n, so they take at most update2_max_slices(n) slices
+// of at most n + 1 rows each; small matrices reserve little.  The reserve
+// never binds the split choice below PART_ROWS, so it does not change it.
+int64_t chol_part_rows(int64_t n) { return std::min<int64_t>(PART_ROWS, update2_max_slices(n) * (n + 1)); }
 size_t chol_scratch_bytes(int64_t n) { return (size_t)NB * NB * 8 + (size_t)chol_part_rows(n) * NB_OUT * 8; }
 
 // ------------------------------------------------------------- y^T y

@@ -216,6 +216,13 @@ __global__ void k_update_reduce(double *__restrict__ Wm, int64_t ld, int64_t c0,
   }
 }
 
+// The most k slices the split rule below can choose for a k range of k_len:
+// a slice keeps at least 32 k-steps, and there are at most 64 slices.
+int64_t update2_max_slices(int64_t k_len) {
+  const int64_t q = (k_len + UBK - 1) / UBK / 32;
+  return q < 1 ? 1 : (q > 64 ? 64 : q);
+}
+
 void launch_update2(double *Wm, int64_t ld, int64_t c0, int64_t r1, int64_t c1, int64_t k0, int64_t k1,
                     double *part, int64_t part_rows, hipStream_t s, KernelProbe *probe) {
   if (c0 >= c1 || c0 >= r1 || k0 >= k1) return;

@@ -112,6 +112,7 @@ struct KernelProbe {
 };
 int chol_factor(double *Wm, int64_t n, int64_t ld, double *scratch, int *flag, hipStream_t s,
                 KernelProbe *probe = nullptr);
+int64_t update2_max_slices(int64_t k_len);
 size_t chol_scratch_bytes(int64_t n);
 int64_t chol_part_rows(int64_t n);
 // part: split-k scratch of part_rows x 256 doubles (NULL: no split)

@@ -71,6 +71,7 @@ def _load():
     L.wlc_snr2.argtypes = [vp, vp, vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_snr2_structured.argtypes = [vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_snr2_lmax.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.wlc_snr2_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wlc_pca.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
     L.wlc_plan_timings.argtypes = [vp, vp]
@@ -82,7 +83,7 @@ lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_averaging",
             "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_noalloc", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
@@ -157,6 +158,12 @@ def wlc_snr2(plan, C, row_exp2, d, ws, stream):
     out = ct.c_double()
     _check(lib.wlc_snr2(plan, C, row_exp2, d, ws, ct.byref(out), stream))
     return out.value
+
+
+def wlc_snr2_noalloc(plan, C, row_exp2, d, snr2_dev, status_dev, stream):
+    """Enqueue (S/N)^2 into DEVICE snr2_dev[0] and the pivot status into DEVICE
+    status_dev[0], with the library's fixed scratch (no allocation, no sync)."""
+    _check(lib.wlc_snr2_noalloc(plan, C, row_exp2, d, snr2_dev, status_dev, stream))
 
 
 def wlc_snr2_lmax(plan, C, row_exp2, d, ws, stream, n_ell):
@@ -268,6 +275,12 @@ class Problem:
             self.ws_snr = self.torch.empty(int(self.sizes.ws_snr_bytes), dtype=self.torch.uint8, device=self.device)
         return wlc_snr2(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(self.ws_snr),
                         _stream_handle(stream))
+
+    def snr2_noalloc(self, out, status, stream=None):
+        """Enqueue (S/N)^2 into the device tensors out (float64) and status
+        (int32), one element each, through the fixed-scratch entry point."""
+        wlc_snr2_noalloc(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(out), _ptr(status),
+                         _stream_handle(stream))
 
     def snr2_lmax(self, stream=None):
         """(S/N)^2 of the data vector cut after each ell-bin (numpy array)."""
