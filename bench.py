@@ -56,7 +56,7 @@ def parse():
                     help="requests of the serving stream (0: skip serving)")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=180.0)
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--no-serve-fp64", action="store_true",
                     help="serve the stream in the headline precision only (default: also the plain FP64 path)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -356,11 +356,15 @@ def serve_precisions(args):
     return [args.precision] + ([] if args.no_serve_fp64 or args.precision == "fp64" else ["fp64"])
 
 
-def serving(n_req, budget_gb, slots, precisions, torch):
-    """Continuous-batching server on a seeded Poisson stream of requests
-    (Omega_m, sigma_8, n_z, l_max drawn per request): closed-loop capacity
-    first, then an open loop at half of it; per-request latency is submit to
-    completion on the server clock."""
+def serving(n_req, budget_gb, slots, precisions, torch, fractions=(0.5, 0.8)):
+    """The request server on a seeded stream of requests (Omega_m, sigma_8,
+    n_z, l_max drawn per request).  Closed loop first (every request
+    submitted at once) for the capacity, then open loops with Poisson
+    arrivals at the given fractions of it.  Each request's lensing kernels
+    are built by the client when it arrives, so a request's latency runs
+    from its arrival through that build, submission, queueing and the
+    server's work to its completion.  Finished requests are released as soon
+    as they are seen done, so the arena holds only live requests."""
     import numpy as np
     import synth
     from paper_1812_07437_amd import serve
@@ -368,60 +372,72 @@ def serving(n_req, budget_gb, slots, precisions, torch):
     reqs = synth.serving_requests(n_req, seed=1234, qps=1.0, fid=fid)
     out = {"requests": n_req, "slots": slots, "arena_gb": budget_gb,
            "mix": {"n_z": [int(q["n_z"]) for q in reqs], "ell_max": [q["ell_max"] for q in reqs]}}
+
+    def build_w(q):
+        return synth.lensing_kernels(fid.chi, q["omega_m"], synth.equipopulated_edges(q["n_z"]))
+
+    def run_stream(srv, arrivals, label):
+        """Submit request i at arrivals[i] (seconds from start; None = at once);
+        returns per-request latency (s), queue time (s) and the wall time."""
+        live = {}  # ticket -> (index, client delay before submission)
+        lat = np.zeros(n_req)
+        queue = np.zeros(n_req)
+        ok = True
+        done = 0
+        t0 = time.perf_counter()
+
+        def reap(block):
+            nonlocal done, ok
+            for t in list(live):
+                fin, r = srv.poll(t)
+                if not fin:
+                    continue
+                i, client = live.pop(t)
+                lat[i] = client + (r.t_done_ms - r.t_submit_ms) * 1e-3
+                queue[i] = (r.t_admit_ms - r.t_submit_ms) * 1e-3
+                ok &= r.status == 0
+                srv.release(t)
+                done += 1
+                if done % 10 == 0 or done == n_req:
+                    log("  %s: %d/%d done at %.1f s" % (label, done, n_req, time.perf_counter() - t0))
+            if block and live:
+                time.sleep(0.0005)
+
+        for i, q in enumerate(reqs):
+            ta = arrivals[i] if arrivals is not None else 0.0
+            while time.perf_counter() - t0 < ta:
+                reap(False)
+                time.sleep(0.0002)
+            W = build_w(q)
+            t = srv.submit(W, q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+            live[t] = (i, time.perf_counter() - t0 - ta)
+        while live:
+            reap(True)
+        return lat, queue, time.perf_counter() - t0, ok
+
     for prec in precisions:
         srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=int(budget_gb * (1 << 30)), max_inflight=slots,
                            precision=prec)
-
-        def submit(q):
-            return srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
-
-        # closed loop: everything at once
-        # (a request holds its arena memory until released, and admission is
-        # in arrival order: release each one as soon as it is done)
-        t0 = time.perf_counter()
-        ts = [submit(q) for q in reqs]
-        for i, t in enumerate(ts):
-            r = srv.wait(t)
-            log("  closed loop %s: request %d/%d done at %.0f ms (n=%d)" % (prec, i + 1, n_req, r.t_done_ms,
-                                                                            r.n_data))
-            srv.release(t)
-        t_closed = time.perf_counter() - t0
+        st0 = srv.stats()
+        lat, _, t_closed, ok = run_stream(srv, None, "closed loop %s" % prec)
         cap = n_req / t_closed
-        # open loop: Poisson arrivals at half the capacity
-        qps = 0.5 * cap
-        gaps = np.random.default_rng(1234).exponential(1.0 / qps, size=n_req)
-        arrivals = np.cumsum(gaps)
-        t0 = time.perf_counter()
-        ts, res, released = [], [], 0
-        for q, ta in zip(reqs, arrivals):
-            while time.perf_counter() - t0 < ta:
-                # release finished requests in order while waiting for the next arrival
-                while released < len(ts):
-                    done, r = srv.poll(ts[released])
-                    if not done:
-                        break
-                    res.append(r)
-                    srv.release(ts[released])
-                    released += 1
-                time.sleep(0.0005)
-            ts.append(submit(q))
-        while released < len(ts):
-            r = srv.wait(ts[released])
-            res.append(r)
-            srv.release(ts[released])
-            released += 1
-            log("  open loop %s: request %d/%d done" % (prec, released, n_req))
-        t_open = time.perf_counter() - t0
-        lat = np.array([r.t_done_ms - r.t_submit_ms for r in res])
-        qwait = np.array([r.t_admit_ms - r.t_submit_ms for r in res])
+        res = dict(closed_loop_req_per_s=cap, closed_loop_s=t_closed, all_ok=ok)
+        log("serve %s: closed loop %d requests in %.1f s (%.2f req/s)" % (prec, n_req, t_closed, cap))
+        for f in fractions:
+            qps = f * cap
+            arrivals = np.cumsum(np.random.default_rng(1234).exponential(1.0 / qps, size=n_req))
+            lat, queue, t_open, ok = run_stream(srv, arrivals, "open loop %s at %.0f%%" % (prec, 100 * f))
+            key = "open_%d" % round(100 * f)
+            res[key] = dict(fraction_of_capacity=f, qps=qps, achieved_req_per_s=n_req / t_open, n=n_req,
+                            p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                            max_ms=float(lat.max() * 1e3), mean_queue_ms=float(queue.mean() * 1e3), all_ok=ok)
+            log("serve %s at %.0f%% (%.2f qps): p50 %.0f ms p99 %.0f ms (n = %d), mean queue %.0f ms" % (
+                prec, 100 * f, qps, res[key]["p50_ms"], res[key]["p99_ms"], n_req, res[key]["mean_queue_ms"]))
         st = srv.stats()
+        res.update(batches=st.batches - st0.batches, batched_requests=st.batched_requests - st0.batched_requests,
+                   max_batch=st.max_batch, arena_peak_gb=st.arena_peak / 2 ** 30)
         srv.close()
-        ok = all(r.status == 0 for r in res)
-        out[prec] = dict(closed_loop_req_per_s=cap, qps=qps, achieved_req_per_s=n_req / t_open,
-                         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                         mean_queue_ms=float(qwait.mean()), arena_peak_gb=st.arena_peak / 2 ** 30, all_ok=ok)
-        log("serve %s: capacity %.2f req/s, open loop at %.2f qps: p50 %.0f ms p99 %.0f ms" %
-            (prec, cap, qps, out[prec]["p50_ms"], out[prec]["p99_ms"]))
+        out[prec] = res
         torch.cuda.empty_cache()
     return out
 
@@ -444,7 +460,7 @@ def main():
         return
 
     if args.serve_only:
-        srv = serving(args.serve_requests or 24, args.serve_budget_gb, args.serve_slots, ["bf16x3", "fp64"], torch)
+        srv = serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, serve_precisions(args), torch)
         print(json.dumps({"metric": "serving p50/p99 latency (ms) and requests/s", "data": "synthetic",
                           "serving": srv}), flush=True)
         return

@@ -6,11 +6,19 @@
  * The paper computes the data vector, covariance and S/N for one survey set-up
  * at a time (Rizzato et al. 2019, Secs. 3 and 5, eq. eq:SN for the cut at
  * l_max); a likelihood code needs the same quantities for many nearby set-ups.
- * The server keeps the chi / k / M tables on the device, admits requests in
+ * The server keeps the chi / k / M tables on the device and admits requests in
  * arrival order as soon as their device-memory footprint fits a fixed arena
- * and an execution slot is free, and runs every admitted request on its own
- * HIP stream, so requests that arrive while others run overlap with them on
- * the device.  Each request's result does not depend on what else is running.
+ * and an execution slot is free.  An admitted request runs its quadrature
+ * and A-build on its own HIP stream; the one-halo Gram products of the bf16
+ * and split-bf16 requests admitted so far are then batched into one
+ * persistent kernel that drains a device queue of their tile work items
+ * (requests of different sizes in one launch; a narrow and a wide batch lane
+ * so that small requests do not wait behind the product of a large one);
+ * assembly and the FP64 Cholesky follow on the request's own stream, so
+ * requests that arrive while others run overlap with them on the device.
+ * FP64 and FP32 requests compute their Gram product on their own stream.
+ * Each request's result does not depend on what else is running: a product
+ * in a batch runs the same tiles, k slices and summation order as alone.
  *
  * Conventions as in wlcov.h (int return codes, wlc_last_error()).
  */
@@ -60,6 +68,9 @@ typedef struct {
   int64_t queued, running, done;
   size_t arena_bytes, arena_used, arena_peak;
   int64_t completed_total;
+  int64_t batches;           /* batched Gram launches so far                    */
+  int64_t batched_requests;  /* requests whose Gram ran in a batched launch     */
+  int64_t max_batch;         /* most requests in one batched launch             */
 } wlc_server_stats;
 
 /* Create a server.  fiducial: DEVICE tables of the base configuration (W is
@@ -69,7 +80,8 @@ typedef struct {
  * base ones), and wlc_server_submit refuses one with more triangles
  * (WLC_EINVAL).
  * hbm_budget: bytes of the arena reserved on the current device for request
- * workspaces and results.  max_inflight: execution slots (streams). */
+ * workspaces and results.  max_inflight: execution slots (streams), 1..64,
+ * which also bounds the requests of one batch. */
 int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t hbm_budget, int32_t max_inflight,
                       wlc_server *out);
 

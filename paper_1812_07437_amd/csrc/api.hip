@@ -333,8 +333,7 @@ int validate_tables(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s
   return WLC_OK;
 }
 
-int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
-                hipStream_t s, PhaseHooks *hooks, double rho) {
+int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s, PhaseHooks *hooks, double rho) {
   int rc = check_tables_present(tb);
   if (rc) return rc;
   const wlc_config &c = p.cfg;
@@ -376,36 +375,67 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   }
   if (hooks) hooks->end(WLC_PHASE_TABLES);
 
+  // the flattened factor A (none in the chi-factorised form)
+  if (hooks) hooks->begin(WLC_PHASE_ABUILD);
+  if (c.precision != WLC_FP64_CHI) {
+    const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
+    launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, n_mg, p.k_pad, p.k_pad, at<void>(ws, L, B_A0),
+                  at<void>(ws, L, B_A1), s);
+  }
+  if (hooks) hooks->end(WLC_PHASE_ABUILD);
+  return hip_check(hipGetLastError(), "run launch");
+}
+
+static GramShape gram_shape(const Plan &p) { return GramShape{p.r_pad, p.k_pad, p.r_pad, p.k_pad}; }
+
+int run_enqueue_gram(const Plan &p, void *ws, hipStream_t s, PhaseHooks *hooks) {
+  const wlc_config &c = p.cfg;
+  const Layout L = run_layout(p);
   void *Gm = at<void>(ws, L, B_GM);
+  if (hooks) hooks->begin(WLC_PHASE_GRAM);
   if (c.precision == WLC_FP64_CHI) {
     // no flattened factor: the one-halo product from T and G directly
-    if (hooks) hooks->begin(WLC_PHASE_ABUILD);
-    if (hooks) hooks->end(WLC_PHASE_ABUILD);
-    if (hooks) hooks->begin(WLC_PHASE_GRAM);
     const int nz = c.n_z;
-    launch_chifact(Ts, G, at<double>(ws, L, B_H), n_cfg, c.n_chi, n_mg, p.n_ell, nz * (nz + 1) / 2,
-                   nz * (nz + 1) * (nz + 2) / 6, p.n_tri, (double *)Gm, p.r_pad, s);
-    if (hooks) hooks->end(WLC_PHASE_GRAM);
+    launch_chifact(at<double>(ws, L, B_TS), at<double>(ws, L, B_G), at<double>(ws, L, B_H), (int)p.cfgs.size(),
+                   c.n_chi, g_cols(c), p.n_ell, nz * (nz + 1) / 2, nz * (nz + 1) * (nz + 2) / 6, p.n_tri,
+                   (double *)Gm, p.r_pad, s);
   } else {
-    const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
-    void *A0 = at<void>(ws, L, B_A0), *A1 = at<void>(ws, L, B_A1);
-    if (hooks) hooks->begin(WLC_PHASE_ABUILD);
-    launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, n_mg, p.k_pad, p.k_pad, A0, A1, s);
-    if (hooks) hooks->end(WLC_PHASE_ABUILD);
-    GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
-    if (hooks) hooks->begin(WLC_PHASE_GRAM);
-    launch_gram(c.precision, g, A0, A1, Gm, at<void>(ws, L, B_PART), s);
-    if (hooks) hooks->end(WLC_PHASE_GRAM);
+    launch_gram(c.precision, gram_shape(p), at<void>(ws, L, B_A0), at<void>(ws, L, B_A1), Gm, at<void>(ws, L, B_PART),
+                s);
   }
+  if (hooks) hooks->end(WLC_PHASE_GRAM);
+  return hip_check(hipGetLastError(), "gram launch");
+}
 
+bool run_gram_batchable(const Plan &p) { return gram_batchable(p.cfg.precision); }
+
+void run_gram_job(const Plan &p, void *ws, GramJob &job) {
+  const Layout L = run_layout(p);
+  gram_job(p.cfg.precision, gram_shape(p), at<void>(ws, L, B_A0), at<void>(ws, L, B_A1), at<void>(ws, L, B_GM),
+           at<void>(ws, L, B_PART), job);
+}
+
+int run_enqueue_gram_reduce(const Plan &p, void *ws, hipStream_t s) {
+  const Layout L = run_layout(p);
+  launch_gram_reduce(p.cfg.precision, gram_shape(p), at<void>(ws, L, B_GM), at<void>(ws, L, B_PART), s);
+  return hip_check(hipGetLastError(), "gram reduce launch");
+}
+
+int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
+                     hipStream_t s, PhaseHooks *hooks) {
+  const wlc_config &c = p.cfg;
+  const Layout L = run_layout(p);
+  int rc = WLC_OK;
+  void *Gm = at<void>(ws, L, B_GM);
+  const bool ssc_chi = (c.flags & WLC_FLAG_SSC_CHI) != 0;
   AsmArgs a{};
   a.rowO = at<int32_t>(ws, L, B_ROWO);
-  a.cfgT = cfgT;
-  a.sexp = sexp;
+  a.cfgT = at<int32_t>(ws, L, B_CFGT);
+  a.sexp = at<int32_t>(ws, L, B_SEXP);
   a.Gm = Gm;
   a.ld_g = p.r_pad;
   a.gm_f32 = !prec_f64(c.precision);
-  a.Ps = Ps;
+  a.Ps = at<double>(ws, L, B_PS);
   a.nmodes = at<double>(ws, L, B_NMODES);
   if (tb.n_tri && p.n_tri > 0) {  // the workspace keeps the counts this run used
     rc = hip_check(hipMemcpyAsync(at<double>(ws, L, B_NTRI), tb.n_tri, (size_t)p.n_tri * 8, hipMemcpyDeviceToDevice,
@@ -413,8 +443,8 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
     if (rc) return rc;
   }
   a.ntri = at<double>(ws, L, B_NTRI);
-  a.rR = rR;
-  a.dR = dR;
+  a.rR = at<double>(ws, L, B_RR);
+  a.dR = at<double>(ws, L, B_DR);
   a.n_z = c.n_z;
   a.n_ell = p.n_ell;
   a.n = p.n_out;
@@ -430,6 +460,14 @@ int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double
   launch_assemble(a, row_exp2, C, !prec_f64(c.precision), s);
   if (hooks) hooks->end(WLC_PHASE_ASSEMBLE);
   return hip_check(hipGetLastError(), "run launch");
+}
+
+int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
+                hipStream_t s, PhaseHooks *hooks, double rho) {
+  int rc = run_enqueue_front(p, tb, ws, s, hooks, rho);
+  if (!rc) rc = run_enqueue_gram(p, ws, s, hooks);
+  if (!rc) rc = run_enqueue_back(p, tb, ws, d, r, C, row_exp2, s, hooks);
+  return rc;
 }
 
 int snr_enqueue(const Plan &p, const void *C, const int32_t *row_exp2, const double *d, void *ws, hipStream_t s,

@@ -30,6 +30,22 @@ int validate_tables(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s
 int run_enqueue(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
                 hipStream_t s, PhaseHooks *hooks, double rho = 0.0);
 
+// The same path in three parts, so that the Gram products of several runs
+// can share one batched launch (the request server): front = index upload,
+// staging, quadrature, projection and A-build; gram = the one-halo product
+// with its split-K reduction; back = mirror, row exponents and assembly.
+int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s, PhaseHooks *hooks,
+                      double rho = 0.0);
+int run_enqueue_gram(const Plan &p, void *ws, hipStream_t s, PhaseHooks *hooks);
+int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
+                     hipStream_t s, PhaseHooks *hooks);
+// For a batched Gram instead of run_enqueue_gram: whether the plan's
+// precision has a batched kernel, the plan's product as a batch job (item0
+// left 0), and its split-K reduction, enqueued after the batch.
+bool run_gram_batchable(const Plan &p);
+void run_gram_job(const Plan &p, void *ws, GramJob &job);
+int run_enqueue_gram_reduce(const Plan &p, void *ws, hipStream_t s);
+
 // Enqueue the S/N factorisation (no synchronisation).  On completion
 // *flag_dev != 0 marks a non-positive pivot and *out_dev holds (S/N)^2.
 // With lmax, the rows are taken in ell_max order and *out_dev holds the

@@ -29,6 +29,8 @@
 // tile fetching its own panels from HBM.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "f64tile.h"
 #include "kernels.h"
 
@@ -82,16 +84,23 @@ __device__ __forceinline__ void sb_tile(int64_t t, int nt, int &I, int &J) {
 // step, so the panels are shared through L2.  Returns false for padding.
 constexpr int GS = 32;
 
-__device__ __forceinline__ bool gram_work(int64_t n_work, int n_split, int nt, int &I, int &J, int &split) {
-  const int64_t per = (int64_t)gridDim.x / N_XCD;
-  const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
-  if (w >= n_work) return false;
+// Work item w of a product with n_work = tiles x n_split items -> (tile,
+// split), in the order described above.
+__device__ __forceinline__ void gram_item(int64_t w, int64_t n_work, int n_split, int nt, int &I, int &J,
+                                          int &split) {
   const int64_t n_tiles = n_work / n_split;
   const int64_t grp = w / ((int64_t)GS * n_split), base = grp * GS;
   const int64_t gsz = n_tiles - base < GS ? n_tiles - base : GS;
   const int64_t u = w - grp * GS * n_split;
   split = (int)(u / gsz);
   sb_tile(base + u % gsz, nt, I, J);
+}
+
+__device__ __forceinline__ bool gram_work(int64_t n_work, int n_split, int nt, int &I, int &J, int &split) {
+  const int64_t per = (int64_t)gridDim.x / N_XCD;
+  const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
+  if (w >= n_work) return false;
+  gram_item(w, n_work, n_split, nt, I, J, split);
   return true;
 }
 
@@ -167,18 +176,17 @@ struct GramDma {
   }
 };
 
+// One work item: tile (I, J), k slice split, through the workgroup's two LDS
+// stage buffers (distinct __shared__ arrays of the calling kernel).
 template <bool X3, int NW>
-__global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
-                                                  int64_t k_pad, int64_t r_pad, int64_t k_split, int n_split,
-                                                  int nt, int64_t n_work, float *__restrict__ out,
-                                                  float *__restrict__ partial, int64_t ld, int64_t part_stride) {
+__device__ __forceinline__ void gram_bf16_tile(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
+                                               int64_t k_pad, int64_t r_pad, int64_t k_split, int I, int J,
+                                               int split, float *__restrict__ out, float *__restrict__ partial,
+                                               int64_t ld, int64_t part_stride,
+                                               uint16_t (*lds0)[2][T2 * BK2], uint16_t (*lds1)[2][T2 * BK2]) {
   constexpr int NOPS = X3 ? 2 : 1;  // hi (and lo)
-  __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];  // [op][I/J side]
-  __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  int I, J, split;
-  if (!gram_work(n_work, n_split, nt, I, J, split)) return;
   const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
   const int64_t kb = (int64_t)split * k_split;
   const int64_t ke = min(k_pad, kb + k_split);
@@ -255,6 +263,75 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
         const int64_t c = col0 + wc + j * 32 + (lane & 31);
         dst[r * ld + c] = acc[i][j][v];
       }
+}
+
+template <bool X3, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
+                                                  int64_t k_pad, int64_t r_pad, int64_t k_split, int n_split,
+                                                  int nt, int64_t n_work, float *__restrict__ out,
+                                                  float *__restrict__ partial, int64_t ld, int64_t part_stride) {
+  constexpr int NOPS = X3 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];  // [op][I/J side]
+  __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
+  int I, J, split;
+  if (!gram_work(n_work, n_split, nt, I, J, split)) return;
+  gram_bf16_tile<X3, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, lds0, lds1);
+}
+
+// ---------------------------------------------------------------- batched
+// One persistent launch over the work items of several products (the Gram
+// products of several requests of a server, each with its own operands,
+// output, split-K choice and partial buffer).  Items are numbered product
+// after product, each product's items in the order of gram_item, so that a
+// product computes exactly what its own launch would (the same tiles, k
+// slices and summation order).  The item range is cut into N_XCD contiguous
+// queues; a workgroup claims items of its own XCD's queue (workgroup b runs
+// on XCD b mod N_XCD) one at a time with an atomic counter, so the
+// workgroups resident on an XCD walk consecutive items as in the direct
+// launch, and moves on to the next queue when its own is drained.  Every
+// workgroup leaves after finding all N_XCD queues drained, and items never
+// wait for one another, so the grid drains whatever the residency.
+constexpr int QSTRIDE = 16;  // counters 64 bytes apart
+
+template <bool X3, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__restrict__ jobs, int n_jobs,
+                                                        int64_t total, uint32_t *__restrict__ counters) {
+  constexpr int NOPS = X3 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];
+  __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
+  __shared__ int64_t s_item;
+  const int x0 = blockIdx.x % N_XCD;
+  int q = 0;
+  while (q < N_XCD) {
+    const int x = (x0 + q) % N_XCD;
+    const int64_t lo = total * x / N_XCD, hi = total * (x + 1) / N_XCD;
+    __syncthreads();  // the previous item's LDS reads and s_item are done
+    if (threadIdx.x == 0) {
+      const int64_t g = lo + (int64_t)atomicAdd(&counters[QSTRIDE * x], 1u);
+      s_item = g < hi ? g : -1;
+    }
+    __syncthreads();
+    const int64_t g = s_item;
+    if (g < 0) {
+      ++q;
+      continue;
+    }
+    int a = 0, b = n_jobs - 1;  // the job whose items hold g: largest item0 <= g
+    while (a < b) {
+      const int m = (a + b + 1) / 2;
+      if (jobs[m].item0 <= g) a = m; else b = m - 1;
+    }
+    const GramJob &jb = jobs[a];
+    int I, J, split;
+    gram_item(g - jb.item0, jb.n_work, jb.n_split, jb.nt, I, J, split);
+    gram_bf16_tile<X3, NW>((const uint16_t *)jb.A0, (const uint16_t *)jb.A1, jb.k_pad, jb.r_pad, jb.k_split, I, J,
+                           split, (float *)jb.out, (float *)jb.partial, jb.ld, jb.part_stride, lds0, lds1);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
 }
 
 // ===================================================================== f32 / f64
@@ -498,15 +575,98 @@ size_t gram_partial_bytes(int prec, const GramShape &g) {
   return (size_t)(s - 1) * g.r_pad * g.ld_out * el;  // slice 0 goes to the output
 }
 
+// Tiles, split-K slices and work items of one product: a function of its
+// shape and precision only, so a product is computed the same way alone and
+// in a batch.
+struct GramSplit {
+  int64_t nt, tiles, ksplit, pstride, n_work;
+  int ns;
+};
+
+static GramSplit gram_split(int prec, const GramShape &g) {
+  GramSplit q;
+  q.nt = g.r_pad / gram_tile(prec);
+  q.tiles = gram_tile_count(prec, g);
+  const int bk = gram_bk(prec);
+  q.ns = pick_split(q.tiles, g.k_pad, bk, is_bf16(prec));
+  q.ksplit = (g.k_pad / bk + q.ns - 1) / q.ns * bk;
+  q.pstride = q.ns > 1 ? g.r_pad * g.ld_out : 0;
+  q.n_work = q.tiles * q.ns;
+  return q;
+}
+
+bool gram_batchable(int prec) { return is_bf16(prec); }
+
+void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job) {
+  const GramSplit q = gram_split(prec, g);
+  job.A0 = A0;
+  job.A1 = A1;
+  job.out = out;
+  job.partial = partial;
+  job.r_pad = g.r_pad;
+  job.k_pad = g.k_pad;
+  job.k_split = q.ksplit;
+  job.ld = g.ld_out;
+  job.part_stride = q.pstride;
+  job.n_work = q.n_work;
+  job.item0 = 0;
+  job.n_split = q.ns;
+  job.nt = (int32_t)q.nt;
+}
+
+// Workgroups of the batched kernel that fit on the device at once (the grid
+// of the persistent launch), a multiple of N_XCD.
+template <bool X3>
+static int batch_slots() {
+  static int slots = 0;  // per process: every device here is the same part
+  if (!slots) {
+    int dev = 0, cus = 0, occ = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gram_bf16_batch<X3, GRAM_NW>, 64 * GRAM_NW, 0) !=
+            hipSuccess || occ <= 0)
+      occ = 1;
+    slots = (cus * occ + N_XCD - 1) / N_XCD * N_XCD;
+  }
+  return slots;
+}
+
+int launch_gram_batch(int prec, const GramJob *jobs_dev, int n_jobs, int64_t total, uint32_t *counters,
+                      hipStream_t s) {
+  if (!gram_batchable(prec) || n_jobs < 1 || total < 1) return -1;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(GRAM_BATCH_COUNTERS), 0, s, counters, GRAM_BATCH_COUNTERS);
+  const bool x3 = prec == WLC_BF16X3;
+  const int64_t slots = x3 ? batch_slots<true>() : batch_slots<false>();
+  const unsigned grid = (unsigned)std::min<int64_t>(slots, (total + N_XCD - 1) / N_XCD * N_XCD);
+  if (x3)
+    hipLaunchKernelGGL((k_gram_bf16_batch<true, GRAM_NW>), dim3(grid), dim3(64 * GRAM_NW), 0, s, jobs_dev, n_jobs,
+                       total, counters);
+  else
+    hipLaunchKernelGGL((k_gram_bf16_batch<false, GRAM_NW>), dim3(grid), dim3(64 * GRAM_NW), 0, s, jobs_dev, n_jobs,
+                       total, counters);
+  return 0;
+}
+
+void launch_gram_reduce(int prec, const GramShape &g, void *out, void *partial, hipStream_t s) {
+  const GramSplit q = gram_split(prec, g);
+  if (q.ns <= 1) return;
+  // the reduction walks the lower triangle in 128 x 128 tiles, which the
+  // 256 x 256 tiles cover exactly
+  const int64_t nr = g.r_pad / TILE;
+  const unsigned rt = (unsigned)(nr * (nr + 1) / 2);
+  if (prec == WLC_FP64)
+    hipLaunchKernelGGL(k_gram_reduce<double>, dim3(rt), dim3(256), 0, s, (const double *)partial, q.ns, q.pstride,
+                       (double *)out, g.ld_out);
+  else
+    hipLaunchKernelGGL(k_gram_reduce<float>, dim3(rt), dim3(256), 0, s, (const float *)partial, q.ns, q.pstride,
+                       (float *)out, g.ld_out);
+}
+
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
                  hipStream_t s) {
-  const int64_t nt = g.r_pad / gram_tile(prec);
-  const int64_t tiles = gram_tile_count(prec, g);
-  const int bk = gram_bk(prec);
-  const int ns = pick_split(tiles, g.k_pad, bk, is_bf16(prec));
-  int64_t ksplit = (g.k_pad / bk + ns - 1) / ns * bk;
-  const int64_t pstride = ns > 1 ? g.r_pad * g.ld_out : 0;
-  const int64_t n_work = tiles * ns;
+  const GramSplit q = gram_split(prec, g);
+  const int64_t nt = q.nt, tiles = q.tiles, ksplit = q.ksplit, pstride = q.pstride, n_work = q.n_work;
+  const int ns = q.ns;
   const dim3 grid((unsigned)((n_work + N_XCD - 1) / N_XCD * N_XCD));
   const int nti = (int)nt;
   switch (prec) {
@@ -534,18 +694,8 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
                          n_work, (double *)out, (double *)partial, g.ld_out, pstride);
       break;
   }
-  if (ns > 1) {
-    // the reduction walks the lower triangle in 128 x 128 tiles, which the
-    // 256 x 256 tiles cover exactly
-    const int64_t nr = g.r_pad / TILE;
-    const unsigned rt = (unsigned)(nr * (nr + 1) / 2);
-    if (prec == WLC_FP64)
-      hipLaunchKernelGGL(k_gram_reduce<double>, dim3(rt), dim3(256), 0, s, (const double *)partial, ns, pstride,
-                         (double *)out, g.ld_out);
-    else
-      hipLaunchKernelGGL(k_gram_reduce<float>, dim3(rt), dim3(256), 0, s, (const float *)partial, ns, pstride,
-                         (float *)out, g.ld_out);
-  }
+  (void)tiles;
+  launch_gram_reduce(prec, g, out, partial, s);
 }
 
 }  // namespace wlc

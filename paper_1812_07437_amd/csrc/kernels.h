@@ -62,6 +62,25 @@ struct GramShape {
 size_t gram_partial_bytes(int prec, const GramShape &g);
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
                  hipStream_t s);
+// Batched bf16 Gram products (one persistent launch over the work items of
+// several products, e.g. of the requests of a server).  A product in a
+// batch computes exactly what launch_gram computes for it: the same tiles,
+// k slices and partial buffer, followed by its own launch_gram_reduce.
+struct GramJob {
+  const void *A0, *A1;   // hi (and lo) operands, k-blocked
+  void *out, *partial;   // FP32 output and split-K partials
+  int64_t r_pad, k_pad, k_split, ld, part_stride;
+  int64_t n_work;        // work items: tiles x n_split
+  int64_t item0;         // first item of this product in the batch (set by the caller)
+  int32_t n_split, nt;
+};
+bool gram_batchable(int prec);  // bf16 and split bf16
+void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job);
+// counters: N_XCD x 16 uint32 of device scratch, cleared by the launch itself
+constexpr int GRAM_BATCH_COUNTERS = 8 * 16;
+int launch_gram_batch(int prec, const GramJob *jobs_dev, int n_jobs, int64_t total, uint32_t *counters,
+                      hipStream_t s);
+void launch_gram_reduce(int prec, const GramShape &g, void *out, void *partial, hipStream_t s);
 // One-halo product through the chi factorisation (k_chifact.hip): H (scratch,
 // n_cfg^2 n_chi doubles) from the configuration factors G, then the lower
 // triangle of out[e][f] = sum_n Ts[e][n] Ts[f][n] H[c(e)][c(f)][n] over the

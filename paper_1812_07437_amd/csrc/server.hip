@@ -3,13 +3,28 @@
 //
 // One worker thread owns every HIP call.  Requests wait in arrival order;
 // the head request is admitted as soon as an execution slot (a stream of
-// default priority) is free and its device footprint fits the arena, so a
-// request that arrives while others run starts beside them and their kernels
-// overlap on the device.  Device memory comes from one arena allocated at
-// creation (first-fit free list on the host), so admission and release never
-// call the device allocator.  Plans are cached per (n_z, l_max, precision).
+// default priority) is free and its device footprint fits the arena.  Device
+// memory comes from one arena allocated at creation (first-fit free list on
+// the host), so admission and release never call the device allocator.
+// Plans are cached per (n_z, l_max, precision).
+//
+// Each admitted request runs its table staging, quadrature, projection and
+// A-build on its slot's stream.  The one-halo Gram products of bf16 and split
+// bf16 requests are then batched: whenever a batch lane is idle, every
+// admitted request whose A-build has been enqueued (and not yet batched)
+// joins one persistent Gram launch on that lane's stream, which drains a
+// device queue holding the tile work items of all of them (k_gram_bf16_batch:
+// each request's items are the ones its own launch would run, so its result
+// does not depend on the batch).  Requests arriving while a batch runs wait
+// for the next one.  Two lanes keep small requests from waiting behind the
+// Gram of a large one: products of less than LANE_SPLIT work units go to the
+// narrow lane, the others to the wide lane, and the two lanes' launches run
+// side by side.  After its batch, each request's split-K reduction, assembly
+// and FP64 Cholesky run on its own stream again, overlapping with other
+// requests' work.  FP64 and FP32 requests run their own Gram on their stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -85,20 +100,42 @@ struct Request {
   int status = WLC_OK;
   size_t footprint = 0, off = 0;
   int slot = -1;
+  bool batched = false;       // Gram in a batched persistent launch
+  bool back_enqueued = false; // its done event is recorded
   double t_submit = 0, t_admit = 0, t_done = 0, snr2 = 0;
   // device pointers inside the arena
   char *ws_run = nullptr, *ws_snr = nullptr;
   double *d = nullptr, *r = nullptr, *P = nullptr, *nm = nullptr, *Wd = nullptr;
   void *C = nullptr;
   int32_t *t = nullptr;
+  wlc_tables tb{};
 };
 
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  hipEvent_t front = nullptr;    // the request's A-build is complete
   double *pinned_W = nullptr;    // staging for the kernels upload
   double *pinned_out = nullptr;  // [flag, snr2]
   uint64_t ticket = 0;
+  bool busy = false;
+};
+
+// Products below this many work units (items x k per item) go to the
+// narrow batch lane: at the serving grid (K = 32768) that is every request
+// but the largest few (n_z >= 7 with l_max = 5000).
+constexpr double LANE_SPLIT = 16777216.0;
+constexpr int MAX_BATCH = 64;
+
+// A batch lane: one stream for its persistent launches, the device job
+// list and queue counters, and the pinned staging of the job list (rewritten
+// only while the lane is idle, so the previous upload has completed).
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  GramJob *jobs_dev = nullptr;
+  GramJob *jobs_host = nullptr;
+  uint32_t *counters = nullptr;
   bool busy = false;
 };
 
@@ -114,14 +151,17 @@ struct wlc_server_s {
   char *arena_base = nullptr;
   std::unique_ptr<Arena> arena;
   std::vector<Slot> slots;
+  Lane lanes[2];
   size_t w_stage_doubles = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> pending;
+  std::deque<uint64_t> gram_ready;  // admitted, A-build enqueued, waiting for a batch
   std::unordered_map<uint64_t, Request> reqs;
   std::map<std::tuple<int, double, int>, std::shared_ptr<Plan>> plans;
   uint64_t next_ticket = 1;
   int64_t completed = 0;
+  int64_t n_batches = 0, n_batched = 0, max_batch = 0;
   bool stop = false;
   std::thread worker;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -136,8 +176,10 @@ struct wlc_server_s {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
 
-  // Enqueue all device work of an admitted request on its slot's stream.
-  int launch(Request &R, Slot &S) {
+  // Carve the request's buffers out of its arena block, upload its kernels,
+  // rescale the shared tables and enqueue everything up to the A-build (and
+  // the Gram itself when it is not batched).
+  int launch_front(Request &R, Slot &S) {
     const Plan &p = *R.plan;
     const int64_t n = p.n_out;
     char *mem = arena_base + R.off;
@@ -153,8 +195,8 @@ struct wlc_server_s {
     R.r = (double *)take(n * 8);
     R.t = (int32_t *)take(n * 4);
     R.C = take((size_t)n * n * (prec_f64(p.cfg.precision) ? 8 : 4));
-    R.P = (double *)take((size_t)base_cfg().n_chi * base_cfg().n_k * 8);
-    R.nm = (double *)take((size_t)base_cfg().n_m * 8);
+    R.P = (double *)take((size_t)base.n_chi * base.n_k * 8);
+    R.nm = (double *)take((size_t)base.n_m * 8);
     R.Wd = (double *)take(R.W.size() * 8);
     hipStream_t s = S.stream;
     std::memcpy(S.pinned_W, R.W.data(), R.W.size() * 8);
@@ -162,11 +204,29 @@ struct wlc_server_s {
     if (rc) return rc;
     launch_scale(fid.P, R.P, (int64_t)base.n_chi * base.n_k, R.q.p_scale, s);
     launch_scale(fid.n_m, R.nm, base.n_m, R.q.n_scale, s);
-    wlc_tables tb = fid;
-    tb.P = R.P;
-    tb.n_m = R.nm;
-    tb.W = R.Wd;
-    rc = run_enqueue(p, tb, R.ws_run, R.d, R.r, R.C, R.t, s, nullptr, R.q.rho_mean);
+    R.tb = fid;
+    R.tb.P = R.P;
+    R.tb.n_m = R.nm;
+    R.tb.W = R.Wd;
+    rc = run_enqueue_front(p, R.tb, R.ws_run, s, nullptr, R.q.rho_mean);
+    if (rc) return rc;
+    if (R.batched) return hip_check(hipEventRecord(S.front, s), "event record");
+    return run_enqueue_gram(p, R.ws_run, s, nullptr);
+  }
+
+  // Everything after the Gram product, on the request's stream: for a
+  // batched request, wait for its batch and reduce its split-K slices; then
+  // assembly, the FP64 Cholesky and the result copies.
+  int launch_back(Request &R, Slot &S, hipEvent_t batch_done) {
+    const Plan &p = *R.plan;
+    hipStream_t s = S.stream;
+    int rc = WLC_OK;
+    if (R.batched) {
+      rc = hip_check(hipStreamWaitEvent(s, batch_done, 0), "wait for the batch");
+      if (!rc) rc = run_enqueue_gram_reduce(p, R.ws_run, s);
+      if (rc) return rc;
+    }
+    rc = run_enqueue_back(p, R.tb, R.ws_run, R.d, R.r, R.C, R.t, s, nullptr);
     if (rc) return rc;
     int32_t *flag = nullptr;
     double *out = nullptr;
@@ -178,7 +238,95 @@ struct wlc_server_s {
     return rc;
   }
 
-  const wlc_config &base_cfg() const { return base; }
+  // One persistent Gram launch over the members' work items on a lane, then
+  // every member's remaining work on its own stream.  Returns an error that
+  // concerns the whole batch; a member whose own work could not be enqueued
+  // gets its error in err.
+  int launch_batch(Lane &L, std::vector<Request *> &mem, std::vector<int> &err) {
+    hipStream_t s = L.stream;
+    int64_t total = 0;
+    for (size_t i = 0; i < mem.size(); ++i) {
+      Request &R = *mem[i];
+      int rc = hip_check(hipStreamWaitEvent(s, slots[R.slot].front, 0), "wait for the A-build");
+      if (rc) return rc;
+      run_gram_job(*R.plan, R.ws_run, L.jobs_host[i]);
+      L.jobs_host[i].item0 = total;
+      total += L.jobs_host[i].n_work;
+    }
+    const int prec = mem[0]->plan->cfg.precision;
+    int rc = hip_check(hipMemcpyAsync(L.jobs_dev, L.jobs_host, mem.size() * sizeof(GramJob), hipMemcpyHostToDevice, s),
+                       "job upload");
+    if (rc) return rc;
+    if (launch_gram_batch(prec, L.jobs_dev, (int)mem.size(), total, L.counters, s))
+      return fail(WLC_EINVAL, "no batched Gram for this precision");
+    rc = hip_check(hipGetLastError(), "batched gram launch");
+    if (!rc) rc = hip_check(hipEventRecord(L.done, s), "event record");
+    if (rc) return rc;
+    for (size_t i = 0; i < mem.size(); ++i) err[i] = launch_back(*mem[i], slots[mem[i]->slot], L.done);
+    return WLC_OK;
+  }
+
+  static int lane_of(const Request &R) {
+    GramJob j{};
+    run_gram_job(*R.plan, R.ws_run, j);
+    return (double)j.n_work * (double)j.k_split >= LANE_SPLIT ? 1 : 0;
+  }
+
+  // Finish a request that failed before its done event was recorded.
+  void fail_request(Request &R, int rc) {
+    Slot &S = slots[R.slot];
+    (void)hipStreamSynchronize(S.stream);
+    R.status = rc;
+    R.state = State::Done;
+    R.t_done = now_ms();
+    R.slot = -1;
+    S.busy = false;
+    ++completed;
+    cv_done.notify_all();
+  }
+
+  // Form and launch a batch on every idle lane from the ready requests: all
+  // ready requests of the lane with the precision of the oldest of them.
+  // Called with the lock held; releases it while enqueueing (running
+  // requests cannot be released, and map nodes do not move).
+  void batch(std::unique_lock<std::mutex> &lk) {
+    for (int li = 0; li < 2; ++li) {
+      Lane &L = lanes[li];
+      if (L.busy) continue;
+      std::vector<Request *> mem;
+      int prec = -1;
+      for (auto it = gram_ready.begin(); it != gram_ready.end() && (int)mem.size() < MAX_BATCH;) {
+        Request &R = reqs[*it];
+        if (lane_of(R) == li && (prec < 0 || R.plan->cfg.precision == prec)) {
+          prec = R.plan->cfg.precision;
+          mem.push_back(&R);
+          it = gram_ready.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      if (mem.empty()) continue;
+      std::vector<int> err(mem.size(), WLC_OK);
+      L.busy = true;
+      ++n_batches;
+      n_batched += (int64_t)mem.size();
+      max_batch = std::max<int64_t>(max_batch, (int64_t)mem.size());
+      lk.unlock();
+      const int rc = launch_batch(L, mem, err);
+      lk.lock();
+      if (rc) {
+        (void)hipStreamSynchronize(L.stream);
+        L.busy = false;
+      }
+      for (size_t i = 0; i < mem.size(); ++i) {
+        const int e = rc ? rc : err[i];
+        if (e)
+          fail_request(*mem[i], e);
+        else
+          mem[i]->back_enqueued = true;
+      }
+    }
+  }
 
   void loop() {
     (void)hipSetDevice(device);
@@ -187,9 +335,10 @@ struct wlc_server_s {
       // completions
       for (Slot &S : slots) {
         if (!S.busy) continue;
+        Request &R = reqs[S.ticket];
+        if (!R.back_enqueued) continue;  // waiting for its batch: no done event yet
         const hipError_t q = hipEventQuery(S.done);
         if (q == hipErrorNotReady) continue;
-        Request &R = reqs[S.ticket];
         if (q != hipSuccess) {
           R.status = WLC_EDEVICE;
         } else {
@@ -205,9 +354,12 @@ struct wlc_server_s {
         ++completed;
         cv_done.notify_all();
       }
+      for (Lane &L : lanes)
+        if (L.busy && hipEventQuery(L.done) != hipErrorNotReady) L.busy = false;
       if (stop) {
-        bool any = false;
+        bool any = !gram_ready.empty();
         for (Slot &S : slots) any |= S.busy;
+        for (Lane &L : lanes) any |= L.busy;
         if (!any) break;
       }
       // admission in arrival order
@@ -224,24 +376,23 @@ struct wlc_server_s {
         R.slot = free_slot;
         R.t_admit = now_ms();
         R.state = State::Running;
+        R.batched = run_gram_batchable(*R.plan);
         Slot &S = slots[free_slot];
         S.ticket = R.ticket;
         S.busy = true;
-        // a running request cannot be released, and map nodes do not move:
-        // enqueue its work without holding the lock
         lk.unlock();
-        const int rc = launch(R, S);
+        int rc = launch_front(R, S);
+        if (!rc && !R.batched) rc = launch_back(R, S, nullptr);
         lk.lock();
-        if (rc) {
-          R.status = rc;
-          R.state = State::Done;
-          R.t_done = now_ms();
-          (void)hipStreamSynchronize(S.stream);
-          S.busy = false;
-          ++completed;
-          cv_done.notify_all();
-        }
+        if (rc)
+          fail_request(R, rc);
+        else if (R.batched)
+          gram_ready.push_back(R.ticket);
+        else
+          R.back_enqueued = true;
       }
+      // batches (also while stopping: admitted requests must finish)
+      if (!gram_ready.empty()) batch(lk);
       cv_work.wait_for(lk, std::chrono::microseconds(100));
     }
   }
@@ -265,7 +416,7 @@ extern "C" {
 
 int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t hbm_budget, int32_t max_inflight,
                       wlc_server *out) {
-  if (!base || !fiducial || !out || max_inflight < 1 || max_inflight > 64 || hbm_budget < (1u << 20))
+  if (!base || !fiducial || !out || max_inflight < 1 || max_inflight > MAX_BATCH || hbm_budget < (1u << 20))
     return fail(WLC_EINVAL, "bad server arguments");
   *out = nullptr;
   if (!fiducial->chi || !fiducial->w_chi || !fiducial->k || !fiducial->m || !fiducial->w_m || !fiducial->P ||
@@ -298,9 +449,23 @@ int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t
   for (Slot &S : h->slots) {
     rc = hip_check(hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking), "stream create");
     if (!rc) rc = hip_check(hipEventCreateWithFlags(&S.done, hipEventDisableTiming), "event create");
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&S.front, hipEventDisableTiming), "event create");
     if (!rc) rc = hip_check(hipHostMalloc((void **)&S.pinned_W, h->w_stage_doubles * 8, hipHostMallocDefault),
                             "pinned allocation");
     if (!rc) rc = hip_check(hipHostMalloc((void **)&S.pinned_out, 16, hipHostMallocDefault), "pinned allocation");
+    if (rc) {
+      wlc_server_destroy(h);
+      return rc;
+    }
+  }
+  for (Lane &L : h->lanes) {
+    rc = hip_check(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking), "stream create");
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&L.done, hipEventDisableTiming), "event create");
+    if (!rc) rc = hip_check(hipMalloc((void **)&L.jobs_dev, MAX_BATCH * sizeof(GramJob)), "job list allocation");
+    if (!rc) rc = hip_check(hipMalloc((void **)&L.counters, GRAM_BATCH_COUNTERS * sizeof(uint32_t)),
+                            "queue counter allocation");
+    if (!rc) rc = hip_check(hipHostMalloc((void **)&L.jobs_host, MAX_BATCH * sizeof(GramJob), hipHostMallocDefault),
+                            "pinned allocation");
     if (rc) {
       wlc_server_destroy(h);
       return rc;
@@ -425,6 +590,9 @@ int wlc_server_get_stats(wlc_server srv, wlc_server_stats *out) {
   out->arena_used = srv->arena->used();
   out->arena_peak = srv->arena->peak();
   out->completed_total = srv->completed;
+  out->batches = srv->n_batches;
+  out->batched_requests = srv->n_batched;
+  out->max_batch = srv->max_batch;
   return WLC_OK;
 }
 
@@ -443,8 +611,19 @@ int wlc_server_destroy(wlc_server srv) {
       (void)hipStreamDestroy(S.stream);
     }
     if (S.done) (void)hipEventDestroy(S.done);
+    if (S.front) (void)hipEventDestroy(S.front);
     if (S.pinned_W) (void)hipHostFree(S.pinned_W);
     if (S.pinned_out) (void)hipHostFree(S.pinned_out);
+  }
+  for (Lane &L : srv->lanes) {
+    if (L.stream) {
+      (void)hipStreamSynchronize(L.stream);
+      (void)hipStreamDestroy(L.stream);
+    }
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.jobs_dev) (void)hipFree(L.jobs_dev);
+    if (L.counters) (void)hipFree(L.counters);
+    if (L.jobs_host) (void)hipHostFree(L.jobs_host);
   }
   if (srv->arena_base) (void)hipFree(srv->arena_base);
   delete srv;

@@ -26,7 +26,8 @@ class wlc_result(ct.Structure):
 class wlc_server_stats(ct.Structure):
     _fields_ = [("queued", ct.c_int64), ("running", ct.c_int64), ("done", ct.c_int64),
                 ("arena_bytes", ct.c_size_t), ("arena_used", ct.c_size_t), ("arena_peak", ct.c_size_t),
-                ("completed_total", ct.c_int64)]
+                ("completed_total", ct.c_int64), ("batches", ct.c_int64), ("batched_requests", ct.c_int64),
+                ("max_batch", ct.c_int64)]
 
 
 vp = ct.c_void_p

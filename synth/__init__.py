@@ -116,16 +116,30 @@ def nz_shape(z, z0=0.64):
     return (z / z0) ** 2 * np.exp(-((z / z0) ** 1.5))
 
 
+_EDGES = {}
+
+
 def equipopulated_edges(n_bins, z0=0.64, z_min=0.001, z_max=2.5, n=200001):
-    z = np.linspace(z_min, z_max, n)
-    cdf = _cumtrapz(nz_shape(z, z0), z)
-    cdf /= cdf[-1]
-    edges = np.interp(np.arange(1, n_bins) / n_bins, cdf, z)
-    return np.concatenate([[z_min], edges, [z_max]])
+    key = (int(n_bins), z0, z_min, z_max, n)
+    if key not in _EDGES:
+        z = np.linspace(z_min, z_max, n)
+        cdf = _cumtrapz(nz_shape(z, z0), z)
+        cdf /= cdf[-1]
+        edges = np.interp(np.arange(1, n_bins) / n_bins, cdf, z)
+        _EDGES[key] = np.concatenate([[z_min], edges, [z_max]])
+    return _EDGES[key].copy()
 
 
 def lensing_kernels(chi_nodes, om, z_edges, z0=0.64, nzs=6001):
-    """W_i(chi) on the given chi nodes; each n_i has unit integral in its bin."""
+    """W_i(chi) on the given chi nodes; each n_i has unit integral in its bin.
+
+    The source integral int dz_s n_i(z_s) (chi_s - chi)/chi_s over chi_s > chi
+    is the trapezoid rule on nzs nodes per bin, with the integrand set to 0
+    at nodes where chi_s <= chi.  On a node grid sorted by chi_s it is the
+    suffix sum over the segments above the crossing of
+    0.5 dz (y_l + y_l+1), y = n_i - chi n_i/chi_s, plus the one segment
+    through the crossing, whose lower node contributes 0."""
+    chi_nodes = np.asarray(chi_nodes, np.float64)
     zt, chit = comoving_distance_table(om, z_max=max(2.5, z_edges[-1]), n=40001)
     z_of_chi = np.interp(chi_nodes, chit, zt)
     n_z = len(z_edges) - 1
@@ -135,9 +149,25 @@ def lensing_kernels(chi_nodes, om, z_edges, z0=0.64, nzs=6001):
         ni = nz_shape(zs, z0)
         ni /= _cumtrapz(ni, zs)[-1]
         chis = np.interp(zs, zt, chit)
-        for n, (chi, z) in enumerate(zip(chi_nodes, z_of_chi)):
-            eff = np.where(chis > chi, (chis - chi) / np.where(chis > 0, chis, 1.0), 0.0)
-            W[i, n] = 1.5 * om * H0 ** 2 * (1.0 + z) * chi * _cumtrapz(ni * eff, zs)[-1]
+        dz = np.diff(zs)
+        a = ni
+        b = ni / np.where(chis > 0, chis, 1.0)
+        # suffix sums of whole segments l .. nzs-2: S[l] = sum_{m >= l} 0.5 dz_m (f_m + f_m+1)
+        seg_a = 0.5 * dz * (a[1:] + a[:-1])
+        seg_b = 0.5 * dz * (b[1:] + b[:-1])
+        Sa = np.concatenate([np.cumsum(seg_a[::-1])[::-1], [0.0]])
+        Sb = np.concatenate([np.cumsum(seg_b[::-1])[::-1], [0.0]])
+        # first node with chi_s > chi (chis increases with z_s)
+        j = np.searchsorted(chis, chi_nodes, side="right")
+        inside = j < nzs
+        jj = np.minimum(j, nzs - 1)
+        whole = Sa[jj] - chi_nodes * Sb[jj]            # segments entirely above the crossing
+        part = np.where(j > 0, 0.5 * dz[np.maximum(jj - 1, 0)] * (a[jj] - chi_nodes * b[jj]), 0.0)
+        # no node above the crossing: the bin lies entirely in front of chi
+        integral = np.where(inside, whole + part, 0.0)
+        # the chi node in front of the whole bin: every segment counts
+        integral = np.where(j == 0, Sa[0] - chi_nodes * Sb[0], integral)
+        W[i] = 1.5 * om * H0 ** 2 * (1.0 + z_of_chi) * chi_nodes * integral
     return W
 
 

@@ -31,40 +31,62 @@ def env():
     return serve, wlcov, fid, small
 
 
-def _run_alone(srv, reqs):
-    out = []
-    for q in reqs:
-        t = srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
-        res, d, r, C, tt = srv.fetch(t)
-        assert res.status == 0
-        out.append((res.snr2, d.cpu(), C.cpu(), tt.cpu()))
-        srv.release(t)
-    return out
+def _submit(srv, q):
+    return srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"],
+                      precision=q.get("precision"))
+
+
+def _mix(fid, reqs):
+    """Requests of every size class in one mix: the small ones of the fixture,
+    an n_z = 7 request in plain bf16 (a batch of another precision), an
+    n_z = 10, l_max = 5000 request (N = 82575, the wide batch lane) and a
+    small FP64 request (its own Gram launch)."""
+    base = reqs[0]
+    def req(n_z, ell_max, **kw):
+        return dict(base, n_z=n_z, ell_max=ell_max, W=synth.lensing_kernels(
+            fid.chi, base["omega_m"], synth.equipopulated_edges(n_z)), **kw)
+    return list(reqs) + [req(7, 3000.0, precision="bf16"), req(10, 5000.0), req(3, 1000.0, precision="fp64")]
 
 
 def test_alone_equals_mix(env):
+    """Each request alone, then all of them submitted together: the results
+    are bitwise the same, requests really ran side by side, and the Gram
+    products of several requests shared persistent launches."""
     serve, wl, fid, reqs = env
-    _say("case serve alone vs mix (%d requests)" % len(reqs))
-    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=24 << 30, max_inflight=4, precision="bf16x3")
-    alone = _run_alone(srv, reqs)
-    tickets = [srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
-               for q in reqs]
+    mix = _mix(fid, reqs)
+    _say("case serve alone vs mix (%d requests, n_z %s)" % (len(mix), [q["n_z"] for q in mix]))
+    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=150 << 30, max_inflight=8, precision="bf16x3")
+    alone = []
+    for q in mix:
+        t = _submit(srv, q)
+        res, d, r, C, tt = srv.fetch(t)
+        assert res.status == 0
+        alone.append((res.snr2, d, C, tt))
+        srv.release(t)
+    st0 = srv.stats()
+    _say("  alone done; batches %d" % st0.batches)
+    tickets = [_submit(srv, q) for q in mix]
     spans = []
-    for q, t, (s_a, d_a, C_a, t_a) in zip(reqs, tickets, alone):
+    for q, t, (s_a, d_a, C_a, t_a) in zip(mix, tickets, alone):
         res, d, r, C, tt = srv.fetch(t)
         assert res.status == 0
         assert res.snr2 == s_a
-        assert torch.equal(d.cpu(), d_a) and torch.equal(C.cpu(), C_a) and torch.equal(tt.cpu(), t_a)
+        assert torch.equal(d, d_a) and torch.equal(C, C_a) and torch.equal(tt, t_a)
         spans.append((res.t_admit_ms, res.t_done_ms))
         srv.release(t)
+        del C, C_a
     # the mix really ran requests side by side: some request was admitted
     # before another one had finished
     overlapped = sum(1 for i, (a0, d0) in enumerate(spans) for j, (a1, d1) in enumerate(spans)
                      if i < j and a1 < d0 and a0 < d1)
-    _say("  overlapping request pairs: %d" % overlapped)
-    assert overlapped >= 1
     st = srv.stats()
-    assert st.completed_total == 2 * len(reqs)
+    n_batchable = sum(1 for q in mix if q.get("precision", "bf16x3") in ("bf16", "bf16x3"))
+    _say("  overlapping request pairs: %d; batches %d, batched requests %d, largest batch %d" % (
+        overlapped, st.batches - st0.batches, st.batched_requests - st0.batched_requests, st.max_batch))
+    assert overlapped >= 1
+    assert st.batched_requests - st0.batched_requests == n_batchable
+    assert st.max_batch >= 2
+    assert st.completed_total == 2 * len(mix)
     srv.close()
 
 
