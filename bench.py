@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=180.0)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-snr", default="direct,structured",
+                    help="S/N methods of the serving legs: direct (Cholesky of the whole covariance) and/or "
+                         "structured (through the distinct rows)")
     ap.add_argument("--no-serve-fp64", action="store_true",
                     help="serve the stream in the headline precision only (default: also the plain FP64 path)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -356,7 +359,7 @@ def serve_precisions(args):
     return [args.precision] + ([] if args.no_serve_fp64 or args.precision == "fp64" else ["fp64"])
 
 
-def serving(n_req, budget_gb, slots, precisions, torch, fractions=(0.5, 0.8)):
+def serving(n_req, budget_gb, slots, precisions, torch, fractions=(0.5, 0.8), snr="direct"):
     """The request server on a seeded stream of requests (Omega_m, sigma_8,
     n_z, l_max drawn per request).  Closed loop first (every request
     submitted at once) for the capacity, then open loops with Poisson
@@ -370,7 +373,7 @@ def serving(n_req, budget_gb, slots, precisions, torch, fractions=(0.5, 0.8)):
     from paper_1812_07437_amd import serve
     fid = synth.serving_fiducial()
     reqs = synth.serving_requests(n_req, seed=1234, qps=1.0, fid=fid)
-    out = {"requests": n_req, "slots": slots, "arena_gb": budget_gb,
+    out = {"requests": n_req, "slots": slots, "arena_gb": budget_gb, "snr_method": snr,
            "mix": {"n_z": [int(q["n_z"]) for q in reqs], "ell_max": [q["ell_max"] for q in reqs]}}
 
     def build_w(q):
@@ -409,7 +412,7 @@ def serving(n_req, budget_gb, slots, precisions, torch, fractions=(0.5, 0.8)):
                 reap(False)
                 time.sleep(0.0002)
             W = build_w(q)
-            t = srv.submit(W, q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+            t = srv.submit(W, q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"], snr=snr)
             live[t] = (i, time.perf_counter() - t0 - ta)
         while live:
             reap(True)
@@ -460,7 +463,8 @@ def main():
         return
 
     if args.serve_only:
-        srv = serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, serve_precisions(args), torch)
+        srv = {m: serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, serve_precisions(args), torch,
+                          snr=m) for m in args.serve_snr.split(",") if m}
         print(json.dumps({"metric": "serving p50/p99 latency (ms) and requests/s", "data": "synthetic",
                           "serving": srv}), flush=True)
         return
@@ -643,7 +647,8 @@ def main():
     srv = None
     if args.serve_requests > 0:
         log("serving stream (%d requests)" % args.serve_requests)
-        srv = serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, serve_precisions(args), torch)
+        srv = {m: serving(args.serve_requests, args.serve_budget_gb, args.serve_slots, serve_precisions(args), torch,
+                          snr=m) for m in args.serve_snr.split(",") if m}
 
     cpu = None
     if not args.no_cpu:

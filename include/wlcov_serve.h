@@ -42,9 +42,17 @@ typedef struct wlc_server_s *wlc_server;
  * kernels W.  (A change of sigma_8 rescales P by (sigma_8/sigma_8,fid)^2; a
  * change of Omega_m rescales rho and n(M) together, keeping the mass
  * normalisation of eq. BoundinMass.) */
+/* How a request's (S/N)^2 is computed (both FP64, both exact):
+ * DIRECT     : bordered Cholesky of the whole covariance, as wlc_snr2;
+ * STRUCTURED : through the distinct rows, as wlc_snr2_structured (PAPER
+ *              tomography, n_z <= 32; one Cholesky on n_distinct rows). */
+enum { WLC_SNR_DIRECT = 0, WLC_SNR_STRUCTURED = 1 };
+
 typedef struct {
   int32_t n_z;        /* redshift bins of this request (1..64)                 */
   int32_t precision;  /* WLC_FP64 / WLC_BF16 / WLC_BF16X3 / WLC_FP32           */
+  int32_t snr_method; /* WLC_SNR_DIRECT / WLC_SNR_STRUCTURED                    */
+  int32_t pad;
   double ell_max;     /* keep ell-bins with centre below (<= 0: all), eq. eq:SN */
   double p_scale;     /* multiplies the fiducial P table                       */
   double n_scale;     /* multiplies the fiducial n(M) table                    */
@@ -86,7 +94,8 @@ int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t
                       wlc_server *out);
 
 /* Enqueue a request (non-blocking); *ticket identifies it.  WLC_EINVAL for a
- * bad request, WLC_EBUSY if its footprint alone exceeds the arena. */
+ * bad request (including WLC_SNR_STRUCTURED where wlc_snr2_structured is not
+ * available), WLC_EBUSY if its footprint alone exceeds the arena. */
 int wlc_server_submit(wlc_server srv, const wlc_request *req, uint64_t *ticket);
 
 /* Non-blocking status: *done = 1 when finished (res filled), 0 otherwise. */

@@ -20,8 +20,10 @@
 // Gram of a large one: products of less than LANE_SPLIT work units go to the
 // narrow lane, the others to the wide lane, and the two lanes' launches run
 // side by side.  After its batch, each request's split-K reduction, assembly
-// and FP64 Cholesky run on its own stream again, overlapping with other
-// requests' work.  FP64 and FP32 requests run their own Gram on their stream.
+// and FP64 S/N (the Cholesky of the whole covariance, or of the distinct-row
+// system when the request asks for the structured method) run on its own
+// stream again, overlapping with other requests' work.  FP64 and FP32
+// requests run their own Gram on their stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -141,6 +143,11 @@ struct Lane {
 
 static inline size_t a256(size_t x) { return (x + 255) / 256 * 256; }
 
+// S/N workspace of a request (0: the method is not available for the plan).
+static size_t snr_bytes(const Plan &p, int method) {
+  return method == WLC_SNR_STRUCTURED ? snr_structured_ws_bytes(p) : p.ws_snr;
+}
+
 }  // namespace wlc
 
 using namespace wlc;
@@ -190,7 +197,7 @@ struct wlc_server_s {
       return ptr;
     };
     R.ws_run = take(p.ws_run);
-    R.ws_snr = take(p.ws_snr);
+    R.ws_snr = take(snr_bytes(p, R.q.snr_method));
     R.d = (double *)take(n * 8);
     R.r = (double *)take(n * 8);
     R.t = (int32_t *)take(n * 4);
@@ -230,7 +237,10 @@ struct wlc_server_s {
     if (rc) return rc;
     int32_t *flag = nullptr;
     double *out = nullptr;
-    rc = snr_enqueue(p, R.C, R.t, R.d, R.ws_snr, s, nullptr, nullptr, &flag, &out);
+    if (R.q.snr_method == WLC_SNR_STRUCTURED)
+      rc = snr_structured_enqueue(p, R.ws_run, R.ws_snr, s, nullptr, nullptr, &flag, &out);
+    else
+      rc = snr_enqueue(p, R.C, R.t, R.d, R.ws_snr, s, nullptr, nullptr, &flag, &out);
     if (rc) return rc;
     rc = hip_check(hipMemcpyAsync(S.pinned_out, flag, 4, hipMemcpyDeviceToHost, s), "result copy");
     if (!rc) rc = hip_check(hipMemcpyAsync(S.pinned_out + 1, out, 8, hipMemcpyDeviceToHost, s), "result copy");
@@ -479,7 +489,7 @@ int wlc_server_create(const wlc_config *base, const wlc_tables *fiducial, size_t
 int wlc_server_submit(wlc_server srv, const wlc_request *q, uint64_t *ticket) {
   if (!srv || !q || !ticket || !q->W) return fail(WLC_EINVAL, "null argument");
   if (q->n_z < 1 || q->n_z > 64 || !(q->p_scale > 0.0) || !(q->n_scale > 0.0) || !(q->rho_mean > 0.0) ||
-      !prec_valid(q->precision))
+      !prec_valid(q->precision) || (q->snr_method != WLC_SNR_DIRECT && q->snr_method != WLC_SNR_STRUCTURED))
     return fail(WLC_EINVAL, "bad request");
   wlc_config cfg = srv->base;
   cfg.n_z = q->n_z;
@@ -501,8 +511,10 @@ int wlc_server_submit(wlc_server srv, const wlc_request *q, uint64_t *ticket) {
   }
   if (srv->fid.n_tri && plan->n_tri > srv->base_n_tri)
     return fail(WLC_EINVAL, "the request has more triangles than the fiducial triangle counts cover");
+  const size_t ws_snr = snr_bytes(*plan, q->snr_method);
+  if (!ws_snr) return fail(WLC_EINVAL, "the structured S/N is not available for this request");
   const int64_t n = plan->n_out;
-  const size_t foot = a256(plan->ws_run) + a256(plan->ws_snr) + 2 * a256(n * 8) + a256(n * 4) +
+  const size_t foot = a256(plan->ws_run) + a256(ws_snr) + 2 * a256(n * 8) + a256(n * 4) +
                       a256((size_t)n * n * (prec_f64(q->precision) ? 8 : 4)) +
                       a256((size_t)cfg.n_chi * cfg.n_k * 8) + a256((size_t)cfg.n_m * 8) +
                       a256((size_t)q->n_z * cfg.n_chi * 8);

@@ -11,7 +11,8 @@ from .wlcov import PRECISIONS, WlcError, _check, _ptr, _stream_handle, lib, make
 
 
 class wlc_request(ct.Structure):
-    _fields_ = [("n_z", ct.c_int32), ("precision", ct.c_int32), ("ell_max", ct.c_double),
+    _fields_ = [("n_z", ct.c_int32), ("precision", ct.c_int32), ("snr_method", ct.c_int32), ("pad", ct.c_int32),
+                ("ell_max", ct.c_double),
                 ("p_scale", ct.c_double), ("n_scale", ct.c_double), ("rho_mean", ct.c_double),
                 ("W", ct.c_void_p)]
 
@@ -29,6 +30,8 @@ class wlc_server_stats(ct.Structure):
                 ("completed_total", ct.c_int64), ("batches", ct.c_int64), ("batched_requests", ct.c_int64),
                 ("max_batch", ct.c_int64)]
 
+
+SNR_METHODS = {"direct": 0, "structured": 1}
 
 vp = ct.c_void_p
 lib.wlc_server_create.argtypes = [vp, vp, ct.c_size_t, ct.c_int32, ct.POINTER(vp)]
@@ -109,12 +112,15 @@ class Server:
         self.tables = wlc_tables(**ptrs)
         self.handle = wlc_server_create(base, self.tables, hbm_budget, max_inflight)
 
-    def submit(self, W, n_z, ell_max, p_scale=1.0, n_scale=1.0, rho_mean=None, precision=None):
+    def submit(self, W, n_z, ell_max, p_scale=1.0, n_scale=1.0, rho_mean=None, precision=None, snr="direct"):
+        """snr: "direct" (Cholesky of the whole covariance) or "structured"
+        (through the distinct rows)."""
         import numpy as np
         W = np.ascontiguousarray(W, dtype=np.float64)
         assert W.shape == (n_z, self.n_chi)
         req = wlc_request(n_z=int(n_z), precision=self.precision if precision is None else
                           (PRECISIONS[precision] if isinstance(precision, str) else int(precision)),
+                          snr_method=SNR_METHODS[snr] if isinstance(snr, str) else int(snr),
                           ell_max=float(ell_max), p_scale=float(p_scale), n_scale=float(n_scale),
                           rho_mean=float(rho_mean if rho_mean is not None else self.cfg["rho_mean"]),
                           W=W.ctypes.data_as(ct.c_void_p))

@@ -112,6 +112,32 @@ def test_server_matches_direct_path_and_oracle(env):
     srv.close()
 
 
+def test_server_structured_snr(env):
+    """A request with the structured S/N: bitwise the direct path's
+    wlc_snr2_structured on the same run, and within 1e-6 of the server's own
+    direct S/N (both FP64 S/N of the same split-bf16 covariance)."""
+    serve, wl, fid, reqs = env
+    q = reqs[0]
+    _say("case serve structured snr n_z=%d l_max=%g" % (q["n_z"], q["ell_max"]))
+    srv = serve.Server(fid.cfg, fid.arrays(), hbm_budget=16 << 30, max_inflight=4, precision="bf16x3")
+    t1 = srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"], snr="structured")
+    t2 = srv.submit(q["W"], q["n_z"], q["ell_max"], q["p_scale"], q["n_scale"], q["rho_mean"])
+    r1 = srv.wait(t1)
+    r2 = srv.wait(t2)
+    assert r1.status == 0 and r2.status == 0
+    tab = synth.request_tables(fid, q)
+    prob = wl.Problem(tab.cfg, tab.arrays(), precision="bf16x3")
+    prob.run()
+    s_struct = prob.snr2_structured()
+    torch.cuda.synchronize()
+    assert r1.snr2 == s_struct
+    assert abs(r1.snr2 - r2.snr2) / r2.snr2 < 1e-6
+    srv.release(t1)
+    srv.release(t2)
+    srv.close()
+    prob.close()
+
+
 def test_memory_admission(env):
     serve, wl, fid, reqs = env
     _say("case serve admission")

@@ -114,3 +114,65 @@ def test_inverse_sky_fraction():
     nz = v1 != 0
     assert np.count_nonzero(nz) > 20
     assert np.allclose(v2[nz] / v1[nz], t1.cfg["f_sky"] / t2.cfg["f_sky"], rtol=1e-13, atol=0)
+
+
+def _bb_pb(o):
+    """The B.B and P.B parts of the in-survey terms on all rows, from the
+    projected bispectra, P^s and the mode counts (the remainder of the
+    oracle's total is the P.T part)."""
+    rows = o.rows
+    kind, lb, zb, tri = rows["kind"], rows["lbin"], rows["zbin"], rows["tri"]
+    Ps, nm, BF = o.ps_table(), o.nmodes(), o.bfull()
+    N = o.N
+    BB = np.zeros((N, N))
+    PB = np.zeros((N, N))
+    Bi = np.where(kind == 3)[0]
+    Pi = np.where(kind == 2)[0]
+    for a in Bi:
+        for b in Bi:
+            for x in range(3):
+                for y in range(3):
+                    if lb[a][x] != lb[b][y]:
+                        continue
+                    z1 = list(zb[a]); z2 = list(zb[b])
+                    z1[x], z2[y] = zb[b][y], zb[a][x]
+                    BB[a, b] += BF[tri[a], z1[0], z1[1], z1[2]] * BF[tri[b], z2[0], z2[1], z2[2]] / nm[lb[a][x]]
+    for p in Pi:
+        l, i, j = lb[p][0], zb[p][0], zb[p][1]
+        for t in Bi:
+            for y in range(3):
+                if lb[t][y] != l:
+                    continue
+                zi = list(zb[t]); zj = list(zb[t])
+                zi[y], zj[y] = i, j
+                v = (Ps[l, zb[t][y], j] * BF[tri[t], zi[0], zi[1], zi[2]] +
+                     Ps[l, i, zb[t][y]] * BF[tri[t], zj[0], zj[1], zj[2]]) / nm[l]
+                PB[p, t] += v
+                PB[t, p] += v
+    return BB, PB
+
+
+@pytest.mark.parametrize("n_z", [1, 2])
+def test_term_structure(n_z):
+    """P.T = P^s (x) T summed over shared modes is a Schur product of two
+    positive semidefinite forms (P^s over the bins, the one-halo T a Gram
+    over haloes), so it is positive semidefinite; B.B is a sum of
+    u u^T / N(l) for one redshift bin and indefinite once it exchanges bins
+    between the two rows; P.B only couples P and B rows."""
+    o = oracle.Oracle(synth.make_tables("tiny", n_z=n_z))
+    Cb = o.covariance()
+    NG = o.covariance(ngins=True) - Cb
+    BB, PB = _bb_pb(o)
+    PT = NG - BB - PB
+    s = 1.0 / np.sqrt(np.diag(Cb))
+    scaled = lambda X: s[:, None] * X * s[None, :]
+    assert np.linalg.eigvalsh(scaled(PT)).min() > -1e-12
+    e_bb = np.linalg.eigvalsh(scaled(BB))
+    if n_z == 1:
+        assert e_bb.min() > -1e-12
+    else:
+        assert e_bb.min() < -1e-3 * e_bb.max()
+    P = o.rows["kind"] == 2
+    assert np.all(PB[np.ix_(P, P)] == 0.0) and np.all(PB[np.ix_(~P, ~P)] == 0.0)
+    # the oracle's P-B block is exactly the P.B part (up to the rounding of the subtraction)
+    assert np.max(np.abs(PT[np.ix_(P, ~P)])) <= 1e-12 * np.max(np.abs(PB))
