@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+PEAK_TFLOPS = {"bf16": 2500.0, "bf16x3": 2500.0, "bf16_auto": 2500.0, "fp32": 157.3, "fp64": 78.6}
 
 
 def log(msg):
@@ -52,7 +52,7 @@ def parse():
                     help="workload of the timed lattice counts (empty: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-requests", type=int, default=12,
+    ap.add_argument("--serve-requests", type=int, default=8,
                     help="requests of the serving stream (0: skip serving)")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=180.0)
@@ -108,14 +108,21 @@ def gram_mfma_work(n_r, k_len, precision):
     return gram_flops(n_r, k_len) * (3 if precision == "bf16x3" else 1)
 
 
-def gram_figures(ms, n_r, k_len, precision):
+def gram_figures(ms, n_r, k_len, precision, split=None):
     """Gram rate on useful flops and, separately, on issued MFMA work, each
-    against the peak of the precision's matrix-core type."""
+    against the peak of the precision's matrix-core type.  split = (tiles
+    with the split product, tiles) for the per-tile precision."""
     useful = gram_flops(n_r, k_len) / (ms * 1e-3) / 1e12
-    work = gram_mfma_work(n_r, k_len, precision) / (ms * 1e-3) / 1e12
+    if precision == "bf16_auto" and split:
+        work = useful * (1.0 + 2.0 * split[0] / max(split[1], 1))
+    else:
+        work = gram_mfma_work(n_r, k_len, precision) / (ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[precision]
-    return dict(ms=ms, useful_tflops=useful, frac_peak_useful=useful / peak, mfma_work_tflops=work,
-                frac_peak_mfma_work=work / peak, peak_tflops=peak)
+    out = dict(ms=ms, useful_tflops=useful, frac_peak_useful=useful / peak, mfma_work_tflops=work,
+               frac_peak_mfma_work=work / peak, peak_tflops=peak)
+    if split:
+        out["split_tiles"], out["tiles"] = split
+    return out
 
 
 def timed_runs(prob, runs, warmup, torch, wl):
@@ -160,16 +167,17 @@ def precision_report(workload, torch, wl):
     out["fp64"] = dict(gram=gram_figures(ph["gram"], NR, K, "fp64"), snr2=snr64)
     del p64
     scale = torch.sqrt(torch.outer(d64, d64))
-    for prec in ("bf16", "bf16x3", "fp32"):
+    for prec in ("bf16", "bf16x3", "bf16_auto", "fp32"):
         pm = wl.Problem(t.cfg, t.arrays(), precision=prec, device="cuda:0")
         ph = timed_runs(pm, 2, 1, torch, wl)
+        split = pm.split_tiles() if prec == "bf16_auto" else None
         snr = pm.snr2()
         Cm = true_cov(pm, torch)
         dm = torch.diagonal(Cm)
         ed = torch.abs(dm - d64) / d64
         off = torch.abs(Cm - C64) / scale
         off.fill_diagonal_(0.0)
-        out[prec] = dict(gram=gram_figures(ph["gram"], NR, K, prec), diag_max_rel=float(ed.max()),
+        out[prec] = dict(gram=gram_figures(ph["gram"], NR, K, prec, split), diag_max_rel=float(ed.max()),
                          diag_median_rel=float(ed.median()), offdiag_max_rel_sqrt_caa_cbb=float(off.max()),
                          snr2_rel=abs(snr - snr64) / snr64)
         log("precision %s %s: gram %.3f ms (useful %.1f %% of peak), diag max %.2e median %.2e, off %.2e, "
@@ -183,7 +191,7 @@ def precision_report(workload, torch, wl):
     return out
 
 
-def gram_variants(cfg, arrays, torch, wl, precisions=("bf16", "fp32")):
+def gram_variants(cfg, arrays, torch, wl, precisions):
     """Gram time of the other precisions on the bench workload (wlc_run
     only, one warm-up and one timed run each)."""
     out = {}
@@ -191,7 +199,8 @@ def gram_variants(cfg, arrays, torch, wl, precisions=("bf16", "fp32")):
         p = wl.Problem(cfg, arrays, precision=prec, device="cuda:0")
         s = p.sizes
         ph = timed_runs(p, 1, 1, torch, wl)
-        out[prec] = gram_figures(ph["gram"], s.n_distinct, s.k_len, prec)
+        out[prec] = gram_figures(ph["gram"], s.n_distinct, s.k_len, prec,
+                                 p.split_tiles() if prec == "bf16_auto" else None)
         out[prec]["run_ms"] = sum(ph[k] for k in ("tables", "abuild", "gram", "assemble"))
         log("gram %s: %.1f ms, useful %.1f TFLOP/s (%.1f %% of its peak)" % (
             prec, ph["gram"], out[prec]["useful_tflops"], 100 * out[prec]["frac_peak_useful"]))
@@ -490,6 +499,7 @@ def main():
     value = entries / (dt / args.steps)
     log("mixed: %.1f ms/step  phases %s  snr2 %.6e" % (ms_step, {k: round(v, 2) for k, v in ph.items()}, snrs[-1]))
 
+    split_main = prob.split_tiles() if args.precision == "bf16_auto" else None
     d_mixed = prob.C.diagonal().double().cpu().numpy()
     t_mixed = prob.row_exp2.cpu().numpy().astype(np.int64)
     diag_mixed = np.ldexp(d_mixed, -2 * t_mixed)
@@ -519,7 +529,8 @@ def main():
         del p64
         torch.cuda.empty_cache()
 
-    variants = gram_variants(cfg, t.arrays(), torch, wl) if args.gram_variants else None
+    others = [q for q in ("bf16", "bf16x3", "bf16_auto", "fp32") if q != args.precision]
+    variants = gram_variants(cfg, t.arrays(), torch, wl, others) if args.gram_variants else None
     prec_rep = precision_report(args.precision_workload, torch, wl) if args.precision_workload else None
     lattice = lattice_leg(args.lattice_workload, torch, wl) if args.lattice_workload else None
 
@@ -609,7 +620,7 @@ def main():
     # roofline of the dominant kernel of the step: the one-halo Gram (one
     # launch per step) or the Cholesky block update (many launches per step,
     # timed one by one with HIP events on the run's stream)
-    gram_fig = gram_figures(ph["gram"], NR, K, args.precision)
+    gram_fig = gram_figures(ph["gram"], NR, K, args.precision, split_main)
     chol_flops = N ** 3 / 3.0
     chol_tf = chol_flops / (ph["chol"] * 1e-3) / 1e12
     upd_frac_timed = upd["timed"] / max(upd["launches"], 1)

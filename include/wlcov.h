@@ -55,8 +55,17 @@ enum { WLC_TOMO_PAPER = 0, WLC_TOMO_SORTED = 1 };
  * FP64_CHI : FP64, the same sum taken over M first and then over chi (the
  *            factorisation of eq. General1h along the line of sight),
  *            N_M times fewer operations; FP64 covariance output.
- * BF16X3 and FP32 also return an FP32 covariance. */
-enum { WLC_FP64 = 0, WLC_BF16 = 1, WLC_BF16X3 = 2, WLC_FP32 = 3, WLC_FP64_CHI = 4 };
+ * BF16_AUTO: per 256 x 256 tile of the product, the split product where an
+ *            a-priori bound needs it and one bf16 product elsewhere.  With
+ *            f_a the one-halo share of the diagonal entry C_aa (in FP64, before
+ *            the product) and F_I the largest f_a of the rows of panel I, a
+ *            single bf16 product changes an entry of tile (I, J) by at most
+ *            (2u + u^2 + K 2^-24) sqrt(F_I F_J) sqrt(C_aa C_bb) (u = 2^-8
+ *            for bf16 operands, K 2^-24 for the FP32 accumulation of K
+ *            terms, Cauchy-Schwarz over the products); tiles where that bound
+ *            exceeds gram_tol take the split product.
+ * BF16X3, FP32 and BF16_AUTO also return an FP32 covariance. */
+enum { WLC_FP64 = 0, WLC_BF16 = 1, WLC_BF16X3 = 2, WLC_FP32 = 3, WLC_FP64_CHI = 4, WLC_BF16_AUTO = 5 };
 
 /* ---- flags */
 enum {
@@ -84,7 +93,7 @@ typedef struct {
   int32_t n_k;        /* k nodes of the P and u tables                         */
   int32_t n_m;        /* mass nodes                                            */
   int32_t tomo_mode;  /* WLC_TOMO_*                                            */
-  int32_t precision;  /* WLC_FP64 / WLC_BF16 / WLC_BF16X3 / WLC_FP32           */
+  int32_t precision;  /* WLC_FP64 / WLC_BF16 / WLC_BF16X3 / WLC_FP32 / ...     */
   int32_t flags;      /* WLC_FLAG_*                                            */
   double ell_min, ell_max;
   double ell_cut;     /* keep only ell-bins whose centre is below this (<= 0: all), eq. eq:SN */
@@ -107,6 +116,10 @@ typedef struct {
                          the one-halo and super-sample terms average; the
                          Gaussian term keeps its form with the averaged power
                          spectra.  Not combinable with WLC_FLAG_NGINS. */
+  double gram_tol;    /* WLC_BF16_AUTO: bound on the one-halo rounding error of
+                         an entry relative to sqrt(C_aa C_bb) above which a tile
+                         takes the split product (<= 0: 2^-17, below the 1e-5
+                         target on the diagonal); ignored otherwise */
 } wlc_config;
 
 /* Input tables, all DEVICE pointers to float64, row-major:
@@ -301,6 +314,13 @@ int wlc_pca(wlc_plan plan, const void *C, const int32_t *row_exp2, const double 
  * WLC_FLAG_NGINS (its terms are not of the form E M E^T);
  * WLC_ENOTPD if a pivot is not positive. */
 int wlc_snr2_structured(wlc_plan plan, const void *ws_run, void *ws, double *snr2_host, void *stream);
+
+/* Tiles of the last run's one-halo product that took the split bf16 product
+ * (WLC_BF16_AUTO: the tiles whose one-product error bound exceeds gram_tol;
+ * all of them for WLC_BF16X3, none otherwise) and the number of tiles, into
+ * HOST scalars.  ws_run: the DEVICE workspace of a completed wlc_run with
+ * this plan; synchronises the device for the copy. */
+int wlc_gram_split_tiles(wlc_plan plan, const void *ws_run, int64_t *split, int64_t *tiles);
 
 /* ---- phase timing (per-plan HIP events; not for plans shared by concurrent runs)
  * With timing enabled, wlc_run and wlc_snr2 record a HIP event pair on their

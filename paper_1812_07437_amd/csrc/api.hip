@@ -53,7 +53,7 @@ constexpr int64_t K_ALIGN = 64;
 enum Buf {
   B_ROWR, B_ROWO, B_CFGT, B_CENT, B_NMODES, B_NTRI, B_THR, B_TRI, B_FLAGS,
   B_U, B_PK, B_NE, B_X, B_R, B_DR, B_RR, B_PS, B_G, B_GMAX, B_TS, B_SEXP,
-  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, B_SW, B_SOFF, B_SLEG, B_SWT, NBUF
+  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, B_SW, B_SOFF, B_SLEG, B_SWT, B_SQ, B_GD, B_FP, NBUF
 };
 
 // Columns per chi node of the configuration factor G: the mass nodes, and
@@ -102,7 +102,12 @@ static Layout run_layout(const Plan &p) {
   const bool chi = c.precision == WLC_FP64_CHI;
   const size_t ael = c.precision == WLC_FP64 ? 8 : (c.precision == WLC_FP32 ? 4 : 2);
   sz[B_A0] = chi ? 0 : (size_t)p.r_pad * p.k_pad * ael;
-  sz[B_A1] = c.precision == WLC_BF16X3 ? sz[B_A0] : 0;
+  sz[B_A1] = c.precision == WLC_BF16X3 || c.precision == WLC_BF16_AUTO ? sz[B_A0] : 0;
+  if (c.precision == WLC_BF16_AUTO) {  // the per-tile precision plan
+    sz[B_SQ] = (size_t)n_cfg * c.n_chi * 8;
+    sz[B_GD] = (size_t)p.n_R * 8;
+    sz[B_FP] = (size_t)(p.r_pad / GRAM_TILE + 1) * 8;  // per panel, then the largest
+  }
   const size_t gel = prec_f64(c.precision) ? 8 : 4;
   sz[B_GM] = (size_t)p.r_pad * p.r_pad * gel;
   GramShape g{p.r_pad, p.k_pad, p.r_pad, p.k_pad};
@@ -333,6 +338,9 @@ int validate_tables(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s
   return WLC_OK;
 }
 
+static AsmArgs asm_args(const Plan &p, void *ws, const Layout &L);
+static double split_lim(const Plan &p);
+
 int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t s, PhaseHooks *hooks, double rho) {
   int rc = check_tables_present(tb);
   if (rc) return rc;
@@ -340,6 +348,11 @@ int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t
   const Layout L = run_layout(p);
   rc = upload_index(p, ws, L, s);
   if (rc) return rc;
+  if (tb.n_tri && p.n_tri > 0) {  // the workspace keeps the counts this run used
+    rc = hip_check(hipMemcpyAsync(at<double>(ws, L, B_NTRI), tb.n_tri, (size_t)p.n_tri * 8, hipMemcpyDeviceToDevice,
+                                  s), "triangle counts");
+    if (rc) return rc;
+  }
   const DevTables T = dev_tables(p, tb, rho);
   const double *cent = at<double>(ws, L, B_CENT);
   const int n_cfg = (int)p.cfgs.size();
@@ -364,6 +377,9 @@ int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t
   if (ssc_chi) launch_sigma_w2(T, theta_sky(p), sw, s);
   launch_gfactor(T, cfgT, n_cfg, sl, U, R, sw, std::sqrt(p.omega), n_mg, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
+  if (c.precision == WLC_BF16_AUTO)
+    launch_split_plan(asm_args(p, ws, L), rowR, Ts, G, p.n_R, n_cfg, c.n_chi, n_mg, at<double>(ws, L, B_SQ),
+                      at<double>(ws, L, B_GD), at<double>(ws, L, B_FP), (int)(p.r_pad / GRAM_TILE), s);
   if (c.flags & WLC_FLAG_NGINS) {
     // the projected one-halo trispectrum of two legs per triangle (the P.T
     // term), in FP64 through the factorisation along chi
@@ -378,15 +394,28 @@ int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t
   // the flattened factor A (none in the chi-factorised form)
   if (hooks) hooks->begin(WLC_PHASE_ABUILD);
   if (c.precision != WLC_FP64_CHI) {
-    const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_BF16X3 ? 2 : 3;
+    const int fmt = c.precision == WLC_FP64 ? 0 : c.precision == WLC_BF16 ? 1 : c.precision == WLC_FP32 ? 3 : 2;
+    const bool auto_split = c.precision == WLC_BF16_AUTO;
     launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, n_mg, p.k_pad, p.k_pad, at<void>(ws, L, B_A0),
-                  at<void>(ws, L, B_A1), s);
+                  at<void>(ws, L, B_A1), s, auto_split ? at<double>(ws, L, B_FP) : nullptr,
+                  auto_split ? split_lim(p) : 0.0);
   }
   if (hooks) hooks->end(WLC_PHASE_ABUILD);
   return hip_check(hipGetLastError(), "run launch");
 }
 
 static GramShape gram_shape(const Plan &p) { return GramShape{p.r_pad, p.k_pad, p.r_pad, p.k_pad}; }
+
+// WLC_BF16_AUTO: tile (I, J) takes the split product iff
+// (2u + u^2 + K 2^-24) sqrt(F_I F_J) > tol, i.e. F_I F_J > lim, with
+// u = 2^-8 (bf16 operands rounded to nearest) and K 2^-24 the FP32
+// accumulation of K products.
+static double split_lim(const Plan &p) {
+  const double tol = p.cfg.gram_tol > 0.0 ? p.cfg.gram_tol : std::ldexp(1.0, -17);
+  const double u = std::ldexp(1.0, -8);
+  const double eps = 2.0 * u + u * u + (double)p.k_pad * std::ldexp(1.0, -24);
+  return (tol / eps) * (tol / eps);
+}
 
 int run_enqueue_gram(const Plan &p, void *ws, hipStream_t s, PhaseHooks *hooks) {
   const wlc_config &c = p.cfg;
@@ -401,7 +430,7 @@ int run_enqueue_gram(const Plan &p, void *ws, hipStream_t s, PhaseHooks *hooks) 
                    (double *)Gm, p.r_pad, s);
   } else {
     launch_gram(c.precision, gram_shape(p), at<void>(ws, L, B_A0), at<void>(ws, L, B_A1), Gm, at<void>(ws, L, B_PART),
-                s);
+                s, at<double>(ws, L, B_FP), split_lim(p));
   }
   if (hooks) hooks->end(WLC_PHASE_GRAM);
   return hip_check(hipGetLastError(), "gram launch");
@@ -412,7 +441,7 @@ bool run_gram_batchable(const Plan &p) { return gram_batchable(p.cfg.precision);
 void run_gram_job(const Plan &p, void *ws, GramJob &job) {
   const Layout L = run_layout(p);
   gram_job(p.cfg.precision, gram_shape(p), at<void>(ws, L, B_A0), at<void>(ws, L, B_A1), at<void>(ws, L, B_GM),
-           at<void>(ws, L, B_PART), job);
+           at<void>(ws, L, B_PART), job, at<double>(ws, L, B_FP), split_lim(p));
 }
 
 int run_enqueue_gram_reduce(const Plan &p, void *ws, hipStream_t s) {
@@ -421,27 +450,18 @@ int run_enqueue_gram_reduce(const Plan &p, void *ws, hipStream_t s) {
   return hip_check(hipGetLastError(), "gram reduce launch");
 }
 
-int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
-                     hipStream_t s, PhaseHooks *hooks) {
+static AsmArgs asm_args(const Plan &p, void *ws, const Layout &L) {
   const wlc_config &c = p.cfg;
-  const Layout L = run_layout(p);
-  int rc = WLC_OK;
-  void *Gm = at<void>(ws, L, B_GM);
   const bool ssc_chi = (c.flags & WLC_FLAG_SSC_CHI) != 0;
   AsmArgs a{};
   a.rowO = at<int32_t>(ws, L, B_ROWO);
   a.cfgT = at<int32_t>(ws, L, B_CFGT);
   a.sexp = at<int32_t>(ws, L, B_SEXP);
-  a.Gm = Gm;
+  a.Gm = at<void>(ws, L, B_GM);
   a.ld_g = p.r_pad;
   a.gm_f32 = !prec_f64(c.precision);
   a.Ps = at<double>(ws, L, B_PS);
   a.nmodes = at<double>(ws, L, B_NMODES);
-  if (tb.n_tri && p.n_tri > 0) {  // the workspace keeps the counts this run used
-    rc = hip_check(hipMemcpyAsync(at<double>(ws, L, B_NTRI), tb.n_tri, (size_t)p.n_tri * 8, hipMemcpyDeviceToDevice,
-                                  s), "triangle counts");
-    if (rc) return rc;
-  }
   a.ntri = at<double>(ws, L, B_NTRI);
   a.rR = at<double>(ws, L, B_RR);
   a.dR = at<double>(ws, L, B_DR);
@@ -454,6 +474,16 @@ int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, d
   a.ngins = (c.flags & WLC_FLAG_NGINS) != 0;
   a.T2 = a.ngins ? at<double>(ws, L, B_T2) : nullptr;
   a.ld_t2 = a.ngins ? twoleg_ld(p) : 0;
+  return a;
+}
+
+int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, double *r, void *C, int32_t *row_exp2,
+                     hipStream_t s, PhaseHooks *hooks) {
+  (void)tb;
+  const wlc_config &c = p.cfg;
+  const Layout L = run_layout(p);
+  void *Gm = at<void>(ws, L, B_GM);
+  const AsmArgs a = asm_args(p, ws, L);
   if (hooks) hooks->begin(WLC_PHASE_ASSEMBLE);
   launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
   launch_rowexp(a, row_exp2, d, r, s);
@@ -781,6 +811,26 @@ int wlc_snr2(wlc_plan plan, const void *C, const int32_t *row_exp2, const double
   if (rc) return rc;
   if (h.flag) return fail(WLC_ENOTPD, "covariance is not positive definite");
   *snr2_host = h.v;
+  return WLC_OK;
+}
+
+int wlc_gram_split_tiles(wlc_plan plan, const void *ws_run, int64_t *split, int64_t *tiles) {
+  if (!plan || !ws_run || !split || !tiles) return fail(WLC_EINVAL, "null argument");
+  const Plan &p = plan->p;
+  const int64_t np = p.r_pad / GRAM_TILE;
+  *tiles = p.cfg.precision == WLC_FP64_CHI ? 0 : np * (np + 1) / 2;
+  *split = p.cfg.precision == WLC_BF16X3 ? *tiles : 0;
+  if (p.cfg.precision != WLC_BF16_AUTO) return WLC_OK;
+  const Layout L = run_layout(p);
+  std::vector<double> F((size_t)np);
+  int rc = hip_check(hipMemcpy(F.data(), static_cast<const char *>(ws_run) + L.off[B_FP], (size_t)np * 8,
+                               hipMemcpyDeviceToHost), "split plan copy");
+  if (rc) return rc;
+  const double lim = split_lim(p);
+  int64_t n = 0;
+  for (int64_t I = 0; I < np; ++I)
+    for (int64_t J = 0; J <= I; ++J) n += F[I] * F[J] > lim;
+  *split = n;
   return WLC_OK;
 }
 

@@ -149,6 +149,69 @@ void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hi
   hipLaunchKernelGGL(k_rowexp, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, row_exp2, d, r);
 }
 
+// ---- per-tile precision of the bf16 Gram (WLC_BF16_AUTO)
+// The one-halo diagonal of distinct row e in FP64 from its factors,
+//   G_ee = sum_n Ts[e][n]^2 S[c(e)][n],  S[c][n] = sum_m G[c][n][m]^2
+// (the row of A is Ts[e][n] G[c][n][m] over k = (n, m)), then for every data
+// row a the share f_a = C1h_aa / C_aa, C_aa = C1h_aa + Gaussian + super-sample
+// as in k_rowexp, and per panel of 256 distinct rows the largest f_a.
+constexpr int SPLIT_PANEL = 256;  // rows per panel: the bf16 Gram tile
+
+__global__ void k_gsq(const double *__restrict__ G, int64_t items, int n_mg, double *__restrict__ S) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (item >= items) return;
+  const double *g = G + item * n_mg;
+  double acc = 0.0;
+  for (int m = lane; m < n_mg; m += WAVE) acc += g[m] * g[m];
+  acc = wave_sum(acc);
+  if (lane == 0) S[item] = acc;
+}
+
+__global__ void k_gdiag(const int32_t *__restrict__ rowR, const double *__restrict__ Ts, const double *__restrict__ S,
+                        int64_t n_R, int n_chi, double *__restrict__ gd) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (row >= n_R) return;
+  const int c = rowR[4 * row];
+  const double *t = Ts + row * n_chi;
+  const double *sc = S + (int64_t)c * n_chi;
+  double acc = 0.0;
+  for (int n = lane; n < n_chi; n += WAVE) acc += t[n] * t[n] * sc[n];
+  acc = wave_sum(acc);
+  if (lane == 0) gd[row] = acc;
+}
+
+__global__ void k_zero_f64(double *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_split_share(AsmArgs A, const double *__restrict__ gd, double *__restrict__ F) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= A.n) return;
+  const int32_t *ra = A.rowO + 8 * a;
+  const int64_t e = ra[1];
+  const double c1h = ldexp(gd[e], -2 * A.sexp[e]) * A.inv_omega;
+  const double rr = A.rR[e];
+  const double c = c1h + gauss_entry(A, ra, ra) + A.sigma_b2 * rr * rr;
+  // a share of 1 (no other term) for a row whose diagonal is not positive
+  const double f = c > 0.0 && isfinite(c) ? c1h / c : 1.0;
+  // non-negative doubles order like their bit patterns
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(f);
+  atomicMax((unsigned long long *)&F[e / SPLIT_PANEL], bits);
+  atomicMax((unsigned long long *)&F[A.ld_g / SPLIT_PANEL], bits);  // the largest of all panels
+}
+
+void launch_split_plan(const AsmArgs &a, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R,
+                       int n_cfg, int n_chi, int n_mg, double *S, double *gd, double *F, int n_panels, hipStream_t s) {
+  const int64_t items = (int64_t)n_cfg * n_chi;
+  hipLaunchKernelGGL(k_gsq, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, G, items, n_mg, S);
+  hipLaunchKernelGGL(k_gdiag, dim3((unsigned)((n_R + 3) / 4)), dim3(256), 0, s, rowR, Ts, S, n_R, n_chi, gd);
+  hipLaunchKernelGGL(k_zero_f64, dim3((n_panels + 256) / 256), dim3(256), 0, s, F, n_panels + 1);
+  hipLaunchKernelGGL(k_split_share, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, gd, F);
+}
+
 // 64 x 64 output tiles (I >= J); each thread computes 16 entries of one
 // column, the transposed copy goes through LDS so both halves are written
 // with contiguous rows.  Tiles are numbered row-major over the triangle and

@@ -265,17 +265,44 @@ __device__ __forceinline__ void gram_bf16_tile(const uint16_t *__restrict__ Ahi,
       }
 }
 
-template <bool X3, int NW>
+// Products of the bf16 kernels: MODE 0 one bf16 product, MODE 1 the split
+// product, MODE 2 per tile, the split product where the rows' largest
+// one-halo shares F (per 256-row panel) give F_I F_J > lim and one product
+// elsewhere (the split tiles are computed exactly as in MODE 1, the others
+// as in MODE 0).
+template <int MODE>
+__device__ __forceinline__ bool tile_split(const double *__restrict__ panel_f, double lim, int I, int J) {
+  if (MODE == 1) return true;
+  if (MODE == 0) return false;
+  return panel_f[I] * panel_f[J] > lim;
+}
+
+template <int MODE, int NW>
+__device__ __forceinline__ void gram_bf16_item(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
+                                               int64_t k_pad, int64_t r_pad, int64_t k_split, int I, int J,
+                                               int split, float *__restrict__ out, float *__restrict__ partial,
+                                               int64_t ld, int64_t part_stride, const double *__restrict__ panel_f,
+                                               double lim, uint16_t (*lds0)[2][T2 * BK2],
+                                               uint16_t (*lds1)[2][T2 * BK2]) {
+  if (tile_split<MODE>(panel_f, lim, I, J))
+    gram_bf16_tile<true, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, lds0, lds1);
+  else
+    gram_bf16_tile<false, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, lds0, lds1);
+}
+
+template <int MODE, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
                                                   int64_t k_pad, int64_t r_pad, int64_t k_split, int n_split,
                                                   int nt, int64_t n_work, float *__restrict__ out,
-                                                  float *__restrict__ partial, int64_t ld, int64_t part_stride) {
-  constexpr int NOPS = X3 ? 2 : 1;
+                                                  float *__restrict__ partial, int64_t ld, int64_t part_stride,
+                                                  const double *__restrict__ panel_f, double lim) {
+  constexpr int NOPS = MODE == 0 ? 1 : 2;
   __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];  // [op][I/J side]
   __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
   int I, J, split;
   if (!gram_work(n_work, n_split, nt, I, J, split)) return;
-  gram_bf16_tile<X3, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, lds0, lds1);
+  gram_bf16_item<MODE, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, panel_f, lim,
+                           lds0, lds1);
 }
 
 // ---------------------------------------------------------------- batched
@@ -293,10 +320,10 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
 // wait for one another, so the grid drains whatever the residency.
 constexpr int QSTRIDE = 16;  // counters 64 bytes apart
 
-template <bool X3, int NW>
+template <int MODE, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__restrict__ jobs, int n_jobs,
                                                         int64_t total, uint32_t *__restrict__ counters) {
-  constexpr int NOPS = X3 ? 2 : 1;
+  constexpr int NOPS = MODE == 0 ? 1 : 2;
   __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];
   __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
   __shared__ int64_t s_item;
@@ -324,8 +351,9 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__re
     const GramJob &jb = jobs[a];
     int I, J, split;
     gram_item(g - jb.item0, jb.n_work, jb.n_split, jb.nt, I, J, split);
-    gram_bf16_tile<X3, NW>((const uint16_t *)jb.A0, (const uint16_t *)jb.A1, jb.k_pad, jb.r_pad, jb.k_split, I, J,
-                           split, (float *)jb.out, (float *)jb.partial, jb.ld, jb.part_stride, lds0, lds1);
+    gram_bf16_item<MODE, NW>((const uint16_t *)jb.A0, (const uint16_t *)jb.A1, jb.k_pad, jb.r_pad, jb.k_split, I,
+                             J, split, (float *)jb.out, (float *)jb.partial, jb.ld, jb.part_stride, jb.panel_f,
+                             jb.split_lim, lds0, lds1);
   }
 }
 
@@ -551,7 +579,8 @@ static int pick_split(int64_t n_tiles, int64_t k_pad, int bk, bool bf16) {
   return (int)s;
 }
 
-static bool is_bf16(int prec) { return prec == WLC_BF16 || prec == WLC_BF16X3; }
+static bool is_bf16(int prec) { return prec == WLC_BF16 || prec == WLC_BF16X3 || prec == WLC_BF16_AUTO; }
+static int bf16_mode(int prec) { return prec == WLC_BF16 ? 0 : (prec == WLC_BF16X3 ? 1 : 2); }
 static int gram_tile(int prec) { return is_bf16(prec) ? T2 : TILE; }
 static int gram_bk(int prec) { return prec == WLC_FP64 ? 16 : (prec == WLC_FP32 ? 32 : BK2); }
 // the FP64 tile product needs even row pitch (16-byte chunks) and a 256-row
@@ -597,8 +626,11 @@ static GramSplit gram_split(int prec, const GramShape &g) {
 
 bool gram_batchable(int prec) { return is_bf16(prec); }
 
-void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job) {
+void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job,
+              const double *panel_f, double split_lim) {
   const GramSplit q = gram_split(prec, g);
+  job.panel_f = panel_f;
+  job.split_lim = split_lim;
   job.A0 = A0;
   job.A1 = A1;
   job.out = out;
@@ -616,14 +648,14 @@ void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void
 
 // Workgroups of the batched kernel that fit on the device at once (the grid
 // of the persistent launch), a multiple of N_XCD.
-template <bool X3>
+template <int MODE>
 static int batch_slots() {
   static int slots = 0;  // per process: every device here is the same part
   if (!slots) {
     int dev = 0, cus = 0, occ = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gram_bf16_batch<X3, GRAM_NW>, 64 * GRAM_NW, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gram_bf16_batch<MODE, GRAM_NW>, 64 * GRAM_NW, 0) !=
             hipSuccess || occ <= 0)
       occ = 1;
     slots = (cus * occ + N_XCD - 1) / N_XCD * N_XCD;
@@ -635,15 +667,18 @@ int launch_gram_batch(int prec, const GramJob *jobs_dev, int n_jobs, int64_t tot
                       hipStream_t s) {
   if (!gram_batchable(prec) || n_jobs < 1 || total < 1) return -1;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(GRAM_BATCH_COUNTERS), 0, s, counters, GRAM_BATCH_COUNTERS);
-  const bool x3 = prec == WLC_BF16X3;
-  const int64_t slots = x3 ? batch_slots<true>() : batch_slots<false>();
+  const int mode = bf16_mode(prec);
+  const int64_t slots = mode == 0 ? batch_slots<0>() : (mode == 1 ? batch_slots<1>() : batch_slots<2>());
   const unsigned grid = (unsigned)std::min<int64_t>(slots, (total + N_XCD - 1) / N_XCD * N_XCD);
-  if (x3)
-    hipLaunchKernelGGL((k_gram_bf16_batch<true, GRAM_NW>), dim3(grid), dim3(64 * GRAM_NW), 0, s, jobs_dev, n_jobs,
-                       total, counters);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_gram_bf16_batch<0, GRAM_NW>), dim3(grid), dim3(64 * GRAM_NW), 0, s, jobs_dev, n_jobs, total,
+                       counters);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_gram_bf16_batch<1, GRAM_NW>), dim3(grid), dim3(64 * GRAM_NW), 0, s, jobs_dev, n_jobs, total,
+                       counters);
   else
-    hipLaunchKernelGGL((k_gram_bf16_batch<false, GRAM_NW>), dim3(grid), dim3(64 * GRAM_NW), 0, s, jobs_dev, n_jobs,
-                       total, counters);
+    hipLaunchKernelGGL((k_gram_bf16_batch<2, GRAM_NW>), dim3(grid), dim3(64 * GRAM_NW), 0, s, jobs_dev, n_jobs, total,
+                       counters);
   return 0;
 }
 
@@ -663,7 +698,7 @@ void launch_gram_reduce(int prec, const GramShape &g, void *out, void *partial, 
 }
 
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
-                 hipStream_t s) {
+                 hipStream_t s, const double *panel_f, double split_lim) {
   const GramSplit q = gram_split(prec, g);
   const int64_t nt = q.nt, tiles = q.tiles, ksplit = q.ksplit, pstride = q.pstride, n_work = q.n_work;
   const int ns = q.ns;
@@ -671,14 +706,19 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
   const int nti = (int)nt;
   switch (prec) {
     case WLC_BF16:
-      hipLaunchKernelGGL((k_gram_bf16<false, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
+      hipLaunchKernelGGL((k_gram_bf16<0, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
                          (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
-                         g.ld_out, pstride);
+                         g.ld_out, pstride, panel_f, split_lim);
       break;
     case WLC_BF16X3:
-      hipLaunchKernelGGL((k_gram_bf16<true, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
+      hipLaunchKernelGGL((k_gram_bf16<1, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
                          (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
-                         g.ld_out, pstride);
+                         g.ld_out, pstride, panel_f, split_lim);
+      break;
+    case WLC_BF16_AUTO:
+      hipLaunchKernelGGL((k_gram_bf16<2, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
+                         (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
+                         g.ld_out, pstride, panel_f, split_lim);
       break;
     case WLC_FP32:
       hipLaunchKernelGGL(k_gram_x4<float>, grid, dim3(256), 0, s, (const float *)A0, g.k_pad, g.lda, ksplit, ns, nti,

@@ -523,12 +523,20 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
 // operand.
 constexpr int AB_KB = 8;
 
+// With panel_f (the per-tile precision of WLC_BF16_AUTO: per 256-row panel
+// the largest one-halo share, then the largest of all), the lo half of a
+// panel is written only if some tile of its row or column can take the split
+// product, F_P F_max > lim; the product never reads it otherwise.
 template <int FMT>
 __global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
                                                    const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
                                                    int64_t k_pad, int64_t r_pad, uint16_t *__restrict__ A0,
-                                                   uint16_t *__restrict__ A1) {
+                                                   uint16_t *__restrict__ A1, const double *__restrict__ panel_f,
+                                                   double lim) {
   const int64_t row = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 2);
+  // a workgroup's 64 rows lie in one 256-row panel
+  const bool need_lo = FMT == 2 && (panel_f == nullptr ||
+                                    panel_f[blockIdx.y / 4] * panel_f[r_pad / 256] > lim);
   const int chunk = threadIdx.x & 3;
   const int64_t k_len = (int64_t)n_chi * n_m;
   const bool live = row < n_R;
@@ -578,7 +586,7 @@ __global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ 
     for (int e = 0; e < 4; ++e) {
       const uint16_t h0 = f32_to_bf16_rne(x[2 * e]), h1 = f32_to_bf16_rne(x[2 * e + 1]);
       hi[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-      if constexpr (FMT == 2) {
+      if (need_lo) {
         const uint16_t g0 = f32_to_bf16_rne(x[2 * e] - bf16_to_f32(h0));
         const uint16_t g1 = f32_to_bf16_rne(x[2 * e + 1] - bf16_to_f32(h1));
         lo[e] = (uint32_t)g0 | ((uint32_t)g1 << 16);
@@ -586,22 +594,23 @@ __global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ 
     }
     const size_t off = ((size_t)kblk * r_pad + row) * GRAM_KB + 8 * chunk;
     *(u32x4 *)(A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
-    if constexpr (FMT == 2) *(u32x4 *)(A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+    if (need_lo) *(u32x4 *)(A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
   }
 }
 
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
-                   int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s) {
+                   int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s,
+                   const double *panel_f, double lim) {
   if (fmt == 1 || fmt == 2) {
     // r_pad is a multiple of 64 and k_pad of GRAM_KB (rows are padded to the
     // Gram tile, columns to 64)
     const dim3 grid((unsigned)((k_pad / GRAM_KB + AB_KB - 1) / AB_KB), (unsigned)(r_pad / 64));
     if (fmt == 1)
       hipLaunchKernelGGL(k_abuild_blk<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, r_pad,
-                         (uint16_t *)A0, (uint16_t *)A1);
+                         (uint16_t *)A0, (uint16_t *)A1, nullptr, 0.0);
     else
       hipLaunchKernelGGL(k_abuild_blk<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, r_pad,
-                         (uint16_t *)A0, (uint16_t *)A1);
+                         (uint16_t *)A0, (uint16_t *)A1, panel_f, lim);
     return;
   }
   // r_pad is a multiple of AB_ROWS (rows are padded to the Gram tile)

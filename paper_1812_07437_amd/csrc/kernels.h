@@ -39,8 +39,11 @@ void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT
 // GRAM_KB columns of a run of rows (one Gram stage of a row panel) are one
 // contiguous block (k_pad is a multiple of GRAM_KB).
 constexpr int GRAM_KB = 32;
+// panel_f, lim (fmt 2 only): write the lo half only for panels that can
+// take the split product (WLC_BF16_AUTO); nullptr writes it everywhere.
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
-                   int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s);
+                   int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s,
+                   const double *panel_f = nullptr, double lim = 0.0);
 
 // Two-leg factors of the projected one-halo trispectrum (P.T term): G2
 // [n2][n_chi][n_m] and Ts2 [rows][n_chi] for the n2 = n_ell (n_ell + 1) / 2
@@ -60,8 +63,9 @@ struct GramShape {
   int64_t lda;     // row pitch of A in elements (>= k_pad); bf16 operands are k-blocked instead
 };
 size_t gram_partial_bytes(int prec, const GramShape &g);
+// panel_f, split_lim: WLC_BF16_AUTO only (see k_gram.hip); ignored otherwise.
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
-                 hipStream_t s);
+                 hipStream_t s, const double *panel_f = nullptr, double split_lim = 0.0);
 // Batched bf16 Gram products (one persistent launch over the work items of
 // several products, e.g. of the requests of a server).  A product in a
 // batch computes exactly what launch_gram computes for it: the same tiles,
@@ -72,10 +76,13 @@ struct GramJob {
   int64_t r_pad, k_pad, k_split, ld, part_stride;
   int64_t n_work;        // work items: tiles x n_split
   int64_t item0;         // first item of this product in the batch (set by the caller)
+  const double *panel_f; // WLC_BF16_AUTO: per-panel largest one-halo share
+  double split_lim;      // WLC_BF16_AUTO: split tile (I, J) iff panel_f[I] panel_f[J] > split_lim
   int32_t n_split, nt;
 };
-bool gram_batchable(int prec);  // bf16 and split bf16
-void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job);
+bool gram_batchable(int prec);  // the bf16 precisions
+void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job,
+              const double *panel_f = nullptr, double split_lim = 0.0);
 // counters: N_XCD x 16 uint32 of device scratch, cleared by the launch itself
 constexpr int GRAM_BATCH_COUNTERS = 8 * 16;
 int launch_gram_batch(int prec, const GramJob *jobs_dev, int n_jobs, int64_t total, uint32_t *counters,
@@ -113,6 +120,14 @@ struct AsmArgs {
   int64_t ld_t2;
 };
 void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hipStream_t s);
+// WLC_BF16_AUTO: the largest one-halo share f_a = C1h_aa / C_aa of the data
+// rows of every 256-row panel of distinct rows, into F [n_panels], and the
+// largest of all into F[n_panels], from the
+// Gram factors in FP64 before the product: S [n_cfg][n_chi] and gd [n_R]
+// are scratch.  C_aa leaves out the in-survey terms (positive on the
+// diagonal), so F errs on the large side.
+void launch_split_plan(const AsmArgs &a, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R,
+                       int n_cfg, int n_chi, int n_mg, double *S, double *gd, double *F, int n_panels, hipStream_t s);
 void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s);
 
 // ---- signal-to-noise (k_chol.hip)

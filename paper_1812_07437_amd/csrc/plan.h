@@ -52,7 +52,7 @@ struct Plan {
 
 // Precision modes: valid range, and whether the covariance (and the Gram
 // output) is FP64.
-inline bool prec_valid(int p) { return p >= WLC_FP64 && p <= WLC_FP64_CHI; }
+inline bool prec_valid(int p) { return p >= WLC_FP64 && p <= WLC_BF16_AUTO; }
 inline bool prec_f64(int p) { return p == WLC_FP64 || p == WLC_FP64_CHI; }
 
 void set_error(const std::string &msg);

@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libwlcov.so")
 
 WLC_OK, WLC_EINVAL, WLC_ERANGE, WLC_ENOMEM, WLC_ENOTPD, WLC_EDEVICE, WLC_EBUSY, WLC_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 WLC_TOMO_PAPER, WLC_TOMO_SORTED = 0, 1
-WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32, WLC_FP64_CHI = 0, 1, 2, 3, 4
+WLC_FP64, WLC_BF16, WLC_BF16X3, WLC_FP32, WLC_FP64_CHI, WLC_BF16_AUTO = 0, 1, 2, 3, 4, 5
 WLC_FLAG_NOCHECK, WLC_FLAG_NGINS, WLC_FLAG_SSC_CHI = 1, 2, 4
 PRECISIONS = {"fp64": WLC_FP64, "bf16": WLC_BF16, "bf16x3": WLC_BF16X3, "fp32": WLC_FP32,
-              "fp64_chi": WLC_FP64_CHI}
+              "fp64_chi": WLC_FP64_CHI, "bf16_auto": WLC_BF16_AUTO}
 
 
 class WlcError(RuntimeError):
@@ -37,7 +37,7 @@ class wlc_config(ct.Structure):
                 ("ell_min", ct.c_double), ("ell_max", ct.c_double), ("ell_cut", ct.c_double),
                 ("f_sky", ct.c_double), ("sigma_eps", ct.c_double), ("n_gal_arcmin2", ct.c_double),
                 ("sigma_b2", ct.c_double), ("k_max", ct.c_double), ("rho_mean", ct.c_double),
-                ("n_sub", ct.c_int32)]
+                ("n_sub", ct.c_int32), ("gram_tol", ct.c_double)]
 
 
 class wlc_tables(ct.Structure):
@@ -72,6 +72,7 @@ def _load():
     L.wlc_snr2_structured.argtypes = [vp, vp, vp, ct.POINTER(ct.c_double), vp]
     L.wlc_snr2_lmax.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wlc_snr2_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.wlc_gram_split_tiles.argtypes = [vp, vp, vp, vp]
     L.wlc_pca.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
     L.wlc_plan_timings.argtypes = [vp, vp]
@@ -83,7 +84,7 @@ lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_averaging",
             "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_noalloc", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_noalloc", "wlc_gram_split_tiles", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
@@ -166,6 +167,13 @@ def wlc_snr2_noalloc(plan, C, row_exp2, d, snr2_dev, status_dev, stream):
     _check(lib.wlc_snr2_noalloc(plan, C, row_exp2, d, snr2_dev, status_dev, stream))
 
 
+def wlc_gram_split_tiles(plan, ws_run):
+    """(tiles that took the split product, tiles) of the last run."""
+    a, b = ct.c_int64(), ct.c_int64()
+    _check(lib.wlc_gram_split_tiles(plan, ws_run, ct.byref(a), ct.byref(b)))
+    return a.value, b.value
+
+
 def wlc_snr2_lmax(plan, C, row_exp2, d, ws, stream, n_ell):
     import numpy as np
     out = np.zeros(int(n_ell), np.float64)
@@ -190,7 +198,7 @@ def wlc_snr2_structured(plan, ws_run, ws, stream):
 
 # ---------------------------------------------------------------- helpers
 def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False, ngins=False,
-                ssc_chi=False, n_sub=0) -> wlc_config:
+                ssc_chi=False, n_sub=0, gram_tol=0.0) -> wlc_config:
     """wlc_config from a dict of scalars (n_z, n_ell, n_chi, n_k, n_m, ell_min,
     ell_max, f_sky, sigma_eps, n_gal_arcmin2, sigma_b2, k_max, rho_mean and
     optionally ell_cut); ngins adds the B.B, P.T and P.B terms, ssc_chi
@@ -206,7 +214,7 @@ def make_config(cfg: dict, precision="fp64", tomo="paper", nocheck=False, ngins=
                       ell_cut=float(cfg.get("ell_cut", 0.0) or 0.0), f_sky=float(cfg["f_sky"]),
                       sigma_eps=float(cfg["sigma_eps"]), n_gal_arcmin2=float(cfg["n_gal_arcmin2"]),
                       sigma_b2=float(cfg["sigma_b2"]), k_max=float(cfg["k_max"]), rho_mean=float(cfg["rho_mean"]),
-                      n_sub=int(n_sub))
+                      n_sub=int(n_sub), gram_tol=float(gram_tol))
 
 
 def _ptr(t):
@@ -224,11 +232,11 @@ class Problem:
     u, n_m, optional b1, b2, n_tri) to float64 arrays (numpy or torch)."""
 
     def __init__(self, cfg: dict, arrays: dict, precision="fp64", tomo="paper", device="cuda:0",
-                 nocheck=False, ngins=False, ssc_chi=False, n_sub=0):
+                 nocheck=False, ngins=False, ssc_chi=False, n_sub=0, gram_tol=0.0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.config = make_config(cfg, precision, tomo, nocheck, ngins, ssc_chi, n_sub)
+        self.config = make_config(cfg, precision, tomo, nocheck, ngins, ssc_chi, n_sub, gram_tol)
         self.plan = wlc_plan_create(self.config)
         self.sizes = wlc_plan_sizes(self.plan)
         self._tabs = {}
@@ -281,6 +289,11 @@ class Problem:
         (int32), one element each, through the fixed-scratch entry point."""
         wlc_snr2_noalloc(self.plan, _ptr(self.C), _ptr(self.row_exp2), _ptr(self.d), _ptr(out), _ptr(status),
                          _stream_handle(stream))
+
+    def split_tiles(self):
+        """(split, total) tiles of this problem's last run's one-halo product."""
+        self.torch.cuda.synchronize()
+        return wlc_gram_split_tiles(self.plan, _ptr(self.ws))
 
     def snr2_lmax(self, stream=None):
         """(S/N)^2 of the data vector cut after each ell-bin (numpy array)."""

@@ -93,3 +93,99 @@ def test_mixed_precision_euclid5(env, precision, tol_diag, tol_off, tol_snr):
     # the data vector and responses do not depend on the Gram's precision
     assert np.max(np.abs(prob.d.cpu().numpy() - ref["d"]) / ref["d"]) < 1e-10
     prob.close()
+
+
+# ---------------------------------------------------------------- per-tile precision
+def _panel_shares(o, prob):
+    """F_I: the largest one-halo share C1h_aa / C_aa of the data rows whose
+    distinct row lies in 256-row panel I, from the oracle's FP64 diagonal."""
+    idx = np.arange(o.N)
+    pairs = np.stack([idx, idx], 1)
+    f = o.cov1h_pairs(pairs) / o.cov_pairs(pairs)
+    _, _, dist = prob.index()
+    F = np.zeros((prob.sizes.n_distinct + 255) // 256)
+    np.maximum.at(F, dist // 256, f)
+    return F, dist
+
+
+def _tile_bound(F, k_len):
+    eps = 2 * 2.0 ** -8 + 2.0 ** -16 + ((k_len + 63) // 64 * 64) * 2.0 ** -24
+    return eps * np.sqrt(np.outer(F, F))
+
+
+def test_auto_default_is_one_product_euclid5(env):
+    """The default bound 2^-17 holds for every tile with one bf16 product on
+    this workload, so the result is the plain bf16 one bit for bit, within
+    the mixed-precision targets of the oracle."""
+    wl, t, ref = env
+    _say("case precision euclid5 bf16_auto (default bound)")
+    pa = wl.Problem(t.cfg, t.arrays(), precision="bf16_auto")
+    F, _ = _panel_shares(oracle.Oracle(t), pa)
+    assert np.max(_tile_bound(F, pa.sizes.k_len)) < 2.0 ** -17 * 0.95
+    pa.run()
+    s_a = pa.snr2()
+    pb = wl.Problem(t.cfg, t.arrays(), precision="bf16")
+    pb.run()
+    s_b = pb.snr2()
+    torch.cuda.synchronize()
+    assert torch.equal(pa.C, pb.C) and torch.equal(pa.row_exp2, pb.row_exp2) and s_a == s_b
+    dmax, dmed, omax = _errors(pa.covariance_true(), ref["C"])
+    _say("  bf16_auto euclid5: diag max %.2e, off-diagonal %.2e, (S/N)^2 %.2e" % (
+        dmax, omax, abs(s_a - ref["snr2"]) / ref["snr2"]))
+    assert dmax < 1e-5 and omax < 1e-5 and abs(s_a - ref["snr2"]) / ref["snr2"] < 1e-4
+    pa.close()
+    pb.close()
+
+
+@pytest.mark.parametrize("tol,other", [(1e-30, "bf16x3"), (1.0, "bf16")])
+def test_auto_limits(env, tol, other):
+    """A bound below every tile's takes the split product everywhere (= bf16x3);
+    one above every tile's takes one product everywhere (= bf16)."""
+    wl, _, _ = env
+    _say("case precision mid bf16_auto tol=%g vs %s" % (tol, other))
+    t = synth.make_tables("mid")
+    pa = wl.Problem(t.cfg, t.arrays(), precision="bf16_auto", gram_tol=tol)
+    pa.run()
+    s_a = pa.snr2()
+    pb = wl.Problem(t.cfg, t.arrays(), precision=other)
+    pb.run()
+    s_b = pb.snr2()
+    torch.cuda.synchronize()
+    assert torch.equal(pa.C, pb.C) and torch.equal(pa.d, pb.d) and s_a == s_b
+    pa.close()
+    pb.close()
+
+
+def test_auto_mixed_tiles_euclid5(env):
+    """With a bound of 1e-6 the five tiles whose one-product bound exceeds it
+    (the ones touching the first panel's large one-halo share) take the split
+    product and the others one product: every entry equals the bf16x3 or the
+    bf16 result of its tile, and every entry is within the bound of the
+    oracle (relative to sqrt(C_aa C_bb), plus the FP32 storage of C)."""
+    wl, t, ref = env
+    tol = 1e-6
+    _say("case precision euclid5 bf16_auto mixed tiles (tol %g)" % tol)
+    o = oracle.Oracle(t)
+    pa = wl.Problem(t.cfg, t.arrays(), precision="bf16_auto", gram_tol=tol)
+    F, dist = _panel_shares(o, pa)
+    split = _tile_bound(F, pa.sizes.k_len) > tol
+    n_split = int(np.sum(np.tril(split)))
+    _say("  split tiles %d of %d" % (n_split, split.shape[0] * (split.shape[0] + 1) // 2))
+    assert 1 <= n_split < split.shape[0] * (split.shape[0] + 1) // 2
+    pa.run()
+    Ca = pa.covariance_true()
+    runs = {}
+    for prec in ("bf16x3", "bf16"):
+        p = wl.Problem(t.cfg, t.arrays(), precision=prec)
+        p.run()
+        torch.cuda.synchronize()
+        runs[prec] = p.covariance_true()
+        p.close()
+    pan = dist // 256
+    use_x3 = split[pan[:, None], pan[None, :]]
+    want = np.where(use_x3, runs["bf16x3"], runs["bf16"])
+    assert np.array_equal(Ca, want)
+    _, _, omax = _errors(Ca, ref["C"])
+    _say("  off-diagonal error %.2e (bound %.1e)" % (omax, tol))
+    assert omax < tol + 1e-7
+    pa.close()

@@ -38,14 +38,16 @@ def _submit(srv, q):
 
 def _mix(fid, reqs):
     """Requests of every size class in one mix: the small ones of the fixture,
-    an n_z = 7 request in plain bf16 (a batch of another precision), an
-    n_z = 10, l_max = 5000 request (N = 82575, the wide batch lane) and a
-    small FP64 request (its own Gram launch)."""
+    an n_z = 7 request in plain bf16 and an n_z = 5 one with the per-tile
+    precision (batches of other precisions), an n_z = 10, l_max = 5000
+    request (N = 82575, the wide batch lane) and a small FP64 request (its
+    own Gram launch)."""
     base = reqs[0]
     def req(n_z, ell_max, **kw):
         return dict(base, n_z=n_z, ell_max=ell_max, W=synth.lensing_kernels(
             fid.chi, base["omega_m"], synth.equipopulated_edges(n_z)), **kw)
-    return list(reqs) + [req(7, 3000.0, precision="bf16"), req(10, 5000.0), req(3, 1000.0, precision="fp64")]
+    return list(reqs) + [req(7, 3000.0, precision="bf16"), req(10, 5000.0), req(3, 1000.0, precision="fp64"),
+                         req(5, 5000.0, precision="bf16_auto")]
 
 
 def test_alone_equals_mix(env):
@@ -80,7 +82,7 @@ def test_alone_equals_mix(env):
     overlapped = sum(1 for i, (a0, d0) in enumerate(spans) for j, (a1, d1) in enumerate(spans)
                      if i < j and a1 < d0 and a0 < d1)
     st = srv.stats()
-    n_batchable = sum(1 for q in mix if q.get("precision", "bf16x3") in ("bf16", "bf16x3"))
+    n_batchable = sum(1 for q in mix if q.get("precision", "bf16x3") in ("bf16", "bf16x3", "bf16_auto"))
     _say("  overlapping request pairs: %d; batches %d, batched requests %d, largest batch %d" % (
         overlapped, st.batches - st0.batches, st.batched_requests - st0.batched_requests, st.max_batch))
     assert overlapped >= 1
