@@ -7,7 +7,7 @@ wlc_snr2 (FP64 bordered Cholesky and S/N).  Inputs are resident in HBM before
 the timed region.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload large10|euclid5]
-                  [--precision bf16x3|bf16|fp32|fp64] [--fp64-steps S] [--no-cpu]
+                  [--precision bf16_auto|bf16x3|bf16|fp32|fp64] [--fp64-steps S] [--no-cpu]
 """
 import argparse
 import json
@@ -33,7 +33,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large10")
-    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--precision", default="bf16_auto",
+                    help="Gram precision of the headline step: bf16_auto (one bf16 product per tile where the "
+                         "a-priori bound allows, the split product elsewhere), bf16x3, bf16, fp32 or fp64")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--chi-steps", type=int, default=1,
                     help="steps of the FP64 path with the one-halo term factorised along chi (0: skip)")
@@ -643,7 +645,10 @@ def main():
                     launches=1, avg_launch_ms=ph["gram"], flops_per_step=gram_flops(NR, K))
     roof["traffic_unit"] = "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["traffic_source"] = tr["summary"] if tr else None
-    a_bytes = NR * K * {"bf16": 2, "bf16x3": 4, "fp32": 4, "fp64": 8}[args.precision]
+    # the per-tile mode writes the lo half only for panels that can take the
+    # split product: none when no tile does, else at most every panel
+    auto_bytes = 2 if split_main is not None and split_main[0] == 0 else 4
+    a_bytes = NR * K * {"bf16": 2, "bf16x3": 4, "bf16_auto": auto_bytes, "fp32": 4, "fp64": 8}[args.precision]
     c_bytes = N * N * (8 if args.precision == "fp64" else 4)
     kernels = dict(
         gram=gram_fig,
