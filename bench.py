@@ -44,8 +44,8 @@ def parse():
     ap.add_argument("--pca-workload", default="euclid5",
                     help="workload of the PCA leg (FP64 covariance, then wlc_pca; empty: skip)")
     ap.add_argument("--pca-only", action="store_true")
-    ap.add_argument("--no-pca-tomography", dest="pca_tomography", action="store_false",
-                    help="skip the PCA of the paper's 14-bin binning with 1, 2 and 5 redshift bins")
+    ap.add_argument("--pca-tomography", action="store_true",
+                    help="also run the PCA of the paper's 14-bin binning with 1, 2 and 5 redshift bins")
     ap.add_argument("--precision-workload", default="euclid5",
                     help="workload of the Gram precision report (bf16, bf16x3, fp32 vs FP64; empty: skip)")
     ap.add_argument("--no-gram-variants", dest="gram_variants", action="store_false",

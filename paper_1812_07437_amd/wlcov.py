@@ -52,10 +52,24 @@ class wlc_sizes(ct.Structure):
                 ("ws_snr_structured_bytes", ct.c_size_t), ("n_avg", ct.c_int64), ("ws_pca_bytes", ct.c_size_t)]
 
 
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return {line.split()[-1] for line in f if "libamdhip64" in line and "/" in line}
+    except OSError:
+        return set()
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libwlcov.so is not built (run paper_1812_07437_amd.build.build())")
     L = ct.CDLL(LIB_PATH)
+    # one HIP runtime per process: with two (libwlcov bound to another copy
+    # than torch's), device pointers of one are invalid in the other
+    rt = _hip_runtimes()
+    if len(rt) > 1:
+        raise ImportError("libwlcov and torch loaded different HIP runtimes: %s" % sorted(rt))
     vp = ct.c_void_p
     L.wlc_last_error.restype = ct.c_char_p
     L.wlc_plan_create.argtypes = [ct.POINTER(wlc_config), ct.POINTER(vp)]

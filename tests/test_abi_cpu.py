@@ -122,9 +122,10 @@ def test_precision_modes():
         s = w.wlc_plan_sizes(plan)
         assert s.c_elem_bytes == (8 if name in ("fp64", "fp64_chi") else 4)
         w.wlc_plan_destroy(plan)
-    with pytest.raises(w.WlcError) as e:
-        w.wlc_plan_create(w.make_config(t, 5))
-    assert e.value.code == w.WLC_EINVAL
+    for bad in (6, -1):
+        with pytest.raises(w.WlcError) as e:
+            w.wlc_plan_create(w.make_config(t, bad))
+        assert e.value.code == w.WLC_EINVAL
 
 
 def test_null_arguments_rejected():
