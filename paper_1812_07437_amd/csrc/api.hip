@@ -487,7 +487,7 @@ int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, d
   if (hooks) hooks->begin(WLC_PHASE_ASSEMBLE);
   launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
   launch_rowexp(a, row_exp2, d, r, s);
-  launch_assemble(a, row_exp2, C, !prec_f64(c.precision), s);
+  launch_assemble(a, row_exp2, C, s);
   if (hooks) hooks->end(WLC_PHASE_ASSEMBLE);
   return hip_check(hipGetLastError(), "run launch");
 }

@@ -217,14 +217,17 @@ void launch_split_plan(const AsmArgs &a, const int32_t *rowR, const double *Ts, 
 // with contiguous rows.  Tiles are numbered row-major over the triangle and
 // each XCD (workgroup b runs on XCD b mod 8, each XCD has its own L2) takes
 // a contiguous run of them, so the one-halo rows of a tile row are fetched
-// into one L2 instead of all eight.
+// into one L2 instead of all eight.  A tile's loads form two rounds: the
+// row records and output exponents, then (all depending only on the
+// records) the one-halo values and the distinct rows' exponents and
+// responses, so a workgroup waits on global memory twice before it writes.
 constexpr int AT = 64;
 constexpr int ASM_XCD = 8;
 
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__restrict__ row_exp2,
                                                   OutT *__restrict__ C, int64_t n_tiles) {
-  __shared__ double tileT[AT][AT + 1];
+  __shared__ OutT tileT[AT][AT + 1];
   __shared__ int32_t rowA[AT][8], rowB[AT][8];
   __shared__ int32_t tA[AT], tB[AT], sA[AT], sB[AT];
   __shared__ double rA[AT], rB[AT];
@@ -242,52 +245,48 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__re
     rowA[r][c] = a0 + r < A.n ? A.rowO[(a0 + r) * 8 + c] : 0;
     rowB[r][c] = b0 + r < A.n ? A.rowO[(b0 + r) * 8 + c] : 0;
   }
-  __syncthreads();
   if (tid < AT) {
-    const int64_t a = a0 + tid;
-    tA[tid] = a < A.n ? row_exp2[a] : 0;
-    sA[tid] = a < A.n ? A.sexp[rowA[tid][1]] : 0;
-    rA[tid] = a < A.n ? A.rR[rowA[tid][1]] : 0.0;
+    tA[tid] = a0 + tid < A.n ? row_exp2[a0 + tid] : 0;
   } else if (tid < 2 * AT) {
-    const int q = tid - AT;
-    const int64_t b = b0 + q;
-    tB[q] = b < A.n ? row_exp2[b] : 0;
-    sB[q] = b < A.n ? A.sexp[rowB[q][1]] : 0;
-    rB[q] = b < A.n ? A.rR[rowB[q][1]] : 0.0;
+    tB[tid - AT] = b0 + tid - AT < A.n ? row_exp2[b0 + tid - AT] : 0;
   }
   __syncthreads();
   const int cb = tid & 63;          // column within the tile
   const int rbase = (tid >> 6) * 16;
   const int64_t b = b0 + cb;
-  // the 16 one-halo values first, all loads in flight together (padding
-  // rows map to distinct row 0, so every index is valid)
-  double gv[16];
+  // the 16 one-halo values, all loads in flight together with those of the
+  // exponents and responses (padding rows map to distinct row 0, so every
+  // index is valid)
+  // (the one-halo block has the output's type: FP32 for the mixed modes)
+  OutT gv[16];
   const int64_t eb = rowB[cb][1];
-  if (A.gm_f32) {
-    const float *G = (const float *)A.Gm;
-    float gf[16];
+  const OutT *G = (const OutT *)A.Gm;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) gf[q] = G[rowA[rbase + q][1] * A.ld_g + eb];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) gv[q] = (double)gf[q];
-  } else {
-    const double *G = (const double *)A.Gm;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) gv[q] = G[rowA[rbase + q][1] * A.ld_g + eb];
+  for (int q = 0; q < 16; ++q) gv[q] = G[rowA[rbase + q][1] * A.ld_g + eb];
+  if (tid < AT) {
+    const bool live = a0 + tid < A.n;
+    sA[tid] = live ? A.sexp[rowA[tid][1]] : 0;
+    rA[tid] = live ? A.rR[rowA[tid][1]] : 0.0;
+  } else if (tid < 2 * AT) {
+    const int q = tid - AT;
+    const bool live = b0 + q < A.n;
+    sB[q] = live ? A.sexp[rowB[q][1]] : 0;
+    rB[q] = live ? A.rR[rowB[q][1]] : 0.0;
   }
+  __syncthreads();
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int ra = rbase + q;
     const int64_t a = a0 + ra;
-    double v = 0.0;
+    OutT v = 0;
     const bool live = a < A.n && b < A.n && a >= b;
     if (live) {
       const int tt = tA[ra] + tB[cb];
-      const double g = gv[q];
+      const double g = (double)gv[q];
       double rest = A.sigma_b2 * rA[ra] * rB[cb] + gauss_entry(A, rowA[ra], rowB[cb]);
       if (A.ngins) rest += ngins_entry(A, rowA[ra], rowB[cb]);
-      v = ldexp(g * A.inv_omega, tt - sA[ra] - sB[cb]) + ldexp(rest, tt);
-      C[a * A.n + b] = (OutT)v;
+      v = (OutT)(ldexp(g * A.inv_omega, tt - sA[ra] - sB[cb]) + ldexp(rest, tt));
+      C[a * A.n + b] = v;
     }
     tileT[ra][cb] = v;
   }
@@ -298,15 +297,15 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__re
     const int rb = rbase + q;  // row of the transposed tile (b index)
     const int ca = cb;         // column (a index)
     const int64_t bb = b0 + rb, aa = a0 + ca;
-    if (aa < A.n && bb < A.n && aa > bb) C[bb * A.n + aa] = (OutT)tileT[ca][rb];
+    if (aa < A.n && bb < A.n && aa > bb) C[bb * A.n + aa] = tileT[ca][rb];
   }
 }
 
-void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s) {
+void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, hipStream_t s) {
   const int64_t nt = (a.n + AT - 1) / AT;
   const int64_t tiles = nt * (nt + 1) / 2;
   const dim3 grid((unsigned)((tiles + ASM_XCD - 1) / ASM_XCD * ASM_XCD));
-  if (c_f32)
+  if (a.gm_f32)
     hipLaunchKernelGGL(k_assemble<float>, grid, dim3(256), 0, s, a, row_exp2, (float *)C, tiles);
   else
     hipLaunchKernelGGL(k_assemble<double>, grid, dim3(256), 0, s, a, row_exp2, (double *)C, tiles);

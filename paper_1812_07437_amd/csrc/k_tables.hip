@@ -516,12 +516,24 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
   }
 }
 
-// k-blocked bf16 (hi, and lo for fmt 2; see launch_abuild): a 256-thread
-// block covers 64 rows and AB_KB consecutive 32-column k-blocks; in each,
-// lane l of a wavefront converts 8 consecutive k of row l / 4 (chunk l % 4),
-// so the wavefront writes 16 whole rows of the block, 1 KB contiguous per
-// operand.
-constexpr int AB_KB = 8;
+// k-blocked bf16 (fmt 1: hi only; fmt 2: hi and lo; see launch_abuild): a 256-thread
+// block covers 64 rows and AB_KB consecutive 32-column k-blocks.  Each
+// wavefront takes every fourth k-block of the block; in one, lane l converts
+// 8 consecutive k (chunk l % 4) of the rows l / 4 + 16 j, j < AB_RW, so that
+// each of its stores writes 16 whole rows of the k-block, 1 KB contiguous.
+// Consecutive distinct rows mostly share their configuration, so a lane's
+// 8 values of G are loaded once for its rows of one configuration, and T
+// once per row and chi node.  When N_M is a multiple of 8 a chunk lies in
+// one chi node; otherwise the values are taken one by one.
+constexpr int AB_KB = 32;
+constexpr int AB_RW = 4;
+
+// Two floats to packed bf16, rounded to nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pack_bf16_rne(float a, float b) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2));
+}
 
 // With panel_f (the per-tile precision of WLC_BF16_AUTO: per 256-row panel
 // the largest one-halo share, then the largest of all), the lo half of a
@@ -533,68 +545,78 @@ __global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ 
                                                    int64_t k_pad, int64_t r_pad, uint16_t *__restrict__ A0,
                                                    uint16_t *__restrict__ A1, const double *__restrict__ panel_f,
                                                    double lim) {
-  const int64_t row = (int64_t)blockIdx.y * 64 + (threadIdx.x >> 2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int chunk = lane & 3;
+  const int64_t row0 = (int64_t)blockIdx.y * 64 + (lane >> 2);
   // a workgroup's 64 rows lie in one 256-row panel
-  const bool need_lo = FMT == 2 && (panel_f == nullptr ||
-                                    panel_f[blockIdx.y / 4] * panel_f[r_pad / 256] > lim);
-  const int chunk = threadIdx.x & 3;
+  const bool need_lo = FMT == 2 && (panel_f == nullptr || panel_f[blockIdx.y / 4] * panel_f[r_pad / 256] > lim);
   const int64_t k_len = (int64_t)n_chi * n_m;
-  const bool live = row < n_R;
-  const int c = live ? rowR[4 * row] : 0;
-  const double *Gc = G + (size_t)c * k_len;
-  const double *Tr = Ts + (size_t)(live ? row : 0) * n_chi;
-  const bool pairs = (k_len & 1) == 0;  // 16-byte aligned pairs of G
-  for (int q = 0; q < AB_KB; ++q) {
+  const bool whole = (n_m & 7) == 0;  // a chunk of 8 k lies in one chi node
+  int cfg[AB_RW];
+  const double *Tr[AB_RW];
+#pragma unroll
+  for (int j = 0; j < AB_RW; ++j) {
+    const int64_t row = row0 + 16 * j;
+    cfg[j] = row < n_R ? rowR[4 * row] : -1;
+    Tr[j] = Ts + (size_t)(row < n_R ? row : 0) * n_chi;
+  }
+  int node[AB_RW];
+  double tn[AB_RW];
+#pragma unroll
+  for (int j = 0; j < AB_RW; ++j) node[j] = -1, tn[j] = 0.0;
+  for (int q = wave; q < AB_KB; q += 4) {
     const int64_t kblk = (int64_t)blockIdx.x * AB_KB + q;
+    if (kblk * GRAM_KB >= k_pad) break;
     const int64_t k0 = kblk * GRAM_KB + 8 * chunk;
-    if (k0 >= k_pad) break;
-    float x[8];
-    if (live && k0 + 8 <= k_len) {
-      double g[8];
-      if (pairs) {
+    const int n = k0 < k_len ? (int)(k0 / n_m) : 0;
+    double g[8];
+    int gc = -1;
 #pragma unroll
-        for (int e = 0; e < 8; e += 2) {
-          const double2 t = *(const double2 *)(Gc + k0 + e);
-          g[e] = t.x;
-          g[e + 1] = t.y;
+    for (int j = 0; j < AB_RW; ++j) {
+      const int64_t row = row0 + 16 * j;
+      float x[8];
+      if (whole && cfg[j] >= 0 && k0 < k_len) {
+        if (cfg[j] != gc) {
+          const double *Gc = G + (size_t)cfg[j] * k_len + k0;
+#pragma unroll
+          for (int e = 0; e < 8; e += 2) {
+            const double2 t = *(const double2 *)(Gc + e);
+            g[e] = t.x;
+            g[e + 1] = t.y;
+          }
+          gc = cfg[j];
         }
+        if (node[j] != n) {
+          node[j] = n;
+          tn[j] = Tr[j][n];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = (float)(tn[j] * g[e]);
       } else {
+        // one by one, stepping across the chi node edges (k0 = n N_M + m)
+        const double *Gc = G + (size_t)(cfg[j] >= 0 ? cfg[j] : 0) * k_len;
+        int nn = n, mm = (int)(k0 - (int64_t)n * n_m);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) g[e] = Gc[k0 + e];
-      }
-      // chi node of each k: one division, then a step across the node edge
-      int n = (int)(k0 / n_m), m = (int)(k0 % n_m);
-      double tn = Tr[n];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        x[e] = (float)(tn * g[e]);
-        if (++m == n_m && e < 7) {
-          m = 0;
-          ++n;
-          tn = Tr[n];  // k0 + e + 1 < k_len, so n < n_chi
+        for (int e = 0; e < 8; ++e) {
+          const int64_t k = k0 + e;
+          x[e] = cfg[j] >= 0 && k < k_len ? (float)(Tr[j][nn] * Gc[k]) : 0.0f;
+          if (++mm == n_m) mm = 0, ++nn;
         }
       }
-    } else {
+      uint32_t hi[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + e;
-        x[e] = live && k < k_len ? (float)(Tr[k / n_m] * Gc[k]) : 0.0f;
-      }
-    }
-    uint32_t hi[4], lo[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint16_t h0 = f32_to_bf16_rne(x[2 * e]), h1 = f32_to_bf16_rne(x[2 * e + 1]);
-      hi[e] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      for (int e = 0; e < 4; ++e) hi[e] = pack_bf16_rne(x[2 * e], x[2 * e + 1]);
+      const size_t off = ((size_t)kblk * r_pad + row) * GRAM_KB + 8 * chunk;
+      *(u32x4 *)(A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
       if (need_lo) {
-        const uint16_t g0 = f32_to_bf16_rne(x[2 * e] - bf16_to_f32(h0));
-        const uint16_t g1 = f32_to_bf16_rne(x[2 * e + 1] - bf16_to_f32(h1));
-        lo[e] = (uint32_t)g0 | ((uint32_t)g1 << 16);
+        uint32_t lo[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          lo[e] = pack_bf16_rne(x[2 * e] - __uint_as_float(hi[e] << 16),
+                                x[2 * e + 1] - __uint_as_float(hi[e] & 0xFFFF0000u));
+        *(u32x4 *)(A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
       }
     }
-    const size_t off = ((size_t)kblk * r_pad + row) * GRAM_KB + 8 * chunk;
-    *(u32x4 *)(A0 + off) = u32x4{hi[0], hi[1], hi[2], hi[3]};
-    if (need_lo) *(u32x4 *)(A1 + off) = u32x4{lo[0], lo[1], lo[2], lo[3]};
   }
 }
 

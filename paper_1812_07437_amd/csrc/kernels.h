@@ -128,7 +128,8 @@ void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hi
 // diagonal), so F errs on the large side.
 void launch_split_plan(const AsmArgs &a, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R,
                        int n_cfg, int n_chi, int n_mg, double *S, double *gd, double *F, int n_panels, hipStream_t s);
-void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, int c_f32, hipStream_t s);
+// C in the type of the one-halo block Gm: FP32 when gm_f32, else FP64.
+void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, hipStream_t s);
 
 // ---- signal-to-noise (k_chol.hip)
 // perm (optional): row/column a of the bordered matrix is row perm[a] of C
