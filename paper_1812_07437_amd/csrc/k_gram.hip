@@ -156,6 +156,12 @@ constexpr int GRAM_NW = 8;  // measured faster than 4 at both precisions
 
 __device__ __forceinline__ int swz2(int r, int c) { return r * BK2 + ((c ^ (((r >> 1) ^ (r >> 3)) & 3)) << 3); }
 
+// One stage of one operand: [side][T2 * BK2] (side 0 the rows of tile I,
+// side 1 those of tile J).  Every stage buffer is a __shared__ array of its
+// own, so the compiler can tell the buffer being filled from the ones being
+// read and does not wait for a copy before reading another buffer.
+typedef uint16_t GramStage[2][T2 * BK2];
+
 // Wavefront w copies the 1 KB blocks idx = w PERW + q, q < PERW, of a stage's
 // NOPS x 2 x 16 blocks (operand, side, 16-row group).  PERW divides 16, so a
 // wavefront's blocks share operand and side, and its source is one panel.
@@ -166,11 +172,12 @@ struct GramDma {
   uint32_t off[PERW];   // byte offset of this lane's chunk in the 16 KB panel stage
   const char *panel;    // the wavefront's panel at stage 0 (wavefront-uniform)
   int64_t stage_bytes;  // distance between consecutive k-blocks of A
-  int blk0;
+  int blk0, op;
   __device__ __forceinline__ void init(const uint16_t *Ahi, const uint16_t *Alo, int64_t r_pad, int64_t row0,
                                        int64_t col0, int wave, int lane) {
     blk0 = wave * PERW;
-    const int op = blk0 >> 5, side = (blk0 >> 4) & 1;
+    op = blk0 >> 5;
+    const int side = (blk0 >> 4) & 1;
     panel = (const char *)((op == 0 ? Ahi : Alo) + (side == 0 ? row0 : col0) * BK2);
     stage_bytes = r_pad * BK2 * 2;
 #pragma unroll
@@ -180,47 +187,64 @@ struct GramDma {
       off[q] = (uint32_t)(r * BK2 * 2 + 16 * c);
     }
   }
-  // copy k-block kblk of the panel into buf; the copies are issued before
-  // anything that follows (the scheduler would otherwise sink them below the
-  // products, next to the wait for them)
-  __device__ __forceinline__ void issue(int64_t kblk, void *buf) const {
+  // copy k-block kblk of the panel into the stage buffer of this wavefront's
+  // operand; the copies are issued before anything that follows (the
+  // scheduler would otherwise sink them below the products, next to the wait
+  // for them)
+  __device__ __forceinline__ void issue(int64_t kblk, GramStage &buf) const {
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void *)(panel + kblk * stage_bytes), 0, T2 * BK2 * 2, 0x00020000);
 #pragma unroll
     for (int q = 0; q < PERW; ++q)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          rsrc, (__attribute__((address_space(3))) void *)((char *)buf + (blk0 + q) * 1024), 16, off[q], 0, 0, 0);
+          rsrc, (__attribute__((address_space(3))) void *)((char *)buf + ((blk0 + q) & 31) * 1024), 16, off[q], 0, 0,
+          0);
     __builtin_amdgcn_sched_barrier(0);
+  }
+  __device__ __forceinline__ void issue(int64_t kblk, GramStage &hi, GramStage &lo) const {
+    if (op == 0)
+      issue(kblk, hi);
+    else
+      issue(kblk, lo);
   }
 };
 
-// One work item: tile (I, J), k slice split, through the workgroup's two LDS
-// stage buffers (distinct __shared__ arrays of the calling kernel).
+// Wait until at most N vector-memory operations of this wavefront are
+// outstanding (s_waitcnt vmcnt(N), the other counters left alone).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+
+// Workgroup barrier without a memory fence: the callers wait for their own
+// copies into LDS with wait_vmcnt first (a fence would wait for all of them,
+// including the ones still meant to be in flight).  Every LDS read before it
+// has been consumed by the products, so none is outstanding; lgkmcnt(0)
+// states it.
+__device__ __forceinline__ void stage_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// The products of one 32-k stage on a wavefront's 128 x WCOLS sub-tile:
+// X3 false one product of the hi operands, true the split product.
 template <bool X3, int NW>
-__device__ __forceinline__ void gram_bf16_tile(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
-                                               int64_t k_pad, int64_t r_pad, int64_t k_split, int I, int J,
-                                               int split, float *__restrict__ out, float *__restrict__ partial,
-                                               int64_t ld, int64_t part_stride,
-                                               uint16_t (*lds0)[2][T2 * BK2], uint16_t (*lds1)[2][T2 * BK2]) {
-  constexpr int NOPS = X3 ? 2 : 1;  // hi (and lo)
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
-  const int64_t kb = (int64_t)split * k_split;
-  const int64_t ke = min(k_pad, kb + k_split);
-  constexpr int WCOLS = 512 / NW;  // wavefront tile columns
-  constexpr int BJ = WCOLS / 32;   // 32-column blocks per wavefront
-  const int wr = (wave / (NW / 2)) * 128, wc = (wave % (NW / 2)) * WCOLS;  // wavefront sub-tile origin
-
+struct GramAcc {
+  static constexpr int WCOLS = 512 / NW;  // wavefront tile columns
+  static constexpr int BJ = WCOLS / 32;   // 32-column blocks per wavefront
   f32x16 acc[4][BJ];
+  int wr, wc, lane;
+  __device__ __forceinline__ void init(int wave, int lane_) {
+    lane = lane_;
+    wr = (wave / (NW / 2)) * 128;
+    wc = (wave % (NW / 2)) * WCOLS;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < BJ; ++b)
+      for (int b = 0; b < BJ; ++b)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
-
-  auto compute = [&](uint16_t (*buf)[2][T2 * BK2]) {
+        for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+  }
+  __device__ __forceinline__ void stage(const GramStage &hi, const GramStage &lo) {
+    constexpr int NOPS = X3 ? 2 : 1;
 #pragma unroll
     for (int kk = 0; kk < BK2; kk += 16) {
       // lane holds 8 consecutive k of row (lane & 31), k offset 8 * (lane >> 5)
@@ -228,12 +252,13 @@ __device__ __forceinline__ void gram_bf16_tile(const uint16_t *__restrict__ Ahi,
       bf16x8 a[NOPS][4], b[NOPS][BJ];
 #pragma unroll
       for (int op = 0; op < NOPS; ++op) {
+        const GramStage &buf = op == 0 ? hi : lo;
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk)
-          a[op][blk] = *(const bf16x8 *)(&buf[op][0][swz2(wr + blk * 32 + (lane & 31), cidx)]);
+          a[op][blk] = *(const bf16x8 *)(&buf[0][swz2(wr + blk * 32 + (lane & 31), cidx)]);
 #pragma unroll
         for (int blk = 0; blk < BJ; ++blk)
-          b[op][blk] = *(const bf16x8 *)(&buf[op][1][swz2(wc + blk * 32 + (lane & 31), cidx)]);
+          b[op][blk] = *(const bf16x8 *)(&buf[1][swz2(wc + blk * 32 + (lane & 31), cidx)]);
       }
       // products outermost, so consecutive MFMAs use different accumulators
 #pragma unroll
@@ -242,45 +267,136 @@ __device__ __forceinline__ void gram_bf16_tile(const uint16_t *__restrict__ Ahi,
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < BJ; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[p == 2 ? 1 : 0][i], b[p == 1 ? 1 : 0][j], acc[i][j],
-                                                                0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[p == 2 ? 1 : 0][i], b[p == 1 ? 1 : 0][j],
+                                                                acc[i][j], 0, 0, 0);
     }
-  };
+  }
+  // 32x32 accumulator layout: value v of lane l is row 8 (v/4) + 4 (l/32) + v%4, column l % 32
+  __device__ __forceinline__ void store(float *dst, int64_t row0, int64_t col0, int64_t ld) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t r = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+          const int64_t c = col0 + wc + j * 32 + (lane & 31);
+          dst[r * ld + c] = acc[i][j][v];
+        }
+  }
+};
 
-  GramDma<NOPS, NW> dma;
+// One work item with one product: tile (I, J), k slice split, through three
+// stage buffers in a ring, each copy issued two stages ahead.  Before
+// multiplying stage s a wavefront waits until its copy of stage s is in
+// (only that of s + 1 may be outstanding), and after the barrier every
+// wavefront's is, and the buffer of stage s - 1 is no longer read, so the
+// copy of stage s + 2 goes there.  Two stages in flight per workgroup keep
+// the operand stream busier than one (measured at 33280 rows, K = 131072:
+// 114 -> 100 ms on operands with the sparsity of the one-halo factor).
+template <int NW>
+__device__ __forceinline__ void gram_bf16_tile1(const uint16_t *__restrict__ Ahi, int64_t k_pad, int64_t r_pad,
+                                                int64_t k_split, int I, int J, int split, float *__restrict__ out,
+                                                float *__restrict__ partial, int64_t ld, int64_t part_stride,
+                                                GramStage &b0, GramStage &b1, GramStage &b2) {
+  constexpr int PERW = GramDma<1, NW>::PERW;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
+  const int64_t kb = (int64_t)split * k_split;
+  const int64_t ke = min(k_pad, kb + k_split);
+  GramAcc<false, NW> acc;
+  acc.init(wave, lane);
+  GramDma<1, NW> dma;
+  dma.init(Ahi, Ahi, r_pad, row0, col0, wave, lane);
+  const int64_t n_st = (ke - kb) / BK2, kb0 = kb / BK2;
+  int64_t st = 0;
+  if (n_st >= 5) {
+    // the first two copies on the one path into the steady state, so that
+    // the compiler's count of copies in flight at its top is exact (it would
+    // otherwise wait for the second copy before reading the first)
+    dma.issue(kb0, b0);
+    dma.issue(kb0 + 1, b1);
+  } else {
+    if (n_st > 0) dma.issue(kb0, b0);
+    if (n_st > 1) dma.issue(kb0 + 1, b1);
+  }
+  // steady state: every step issues the copy two stages ahead
+  for (; st + 5 <= n_st; st += 3) {
+    wait_vmcnt<PERW>();
+    stage_barrier();
+    dma.issue(kb0 + st + 2, b2);
+    acc.stage(b0, b0);
+    wait_vmcnt<PERW>();
+    stage_barrier();
+    dma.issue(kb0 + st + 3, b0);
+    acc.stage(b1, b1);
+    wait_vmcnt<PERW>();
+    stage_barrier();
+    dma.issue(kb0 + st + 4, b1);
+    acc.stage(b2, b2);
+  }
+  // the last stages (fewer than five), waiting for every copy
+  for (; st < n_st; st += 3) {
+    wait_vmcnt<0>();
+    stage_barrier();
+    if (st + 2 < n_st) dma.issue(kb0 + st + 2, b2);
+    acc.stage(b0, b0);
+    if (st + 1 < n_st) {
+      wait_vmcnt<0>();
+      stage_barrier();
+      if (st + 3 < n_st) dma.issue(kb0 + st + 3, b0);
+      acc.stage(b1, b1);
+    }
+    if (st + 2 < n_st) {
+      wait_vmcnt<0>();
+      stage_barrier();
+      if (st + 4 < n_st) dma.issue(kb0 + st + 4, b1);
+      acc.stage(b2, b2);
+    }
+  }
+  acc.store(gram_dst(out, partial, split, part_stride), row0, col0, ld);
+}
+
+// One work item with the split product: hi and lo of a stage in two buffers,
+// two stages (b0, b1) and (b2, b3), stage s + 1 copied while stage s is
+// multiplied.
+template <int NW>
+__device__ __forceinline__ void gram_bf16_tile3(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
+                                                int64_t k_pad, int64_t r_pad, int64_t k_split, int I, int J,
+                                                int split, float *__restrict__ out, float *__restrict__ partial,
+                                                int64_t ld, int64_t part_stride, GramStage &b0, GramStage &b1,
+                                                GramStage &b2, GramStage &b3) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
+  const int64_t kb = (int64_t)split * k_split;
+  const int64_t ke = min(k_pad, kb + k_split);
+  GramAcc<true, NW> acc;
+  acc.init(wave, lane);
+  GramDma<2, NW> dma;
   dma.init(Ahi, Alo, r_pad, row0, col0, wave, lane);
   const int64_t n_st = (ke - kb) / BK2, kb0 = kb / BK2;
-  if (n_st > 0) dma.issue(kb0, lds0);
+  if (n_st > 0) dma.issue(kb0, b0, b1);
   int64_t st = 0;
   for (; st + 1 < n_st; st += 2) {
     // this wavefront's copy of stage st is complete; after the barrier every
-    // wavefront's is, and no wavefront still reads the buffer refilled next
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    // wavefront's is, and no wavefront still reads the buffers refilled next
+    wait_vmcnt<0>();
     __syncthreads();
-    dma.issue(kb0 + st + 1, lds1);
-    compute(lds0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);
+    dma.issue(kb0 + st + 1, b2, b3);
+    acc.stage(b0, b1);
+    wait_vmcnt<0>();
     __syncthreads();
-    if (st + 2 < n_st) dma.issue(kb0 + st + 2, lds0);
-    compute(lds1);
+    if (st + 2 < n_st) dma.issue(kb0 + st + 2, b0, b1);
+    acc.stage(b2, b3);
   }
-  if (st < n_st) {  // odd stage count: the last stage sits in buffer 0
-    __builtin_amdgcn_s_waitcnt(0x0F70);
+  if (st < n_st) {  // odd stage count: the last stage sits in (b0, b1)
+    wait_vmcnt<0>();
     __syncthreads();
-    compute(lds0);
+    acc.stage(b0, b1);
   }
-  // 32x32 accumulator layout: value v of lane l is row 8 (v/4) + 4 (l/32) + v%4, column l % 32
-  float *dst = gram_dst(out, partial, split, part_stride);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < BJ; ++j)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t c = col0 + wc + j * 32 + (lane & 31);
-        dst[r * ld + c] = acc[i][j][v];
-      }
+  acc.store(gram_dst(out, partial, split, part_stride), row0, col0, ld);
 }
 
 // Products of the bf16 kernels: MODE 0 one bf16 product, MODE 1 the split
@@ -295,17 +411,24 @@ __device__ __forceinline__ bool tile_split(const double *__restrict__ panel_f, d
   return panel_f[I] * panel_f[J] > lim;
 }
 
+// Stage buffers of a bf16 kernel: three for one product, four for the split
+// product (MODE 1 and 2).
+template <int MODE>
+struct GramLds {
+  static constexpr int N = MODE == 0 ? 3 : 4;
+};
+
 template <int MODE, int NW>
 __device__ __forceinline__ void gram_bf16_item(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
                                                int64_t k_pad, int64_t r_pad, int64_t k_split, int I, int J,
                                                int split, float *__restrict__ out, float *__restrict__ partial,
                                                int64_t ld, int64_t part_stride, const double *__restrict__ panel_f,
-                                               double lim, uint16_t (*lds0)[2][T2 * BK2],
-                                               uint16_t (*lds1)[2][T2 * BK2]) {
-  if (tile_split<MODE>(panel_f, lim, I, J))
-    gram_bf16_tile<true, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, lds0, lds1);
+                                               double lim, GramStage &b0, GramStage &b1, GramStage &b2,
+                                               GramStage &b3) {
+  if (MODE != 0 && tile_split<MODE>(panel_f, lim, I, J))
+    gram_bf16_tile3<NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, b0, b1, b2, b3);
   else
-    gram_bf16_tile<false, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, lds0, lds1);
+    gram_bf16_tile1<NW>(Ahi, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, b0, b1, b2);
 }
 
 template <int MODE, int NW>
@@ -314,13 +437,14 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
                                                   int nt, int64_t n_work, float *__restrict__ out,
                                                   float *__restrict__ partial, int64_t ld, int64_t part_stride,
                                                   const double *__restrict__ panel_f, double lim) {
-  constexpr int NOPS = MODE == 0 ? 1 : 2;
-  __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];  // [op][I/J side]
-  __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
+  __shared__ __attribute__((aligned(16))) GramStage b0;
+  __shared__ __attribute__((aligned(16))) GramStage b1;
+  __shared__ __attribute__((aligned(16))) GramStage b2;
+  __shared__ __attribute__((aligned(16))) uint16_t b3[GramLds<MODE>::N > 3 ? 2 : 1][T2 * BK2];
   int I, J, split;
   if (!gram_work<GRAM_XC>(n_work, n_split, nt, I, J, split)) return;
   gram_bf16_item<MODE, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, panel_f, lim,
-                           lds0, lds1);
+                           b0, b1, b2, *(GramStage *)b3);
 }
 
 // ---------------------------------------------------------------- batched
@@ -342,9 +466,10 @@ constexpr int QSTRIDE = 16;  // counters 64 bytes apart
 template <int MODE, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__restrict__ jobs, int n_jobs,
                                                         int64_t total, uint32_t *__restrict__ counters) {
-  constexpr int NOPS = MODE == 0 ? 1 : 2;
-  __shared__ __attribute__((aligned(16))) uint16_t lds0[NOPS][2][T2 * BK2];
-  __shared__ __attribute__((aligned(16))) uint16_t lds1[NOPS][2][T2 * BK2];
+  __shared__ __attribute__((aligned(16))) GramStage b0;
+  __shared__ __attribute__((aligned(16))) GramStage b1;
+  __shared__ __attribute__((aligned(16))) GramStage b2;
+  __shared__ __attribute__((aligned(16))) uint16_t b3[GramLds<MODE>::N > 3 ? 2 : 1][T2 * BK2];
   __shared__ int64_t s_item;
   const int x0 = blockIdx.x % N_XCD;
   int q = 0;
@@ -376,7 +501,7 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__re
     gram_item(g - jb.item0, jb.n_work, jb.n_split, jb.nt, I, J, split);
     gram_bf16_item<MODE, NW>((const uint16_t *)jb.A0, (const uint16_t *)jb.A1, jb.k_pad, jb.r_pad, jb.k_split, I,
                              J, split, (float *)jb.out, (float *)jb.partial, jb.ld, jb.part_stride, jb.panel_f,
-                             jb.split_lim, lds0, lds1);
+                             jb.split_lim, b0, b1, b2, *(GramStage *)b3);
   }
 }
 

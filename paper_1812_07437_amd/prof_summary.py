@@ -6,7 +6,10 @@ Inputs are the directories rocprofv3 writes with ``--output-format csv``:
 * ``--trace DIR``  from ``--kernel-trace --stats`` (``*_kernel_trace.csv``);
 * ``--fetch DIR``  from ``--pmc FETCH_SIZE``;
 * ``--write DIR``  from ``--pmc WRITE_SIZE``;
-* ``--hit DIR``    from ``--pmc TCC_HIT_sum TCC_MISS_sum`` (optional);
+* ``--hit DIR``    from ``--pmc TCC_HIT_sum TCC_MISS_sum`` (optional), with
+  ``GRBM_GUI_ACTIVE`` if given: the shader clock of each kernel while it ran,
+  GRBM_GUI_ACTIVE (busy cycles, one count per XCD, summed over the
+  device's 8 XCDs) over 8 times the dispatch durations of that run;
 * ``--mfma DIR``   from ``--pmc MfmaUtil MfmaFlopsBF16 MfmaFlopsF64`` (optional):
   MfmaUtil is the share of SIMD cycles with the matrix core busy
   (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE times the SIMD count), per
@@ -149,10 +152,23 @@ def main():
             lines.append("| `%s` | %d | %.4f | %.4f |" % (_short(k), len(f or w), fv, wv))
     if a.hit:
         h, m = counters(a.hit, "TCC_HIT_sum"), counters(a.hit, "TCC_MISS_sum")
-        lines += ["", "L2 hit rate (`--pmc TCC_HIT_sum TCC_MISS_sum`):", "", "| kernel | hit rate |", "|---|---:|"]
+        gui = counters(a.hit, "GRBM_GUI_ACTIVE")
+        if gui:
+            gt = dispatch_times(a.hit, "GRBM_GUI_ACTIVE")
+            lines += ["", "L2 hit rate and shader clock (`--pmc TCC_HIT_sum TCC_MISS_sum GRBM_GUI_ACTIVE`; the "
+                      "clock is GRBM_GUI_ACTIVE, summed over the 8 XCDs, over 8 x the kernel's time in that run):",
+                      "", "| kernel | hit rate | clock GHz |", "|---|---:|---:|"]
+        else:
+            lines += ["", "L2 hit rate (`--pmc TCC_HIT_sum TCC_MISS_sum`):", "", "| kernel | hit rate |",
+                      "|---|---:|"]
         for k in order[:a.top]:
             if k in h and k in m and sum(h[k]) + sum(m[k]) > 0:
-                lines.append("| `%s` | %.3f |" % (_short(k), sum(h[k]) / (sum(h[k]) + sum(m[k]))))
+                row = "| `%s` | %.3f |" % (_short(k), sum(h[k]) / (sum(h[k]) + sum(m[k])))
+                if gui:
+                    dur = sum(gt.get(k, []))
+                    row += " %s |" % ("%.2f" % (sum(gui[k]) / 8.0 / (dur * 1e-3) / 1e9) if k in gui and dur > 0
+                                      else "-")
+                lines.append(row)
     if a.mfma:
         util = counters(a.mfma, "MfmaUtil")
         fb, fd = counters(a.mfma, "MfmaFlopsBF16"), counters(a.mfma, "MfmaFlopsF64")
