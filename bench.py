@@ -152,7 +152,7 @@ def true_cov(prob, torch):
 
 def precision_report(workload, torch, wl):
     """The Gram precisions at one workload (the Euclid-like shape by
-    default): bf16, split bf16 x 3 and FP32 against the FP64 path on the same
+    default): bf16, split bf16 x 3, the per-tile choice and FP32 against the FP64 path on the same
     tables -- Gram time, its useful-flop and issued-work fractions of peak,
     diagonal max / median relative error, off-diagonal error relative to
     sqrt(C_aa C_bb), and the (S/N)^2 error."""
