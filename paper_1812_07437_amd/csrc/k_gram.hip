@@ -411,13 +411,6 @@ __device__ __forceinline__ bool tile_split(const double *__restrict__ panel_f, d
   return panel_f[I] * panel_f[J] > lim;
 }
 
-// Stage buffers of a bf16 kernel: three for one product, four for the split
-// product (MODE 1 and 2).
-template <int MODE>
-struct GramLds {
-  static constexpr int N = MODE == 0 ? 3 : 4;
-};
-
 template <int MODE, int NW>
 __device__ __forceinline__ void gram_bf16_item(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
                                                int64_t k_pad, int64_t r_pad, int64_t k_split, int I, int J,
@@ -440,11 +433,11 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
   __shared__ __attribute__((aligned(16))) GramStage b0;
   __shared__ __attribute__((aligned(16))) GramStage b1;
   __shared__ __attribute__((aligned(16))) GramStage b2;
-  __shared__ __attribute__((aligned(16))) uint16_t b3[GramLds<MODE>::N > 3 ? 2 : 1][T2 * BK2];
+  __shared__ __attribute__((aligned(16))) GramStage b3;  // split tiles only (unused, and not allocated, in MODE 0)
   int I, J, split;
   if (!gram_work<GRAM_XC>(n_work, n_split, nt, I, J, split)) return;
   gram_bf16_item<MODE, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, panel_f, lim,
-                           b0, b1, b2, *(GramStage *)b3);
+                           b0, b1, b2, b3);
 }
 
 // ---------------------------------------------------------------- batched
@@ -469,7 +462,7 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__re
   __shared__ __attribute__((aligned(16))) GramStage b0;
   __shared__ __attribute__((aligned(16))) GramStage b1;
   __shared__ __attribute__((aligned(16))) GramStage b2;
-  __shared__ __attribute__((aligned(16))) uint16_t b3[GramLds<MODE>::N > 3 ? 2 : 1][T2 * BK2];
+  __shared__ __attribute__((aligned(16))) GramStage b3;  // split tiles only (unused, and not allocated, in MODE 0)
   __shared__ int64_t s_item;
   const int x0 = blockIdx.x % N_XCD;
   int q = 0;
@@ -501,7 +494,7 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__re
     gram_item(g - jb.item0, jb.n_work, jb.n_split, jb.nt, I, J, split);
     gram_bf16_item<MODE, NW>((const uint16_t *)jb.A0, (const uint16_t *)jb.A1, jb.k_pad, jb.r_pad, jb.k_split, I,
                              J, split, (float *)jb.out, (float *)jb.partial, jb.ld, jb.part_stride, jb.panel_f,
-                             jb.split_lim, b0, b1, b2, *(GramStage *)b3);
+                             jb.split_lim, b0, b1, b2, b3);
   }
 }
 
