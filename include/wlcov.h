@@ -322,6 +322,39 @@ int wlc_snr2_structured(wlc_plan plan, const void *ws_run, void *ws, double *snr
  * this plan; synchronises the device for the copy. */
 int wlc_gram_split_tiles(wlc_plan plan, const void *ws_run, int64_t *split, int64_t *tiles);
 
+/* ---- the one-halo Gram product of a caller's factor
+ * The one-halo covariance of the distinct rows is (1/Omega) A A^T over the
+ * flattened (chi, M) axis (eq. General1h with eqs. CovPPNG, Ins5P, Ins6P);
+ * wlc_run builds A from the tables.  wlc_gram runs the same product kernels,
+ * with the same tiles, split-K choice and summation order as wlc_run, on a
+ * factor the caller supplies, and writes the lower triangle of A A^T (the
+ * upper one is its mirror image).
+ *   precision  WLC_BF16 (one product), WLC_BF16X3 (hi hi^T + hi lo^T +
+ *              lo hi^T on every tile) or WLC_BF16_AUTO (per tile, see below);
+ *              FP32 accumulation.
+ *   n, k       rows and columns of A; n_pad = n rounded up to 256,
+ *              k_pad = k rounded up to 64.
+ *   a_hi, a_lo DEVICE, bf16 bit patterns of A (hi) and of its residue (lo)
+ *              in the k-blocked layout: element (r, c) at
+ *              ((c / 32) n_pad + r) 32 + c % 32, n_pad x k_pad elements,
+ *              zero in the padding rows and columns.  a_lo is read by
+ *              WLC_BF16X3 and WLC_BF16_AUTO (required there), ignored by
+ *              WLC_BF16 (may be NULL).
+ *   panel_f    WLC_BF16_AUTO: DEVICE, n_pad / 256 doubles F_I; the 256 x 256
+ *              tile (I, J) takes the split product iff F_I F_J > lim, one
+ *              product otherwise.  Ignored (may be NULL) for the others.
+ *   g          DEVICE, FP32 [n_pad][n_pad], row-major: every entry (i, j)
+ *              with i >= j is written; above the diagonal, the diagonal
+ *              256 x 256 tiles hold partial or whole sums and the other tiles
+ *              are left as they are.
+ *   ws         DEVICE workspace of wlc_gram_ws_bytes bytes (the split-K
+ *              partial products), 256-byte aligned; may be NULL when that is 0.
+ * Asynchronous on stream.  WLC_EINVAL for another precision, n or k < 1 or
+ * too large, a missing pointer or an unaligned workspace. */
+int wlc_gram_ws_bytes(int precision, int64_t n, int64_t k, size_t *bytes);
+int wlc_gram(int precision, int64_t n, int64_t k, const uint16_t *a_hi, const uint16_t *a_lo,
+             const double *panel_f, double lim, float *g, void *ws, void *stream);
+
 /* ---- phase timing (per-plan HIP events; not for plans shared by concurrent runs)
  * With timing enabled, wlc_run and wlc_snr2 record a HIP event pair on their
  * stream around each phase; wlc_plan_timings synchronises on them and writes

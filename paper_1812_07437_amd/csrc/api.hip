@@ -834,6 +834,43 @@ int wlc_gram_split_tiles(wlc_plan plan, const void *ws_run, int64_t *split, int6
   return WLC_OK;
 }
 
+// ---- the Gram product of a caller's factor (the kernels of wlc_run's one-halo term)
+static int gram_shape_of(int precision, int64_t n, int64_t k, GramShape &g) {
+  if (precision != WLC_BF16 && precision != WLC_BF16X3 && precision != WLC_BF16_AUTO)
+    return fail(WLC_EINVAL, "wlc_gram: precision must be WLC_BF16, WLC_BF16X3 or WLC_BF16_AUTO");
+  // the tile count and work items stay within the launch and int ranges
+  if (n < 1 || k < 1 || n > ((int64_t)1 << 20) || k > ((int64_t)1 << 30))
+    return fail(WLC_EINVAL, "wlc_gram: n or k out of range");
+  const int64_t n_pad = round_up(n, GRAM_TILE), k_pad = round_up(k, 64);
+  g = GramShape{n_pad, k_pad, n_pad, k_pad};
+  return WLC_OK;
+}
+
+int wlc_gram_ws_bytes(int precision, int64_t n, int64_t k, size_t *bytes) {
+  if (!bytes) return fail(WLC_EINVAL, "null argument");
+  GramShape g;
+  const int rc = gram_shape_of(precision, n, k, g);
+  if (rc) return rc;
+  *bytes = gram_partial_bytes(precision, g);
+  return WLC_OK;
+}
+
+int wlc_gram(int precision, int64_t n, int64_t k, const uint16_t *a_hi, const uint16_t *a_lo,
+             const double *panel_f, double lim, float *g, void *ws, void *stream) {
+  GramShape sh;
+  int rc = gram_shape_of(precision, n, k, sh);
+  if (rc) return rc;
+  if (!a_hi || !g) return fail(WLC_EINVAL, "wlc_gram: null A or G");
+  if (precision != WLC_BF16 && !a_lo) return fail(WLC_EINVAL, "wlc_gram: the split products need a_lo");
+  if (precision == WLC_BF16_AUTO && !panel_f) return fail(WLC_EINVAL, "wlc_gram: WLC_BF16_AUTO needs panel_f");
+  const size_t part = gram_partial_bytes(precision, sh);
+  if (part > 0 && !ws) return fail(WLC_EINVAL, "wlc_gram: null workspace");
+  if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "wlc_gram: workspace must be 256-byte aligned");
+  launch_gram(precision, sh, a_hi, precision == WLC_BF16 ? a_hi : a_lo, g, ws, (hipStream_t)stream,
+              precision == WLC_BF16_AUTO ? panel_f : nullptr, precision == WLC_BF16_AUTO ? lim : 0.0);
+  return hip_check(hipGetLastError(), "wlc_gram launch");
+}
+
 int wlc_snr2_noalloc(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, double *snr2_dev,
                      int32_t *status_dev, void *stream) {
   if (!plan || !C || !row_exp2 || !d || !snr2_dev || !status_dev) return fail(WLC_EINVAL, "null argument");

@@ -25,6 +25,11 @@ PRECISIONS = {"fp64": WLC_FP64, "bf16": WLC_BF16, "bf16x3": WLC_BF16X3, "fp32": 
               "fp64_chi": WLC_FP64_CHI, "bf16_auto": WLC_BF16_AUTO}
 
 
+def _prec(precision):
+    """A precision code from its name or the code itself."""
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
 class WlcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("wlcov error %d: %s" % (code, msg))
@@ -87,6 +92,8 @@ def _load():
     L.wlc_snr2_lmax.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wlc_snr2_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wlc_gram_split_tiles.argtypes = [vp, vp, vp, vp]
+    L.wlc_gram_ws_bytes.argtypes = [ct.c_int, ct.c_int64, ct.c_int64, vp]
+    L.wlc_gram.argtypes = [ct.c_int, ct.c_int64, ct.c_int64, vp, vp, vp, ct.c_double, vp, vp, vp]
     L.wlc_pca.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
     L.wlc_plan_timings.argtypes = [vp, vp]
@@ -98,7 +105,7 @@ lib = _load()
 
 EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_averaging",
             "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_noalloc", "wlc_gram_split_tiles", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_noalloc", "wlc_gram_split_tiles", "wlc_gram_ws_bytes", "wlc_gram", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
@@ -186,6 +193,19 @@ def wlc_gram_split_tiles(plan, ws_run):
     a, b = ct.c_int64(), ct.c_int64()
     _check(lib.wlc_gram_split_tiles(plan, ws_run, ct.byref(a), ct.byref(b)))
     return a.value, b.value
+
+
+def wlc_gram_ws_bytes(precision, n, k):
+    """Workspace bytes of wlc_gram (the split-K partial products)."""
+    b = ct.c_size_t()
+    _check(lib.wlc_gram_ws_bytes(_prec(precision), int(n), int(k), ct.byref(b)))
+    return b.value
+
+
+def wlc_gram(precision, n, k, a_hi, a_lo, panel_f, lim, g, ws, stream):
+    """Enqueue the lower 256-tiles of A A^T (FP32, DEVICE g [n_pad][n_pad]) of a
+    k-blocked bf16 factor (DEVICE a_hi, a_lo; see include/wlcov.h)."""
+    _check(lib.wlc_gram(_prec(precision), int(n), int(k), a_hi, a_lo, panel_f, float(lim), g, ws, stream))
 
 
 def wlc_snr2_lmax(plan, C, row_exp2, d, ws, stream, n_ell):

@@ -209,3 +209,27 @@ def test_averaging_arguments():
         with pytest.raises(w.WlcError) as e:
             w.wlc_plan_create(w.make_config(t, "fp64", **bad))
         assert e.value.code == w.WLC_EINVAL
+
+
+def test_gram_arguments_rejected():
+    """wlc_gram checks its arguments before anything touches the device (the
+    pointers below are never dereferenced: every case fails a check first)."""
+    assert w.wlc_gram_ws_bytes("bf16", 256, 64) == 0
+    assert w.wlc_gram_ws_bytes("bf16", 33165, 131072) == 33280 * 33280 * 4  # two k-slices
+    fake = 4096  # a non-null, 256-byte-aligned stand-in
+    bad = [
+        dict(precision="fp64"), dict(precision="fp32"), dict(n=0), dict(k=0), dict(n=(1 << 20) + 1),
+        dict(a_hi=None), dict(g=None),
+        dict(precision="bf16x3", a_lo=None), dict(precision="bf16_auto", a_lo=None),
+        dict(precision="bf16_auto", panel_f=None),
+        dict(n=256, k=4096, ws=None), dict(n=256, k=4096, ws=fake + 1),
+    ]
+    for b in bad:
+        a = dict(precision="bf16", n=256, k=4096, a_hi=fake, a_lo=fake, panel_f=fake, lim=0.5, g=fake, ws=fake)
+        a.update(b)
+        with pytest.raises(w.WlcError) as e:
+            w.wlc_gram(a["precision"], a["n"], a["k"], a["a_hi"], a["a_lo"], a["panel_f"], a["lim"], a["g"], a["ws"],
+                       None)
+        assert e.value.code == w.WLC_EINVAL, b
+    with pytest.raises(w.WlcError):
+        w.wlc_gram_ws_bytes("bf16", 0, 64)

@@ -1,0 +1,129 @@
+"""The one-halo Gram kernels (eq. General1h: the one-halo covariance of the
+distinct rows is A A^T / Omega over the flattened (chi, M) axis) on integer
+factors, through wlc_gram.  With |hi| <= 8, |lo| <= 4 every bf16 operand,
+every product and every FP32 partial sum is an exact integer below 2^24, so
+whatever the summation order the result must equal the integer product bit
+for bit: hi hi^T for one product, hi hi^T + hi lo^T + lo hi^T for the split
+product (lo lo^T dropped).
+
+The shapes cover one and several 256-row tiles, padding rows and columns, and
+split-K slices whose stage counts (32 columns each) take every residue mod 3
+of the one-product ring (three stage buffers) as well as slices too short for
+its steady state."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+# (n, k): stage counts per slice, with the split-K choice of the library
+# (two k-slices at least on long products, at most 32, at least 4 stages each)
+CASES = [
+    (256, 64),      # one tile, one slice of 2 stages
+    (256, 2048),    # one tile, 16 slices of 4 stages
+    (200, 4000),    # padding rows and columns (k_pad 4032): slices of 5 stages and one of 1
+    (1280, 32768),  # 15 tiles, 32 slices of 32 stages (32 = 2 mod 3)
+    (1280, 33024),  # 31 slices of 33 stages (0 mod 3) and one of 9
+    (1100, 34816),  # padding rows, slices of 34 stages (1 mod 3)
+]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _bf16_bits(x):
+    """bf16 bit patterns of small integers (exact)."""
+    return (np.asarray(x, np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def _kblocked(bits, n_pad, k_pad):
+    """The k-blocked layout: element (r, c) at ((c / 32) n_pad + r) 32 + c % 32."""
+    n, k = bits.shape
+    full = np.zeros((n_pad, k_pad), np.uint16)
+    full[:n, :k] = bits
+    return np.ascontiguousarray(full.reshape(n_pad, k_pad // 32, 32).transpose(1, 0, 2)).reshape(-1)
+
+
+@pytest.fixture(scope="module")
+def wl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_07437_amd import wlcov
+    return wlcov
+
+
+@pytest.fixture(scope="module", params=CASES, ids=["n%d_k%d" % c for c in CASES])
+def case(request, wl):
+    n, k = request.param
+    rng = np.random.default_rng(20191218 + n + k)
+    hi = rng.integers(-8, 9, size=(n, k)).astype(np.float64)
+    lo = rng.integers(-4, 5, size=(n, k)).astype(np.float64)
+    n_pad, k_pad = -(-n // 256) * 256, -(-k // 64) * 64
+    dev = torch.device("cuda:0")
+    a_hi = torch.from_numpy(_kblocked(_bf16_bits(hi), n_pad, k_pad).view(np.int16)).to(dev)
+    a_lo = torch.from_numpy(_kblocked(_bf16_bits(lo), n_pad, k_pad).view(np.int16)).to(dev)
+    hh = np.zeros((n_pad, n_pad))
+    hl = np.zeros((n_pad, n_pad))
+    hh[:n, :n] = hi @ hi.T  # integers below 2^53: exact in float64 whatever the order
+    hl[:n, :n] = hi @ lo.T
+    return dict(n=n, k=k, n_pad=n_pad, a_hi=a_hi, a_lo=a_lo, hh=hh, split=hh + hl + hl.T)
+
+
+def _run(wl, c, precision, panel_f=None, lim=0.0):
+    n, k, n_pad = c["n"], c["k"], c["n_pad"]
+    dev = torch.device("cuda:0")
+    ws_b = wl.wlc_gram_ws_bytes(precision, n, k)
+    ws = torch.empty(max(ws_b, 256), dtype=torch.uint8, device=dev)
+    g = torch.full((n_pad, n_pad), float("nan"), dtype=torch.float32, device=dev)
+    pf = None if panel_f is None else torch.as_tensor(panel_f, dtype=torch.float64).to(dev)
+    stream = torch.cuda.current_stream()
+    _say("case gram exact n=%d k=%d %s" % (n, k, precision))
+    wl.wlc_gram(precision, n, k, wl._ptr(c["a_hi"]), wl._ptr(c["a_lo"]), wl._ptr(pf) if pf is not None else None,
+                lim, wl._ptr(g), wl._ptr(ws), wl._stream_handle(stream))
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64)
+
+
+def _check_tiles(G, want_of_tile, n_pad):
+    """Every entry i >= j of every 256-tile I >= J (above the diagonal of a
+    diagonal tile the split-K slices are not summed)."""
+    nt = n_pad // 256
+    low = np.tril(np.ones((256, 256), bool))
+    for I in range(nt):
+        for J in range(I + 1):
+            s = np.s_[256 * I:256 * I + 256, 256 * J:256 * J + 256]
+            got, want = G[s], want_of_tile(I, J)[s]
+            if I == J:
+                got, want = got[low], want[low]
+            assert np.array_equal(got, want), (I, J, float(np.max(np.abs(got - want))))
+
+
+def test_one_product_exact(wl, case):
+    G = _run(wl, case, "bf16")
+    _check_tiles(G, lambda I, J: case["hh"], case["n_pad"])
+
+
+def test_split_product_exact(wl, case):
+    G = _run(wl, case, "bf16x3")
+    _check_tiles(G, lambda I, J: case["split"], case["n_pad"])
+
+
+def test_per_tile_choice_exact(wl, case):
+    """Panels alternate between F = 0.1 and F = 1 with the limit 0.5: the
+    tiles between two odd panels take the split product, the others one."""
+    nt = case["n_pad"] // 256
+    F = np.array([1.0 if I % 2 else 0.1 for I in range(nt)])
+    G = _run(wl, case, "bf16_auto", panel_f=F, lim=0.5)
+    _check_tiles(G, lambda I, J: case["split"] if F[I] * F[J] > 0.5 else case["hh"], case["n_pad"])
+
+
+def test_upper_tiles_untouched(wl, case):
+    """Only the tiles I >= J are written."""
+    if case["n_pad"] == 256:
+        pytest.skip("one tile")
+    G = _run(wl, case, "bf16")
+    assert np.isnan(G[0:256, 256:512]).all()
