@@ -14,7 +14,8 @@
 // Work decomposition: a workgroup owns one output tile (I >= J) of the lower
 // triangle and one contiguous slice of K: 256 x 256 for the bf16 variants
 // (8 wavefronts), 128 x 128 for f32 / f64 (4 wavefronts, 2 x 2).  The bf16
-// operands are copied from global memory straight into LDS one stage ahead;
+// operands are copied from global memory straight into LDS ahead of their
+// products (two stages ahead for one product, one for the split product);
 // the f32 / f64 ones are staged through registers, the next slice prefetched.
 // Slices of K (split-K) are reduced in a fixed order by a second kernel, so
 // results are deterministic.  A 256-row tile halves the operand bytes per
@@ -133,7 +134,7 @@ __device__ __forceinline__ T *gram_dst(T *out, T *partial, int split, int64_t pa
 // 256 x 256 output tile per workgroup of NW wavefronts on a 2 x (NW/2) grid:
 // NW = 8 gives 128 x 64 per wavefront (4 x 2 blocks of
 // v_mfma_f32_32x32x16_bf16, two wavefronts per SIMD).  K advances in stages
-// of 32 through two LDS buffers ([256 rows][32 bf16] = 64 B per row, operand
+// of 32 through LDS stage buffers ([256 rows][32 bf16] = 64 B per row, operand
 // and side).  Chunk c (16 B) of row r sits at slot c ^ (((r >> 1) ^ (r >> 3))
 // & 3): the 16 consecutive rows that one MFMA operand read touches at a time
 // then fall on 16 distinct 16-byte bank groups (and any 8 consecutive rows on
@@ -145,10 +146,8 @@ __device__ __forceinline__ T *gram_dst(T *out, T *partial, int split, int64_t pa
 // a 256-row panel is a contiguous 16 KB block, and each 1 KB wavefront copy
 // (16 rows) covers whole cache lines.  Lane l fills LDS slot l & 3 of row
 // l >> 2 and fetches the chunk that the swizzle puts there (the swizzle is an
-// XOR, its own inverse).  Stage s + 1 is copied while stage s is multiplied;
-// the two buffers are distinct arrays and the loop is unrolled by two, so the
-// compiler can tell the buffer being filled from the one being read and does
-// not wait for the copy before reading.
+// XOR, its own inverse).  How many stages are in flight is the business of
+// the tile bodies below (gram_bf16_tile1, gram_bf16_tile3).
 constexpr int T2 = 256;
 constexpr int BK2 = 32;
 static_assert(BK2 == GRAM_KB, "a Gram stage is one k-block of A");
