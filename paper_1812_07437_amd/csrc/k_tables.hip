@@ -527,6 +527,9 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
 // one chi node; otherwise the values are taken one by one.
 constexpr int AB_KB = 32;
 constexpr int AB_RW = 4;
+// chi nodes of T a workgroup stages in LDS: its AB_KB k-blocks span
+// AB_KB 32 / N_M + 1 nodes at most (33 for N_M >= 32); more go to global memory
+constexpr int AB_TN = 40;
 
 // Two floats to packed bf16, rounded to nearest even (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint32_t pack_bf16_rne(float a, float b) {
@@ -540,7 +543,7 @@ __device__ __forceinline__ uint32_t pack_bf16_rne(float a, float b) {
 // panel is written only if some tile of its row or column can take the split
 // product, F_P F_max > lim; the product never reads it otherwise.
 template <int FMT>
-__global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_abuild_blk(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
                                                    const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
                                                    int64_t k_pad, int64_t r_pad, uint16_t *__restrict__ A0,
                                                    uint16_t *__restrict__ A1, const double *__restrict__ panel_f,
@@ -559,6 +562,23 @@ __global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ 
     const int64_t row = row0 + 16 * j;
     cfg[j] = row < n_R ? rowR[4 * row] : -1;
     Tr[j] = Ts + (size_t)(row < n_R ? row : 0) * n_chi;
+  }
+  // T of the workgroup's 64 rows at the chi nodes of its k range, staged in
+  // LDS with coalesced loads (a lane would otherwise gather T of its rows
+  // from 16 rows n_chi apart at every node change)
+  __shared__ double Tl[64][AB_TN + 1];
+  const int64_t kbeg = (int64_t)blockIdx.x * AB_KB * GRAM_KB;
+  const int n_lo = kbeg < k_len ? (int)(kbeg / n_m) : 0;
+  const int n_hi = kbeg < k_len ? (int)((min(kbeg + AB_KB * GRAM_KB, k_len) - 1) / n_m) : 0;
+  const int nodes = n_hi - n_lo + 1;
+  const bool staged = whole && kbeg < k_len && nodes <= AB_TN;  // workgroup-uniform
+  if (staged) {
+    for (int idx = threadIdx.x; idx < 64 * nodes; idx += 256) {
+      const int r = idx / nodes, q = idx % nodes;
+      const int64_t row = (int64_t)blockIdx.y * 64 + r;
+      Tl[r][q] = row < n_R ? Ts[row * n_chi + n_lo + q] : 0.0;
+    }
+    __syncthreads();
   }
   int node[AB_RW];
   double tn[AB_RW];
@@ -588,7 +608,7 @@ __global__ __launch_bounds__(256) void k_abuild_blk(const int32_t *__restrict__ 
         }
         if (node[j] != n) {
           node[j] = n;
-          tn[j] = Tr[j][n];
+          tn[j] = staged ? Tl[(lane >> 2) + 16 * j][n - n_lo] : Tr[j][n];
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = (float)(tn[j] * g[e]);
