@@ -522,14 +522,21 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
 // 8 consecutive k (chunk l % 4) of the rows l / 4 + 16 j, j < AB_RW, so that
 // each of its stores writes 16 whole rows of the k-block, 1 KB contiguous.
 // Consecutive distinct rows mostly share their configuration, so a lane's
-// 8 values of G are loaded once for its rows of one configuration, and T
-// once per row and chi node.  When N_M is a multiple of 8 a chunk lies in
-// one chi node; otherwise the values are taken one by one.
+// 8 values of G serve all its rows of one configuration, and T is taken once
+// per row and chi node.  When N_M is a multiple of 8 a chunk lies in one chi
+// node, and T of the workgroup's rows and G of its configurations (at most
+// AB_GC of them) are staged in LDS with coalesced loads; otherwise the values
+// are taken one by one from global memory.
 constexpr int AB_KB = 32;
 constexpr int AB_RW = 4;
 // chi nodes of T a workgroup stages in LDS: its AB_KB k-blocks span
 // AB_KB 32 / N_M + 1 nodes at most (33 for N_M >= 32); more go to global memory
 constexpr int AB_TN = 40;
+// configurations whose G a workgroup stages in LDS, pass by pass (a pass is
+// the four k-blocks the wavefronts convert together): 64 consecutive
+// distinct rows span at most three when a configuration holds 55 rows or
+// more (n_z >= 10); smaller ones take the global path
+constexpr int AB_GC = 3;
 
 // Two floats to packed bf16, rounded to nearest even (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint32_t pack_bf16_rne(float a, float b) {
@@ -543,7 +550,7 @@ __device__ __forceinline__ uint32_t pack_bf16_rne(float a, float b) {
 // panel is written only if some tile of its row or column can take the split
 // product, F_P F_max > lim; the product never reads it otherwise.
 template <int FMT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_abuild_blk(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FMT == 1 ? 5 : 4))) void k_abuild_blk(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
                                                    const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
                                                    int64_t k_pad, int64_t r_pad, uint16_t *__restrict__ A0,
                                                    uint16_t *__restrict__ A1, const double *__restrict__ panel_f,
@@ -580,13 +587,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     }
     __syncthreads();
   }
+  // G of the workgroup's configurations for the four k-blocks of a pass, in
+  // two alternating buffers: the barrier after filling one for pass p also
+  // ends every wavefront's reads of pass p - 1, whose buffer pass p + 1 fills
+  __shared__ double Gl[2][AB_GC][4 * GRAM_KB];
+  const int64_t rfirst = (int64_t)blockIdx.y * 64, rlast = min(rfirst + 63, n_R - 1);
+  const int c_first = rfirst < n_R ? rowR[4 * rfirst] : 0;
+  const int c_last = rfirst < n_R ? rowR[4 * rlast] : 0;
+  const bool gstaged = staged && rfirst < n_R && c_last - c_first < AB_GC;  // workgroup-uniform
+  const int n_kb = (int)min((int64_t)AB_KB, k_pad / GRAM_KB - (int64_t)blockIdx.x * AB_KB);
   int node[AB_RW];
   double tn[AB_RW];
 #pragma unroll
   for (int j = 0; j < AB_RW; ++j) node[j] = -1, tn[j] = 0.0;
-  for (int q = wave; q < AB_KB; q += 4) {
+  for (int pass = 0; pass < (n_kb + 3) / 4; ++pass) {
+    const int q = 4 * pass + wave;
+    if (gstaged) {
+      const int64_t kp = kbeg + (int64_t)pass * 4 * GRAM_KB;
+      for (int idx = threadIdx.x; idx < AB_GC * 2 * GRAM_KB; idx += 256) {
+        const int ci = idx / (2 * GRAM_KB), e = 2 * (idx % (2 * GRAM_KB));
+        const int64_t k = kp + e;  // even, and k_len is a multiple of 8: k + 1 < k_len with k
+        double2 v = make_double2(0.0, 0.0);
+        if (ci <= c_last - c_first && k < k_len) v = *(const double2 *)(G + (size_t)(c_first + ci) * k_len + k);
+        *(double2 *)&Gl[pass & 1][ci][e] = v;
+      }
+      __syncthreads();
+    }
+    if (q >= n_kb) continue;  // past k_pad (later passes' barriers still to come: no break)
     const int64_t kblk = (int64_t)blockIdx.x * AB_KB + q;
-    if (kblk * GRAM_KB >= k_pad) break;
     const int64_t k0 = kblk * GRAM_KB + 8 * chunk;
     const int n = k0 < k_len ? (int)(k0 / n_m) : 0;
     double g[8];
@@ -597,12 +625,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       float x[8];
       if (whole && cfg[j] >= 0 && k0 < k_len) {
         if (cfg[j] != gc) {
-          const double *Gc = G + (size_t)cfg[j] * k_len + k0;
+          if (gstaged) {
+            const double *Gs = &Gl[pass & 1][cfg[j] - c_first][wave * GRAM_KB + 8 * chunk];
 #pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            const double2 t = *(const double2 *)(Gc + e);
-            g[e] = t.x;
-            g[e + 1] = t.y;
+            for (int e = 0; e < 8; ++e) g[e] = Gs[e];
+          } else {
+            const double *Gc = G + (size_t)cfg[j] * k_len + k0;
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+              const double2 t = *(const double2 *)(Gc + e);
+              g[e] = t.x;
+              g[e + 1] = t.y;
+            }
           }
           gc = cfg[j];
         }
