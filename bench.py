@@ -99,29 +99,27 @@ def measured_traffic(*names, per=None):
 
 
 def gram_flops(n_r, k_len):
-    """Useful flops of the one-halo Gram: each of the n_r (n_r + 1)/2 distinct
-    entries is a length-K dot product (2K flops), whatever the precision."""
+    """Flops of the flattened one-halo Gram: each of the n_r (n_r + 1)/2
+    distinct entries as a length-K dot product (2K flops)."""
     return n_r * (n_r + 1) * k_len
 
 
-def gram_mfma_work(n_r, k_len, precision):
-    """Flops the matrix cores issue for the same entries: the split bf16
-    product does three products (hi hi, hi lo, lo hi) per entry."""
-    return gram_flops(n_r, k_len) * (3 if precision == "bf16x3" else 1)
-
-
-def gram_figures(ms, n_r, k_len, precision, split=None):
-    """Gram rate on useful flops and, separately, on issued MFMA work, each
-    against the peak of the precision's matrix-core type.  split = (tiles
-    with the split product, tiles) for the per-tile precision."""
-    useful = gram_flops(n_r, k_len) / (ms * 1e-3) / 1e12
-    if precision == "bf16_auto" and split:
-        work = useful * (1.0 + 2.0 * split[0] / max(split[1], 1))
-    else:
-        work = gram_mfma_work(n_r, k_len, precision) / (ms * 1e-3) / 1e12
+def gram_figures(ms, n_r, k_len, precision, work, split=None):
+    """Gram rates against the peak of the precision's matrix-core type.
+    work = (flops, MFMA flops) the product did (wlc_gram_work: the bf16
+    products sum each tile only up to the column where the shorter of its two
+    panels' factors ends, the split tiles count three times in the second).
+    dense_equivalent_tflops: the flattened product's flops N_R (N_R + 1) K
+    over the time, i.e. as if every column were summed (it can exceed the
+    peak); executed_tflops and mfma_work_tflops: the flops done.  split =
+    (tiles with the split product, tiles) for the per-tile precision."""
+    t = ms * 1e-3
+    dense = gram_flops(n_r, k_len) / t / 1e12
+    executed, mfma = work[0] / t / 1e12, work[1] / t / 1e12
     peak = PEAK_TFLOPS[precision]
-    out = dict(ms=ms, useful_tflops=useful, frac_peak_useful=useful / peak, mfma_work_tflops=work,
-               frac_peak_mfma_work=work / peak, peak_tflops=peak)
+    out = dict(ms=ms, dense_equivalent_tflops=dense, executed_tflops=executed, frac_peak_executed=executed / peak,
+               mfma_work_tflops=mfma, frac_peak_mfma_work=mfma / peak, peak_tflops=peak,
+               executed_fraction_of_dense=work[0] / max(gram_flops(n_r, k_len), 1.0))
     if split:
         out["split_tiles"], out["tiles"] = split
     return out
@@ -153,7 +151,7 @@ def true_cov(prob, torch):
 def precision_report(workload, torch, wl):
     """The Gram precisions at one workload (the Euclid-like shape by
     default): bf16, split bf16 x 3, the per-tile choice and FP32 against the FP64 path on the same
-    tables -- Gram time, its useful-flop and issued-work fractions of peak,
+    tables -- Gram time, its rate on the flops done against peak, its dense-equivalent rate,
     diagonal max / median relative error, off-diagonal error relative to
     sqrt(C_aa C_bb), and the (S/N)^2 error."""
     import synth
@@ -166,7 +164,7 @@ def precision_report(workload, torch, wl):
     snr64 = p64.snr2()
     C64 = true_cov(p64, torch)
     d64 = torch.diagonal(C64).clone()
-    out["fp64"] = dict(gram=gram_figures(ph["gram"], NR, K, "fp64"), snr2=snr64)
+    out["fp64"] = dict(gram=gram_figures(ph["gram"], NR, K, "fp64", p64.gram_work()), snr2=snr64)
     del p64
     scale = torch.sqrt(torch.outer(d64, d64))
     for prec in ("bf16", "bf16x3", "bf16_auto", "fp32"):
@@ -179,11 +177,12 @@ def precision_report(workload, torch, wl):
         ed = torch.abs(dm - d64) / d64
         off = torch.abs(Cm - C64) / scale
         off.fill_diagonal_(0.0)
-        out[prec] = dict(gram=gram_figures(ph["gram"], NR, K, prec, split), diag_max_rel=float(ed.max()),
+        out[prec] = dict(gram=gram_figures(ph["gram"], NR, K, prec, pm.gram_work(), split),
+                         diag_max_rel=float(ed.max()),
                          diag_median_rel=float(ed.median()), offdiag_max_rel_sqrt_caa_cbb=float(off.max()),
                          snr2_rel=abs(snr - snr64) / snr64)
-        log("precision %s %s: gram %.3f ms (useful %.1f %% of peak), diag max %.2e median %.2e, off %.2e, "
-            "snr %.2e" % (workload, prec, ph["gram"], 100 * out[prec]["gram"]["frac_peak_useful"],
+        log("precision %s %s: gram %.3f ms (%.1f %% of peak on the flops done), diag max %.2e median %.2e, "
+            "off %.2e, snr %.2e" % (workload, prec, ph["gram"], 100 * out[prec]["gram"]["frac_peak_mfma_work"],
                           out[prec]["diag_max_rel"], out[prec]["diag_median_rel"],
                           out[prec]["offdiag_max_rel_sqrt_caa_cbb"], out[prec]["snr2_rel"]))
         del pm, Cm, off
@@ -201,11 +200,12 @@ def gram_variants(cfg, arrays, torch, wl, precisions):
         p = wl.Problem(cfg, arrays, precision=prec, device="cuda:0")
         s = p.sizes
         ph = timed_runs(p, 1, 1, torch, wl)
-        out[prec] = gram_figures(ph["gram"], s.n_distinct, s.k_len, prec,
+        out[prec] = gram_figures(ph["gram"], s.n_distinct, s.k_len, prec, p.gram_work(),
                                  p.split_tiles() if prec == "bf16_auto" else None)
         out[prec]["run_ms"] = sum(ph[k] for k in ("tables", "abuild", "gram", "assemble"))
-        log("gram %s: %.1f ms, useful %.1f TFLOP/s (%.1f %% of its peak)" % (
-            prec, ph["gram"], out[prec]["useful_tflops"], 100 * out[prec]["frac_peak_useful"]))
+        log("gram %s: %.1f ms, %.1f TFLOP/s of MFMA work (%.1f %% of its peak), dense-equivalent %.1f TFLOP/s" % (
+            prec, ph["gram"], out[prec]["mfma_work_tflops"], 100 * out[prec]["frac_peak_mfma_work"],
+            out[prec]["dense_equivalent_tflops"]))
         del p
         torch.cuda.empty_cache()
     return out
@@ -502,6 +502,7 @@ def main():
     log("mixed: %.1f ms/step  phases %s  snr2 %.6e" % (ms_step, {k: round(v, 2) for k, v in ph.items()}, snrs[-1]))
 
     split_main = prob.split_tiles() if args.precision == "bf16_auto" else None
+    work_main = prob.gram_work()
     d_mixed = prob.C.diagonal().double().cpu().numpy()
     t_mixed = prob.row_exp2.cpu().numpy().astype(np.int64)
     diag_mixed = np.ldexp(d_mixed, -2 * t_mixed)
@@ -515,6 +516,7 @@ def main():
         log("fp64 path")
         p64 = wl.Problem(cfg, t.arrays(), precision="fp64", device="cuda:0")
         dt64, ph64, snr64, _ = timed_steps(p64, args.fp64_steps, 1, torch, wl)
+        work64 = p64.gram_work()
         d64 = p64.C.diagonal().cpu().numpy()
         t64 = p64.row_exp2.cpu().numpy().astype(np.int64)
         diag64 = np.ldexp(d64, -2 * t64)
@@ -523,7 +525,7 @@ def main():
         fp64 = dict(ms_per_step=dt64 / args.fp64_steps * 1e3, value=entries / (dt64 / args.fp64_steps),
                     phases_ms=ph64, speedup_step=(dt64 / args.fp64_steps) / (dt / args.steps),
                     speedup_gram=ph64["gram"] / max(ph["gram"], 1e-9),
-                    gram=gram_figures(ph64["gram"], NR, K, "fp64"),
+                    gram=gram_figures(ph64["gram"], NR, K, "fp64", work64),
                     err_vs_fp64={"diag_max_rel": err_diag, "snr2_rel": err_snr})
         log("fp64: %.1f ms/step  gram %.1f ms  diag err %.2e  snr err %.2e" % (fp64["ms_per_step"], ph64["gram"],
                                                                            err_diag, err_snr))
@@ -622,7 +624,7 @@ def main():
     # roofline of the dominant kernel of the step: the one-halo Gram (one
     # launch per step) or the Cholesky block update (many launches per step,
     # timed one by one with HIP events on the run's stream)
-    gram_fig = gram_figures(ph["gram"], NR, K, args.precision, split_main)
+    gram_fig = gram_figures(ph["gram"], NR, K, args.precision, work_main, split_main)
     chol_flops = N ** 3 / 3.0
     chol_tf = chol_flops / (ph["chol"] * 1e-3) / 1e12
     upd_frac_timed = upd["timed"] / max(upd["launches"], 1)
@@ -639,16 +641,15 @@ def main():
                     avg_launch_ms=upd_ms / max(upd["launches"], 1), flops_per_step=upd["flops"])
     else:
         tr = measured_traffic("k_gram_bf16")
-        roof = dict(bound="mfma", kernel="k_gram_bf16 (one-halo Gram, useful flops)",
-                    achieved=gram_fig["useful_tflops"], peak=PEAK_TFLOPS[args.precision], unit="TFLOP/s",
-                    frac=gram_fig["frac_peak_useful"], traffic=tr["bytes_per_launch"] / 1e9 if tr else None,
-                    launches=1, avg_launch_ms=ph["gram"], flops_per_step=gram_flops(NR, K))
+        roof = dict(bound="mfma", kernel="k_gram_bf16 (one-halo Gram, MFMA flops done)",
+                    achieved=gram_fig["mfma_work_tflops"], peak=PEAK_TFLOPS[args.precision], unit="TFLOP/s",
+                    frac=gram_fig["frac_peak_mfma_work"], traffic=tr["bytes_per_launch"] / 1e9 if tr else None,
+                    launches=1, avg_launch_ms=ph["gram"], flops_per_step=work_main[1])
     roof["traffic_unit"] = "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["traffic_source"] = tr["summary"] if tr else None
-    # the per-tile mode writes the lo half only for panels that can take the
-    # split product: none when no tile does, else at most every panel
-    auto_bytes = 2 if split_main is not None and split_main[0] == 0 else 4
-    a_bytes = NR * K * {"bf16": 2, "bf16x3": 4, "bf16_auto": auto_bytes, "fp32": 4, "fp64": 8}[args.precision]
+    # the factor's bytes over the distinct rows: the bf16 factors up to each
+    # panel's extent, with the lo half only where a tile can take the split
+    a_bytes = work_main[2]
     c_bytes = N * N * (8 if args.precision == "fp64" else 4)
     kernels = dict(
         gram=gram_fig,

@@ -176,6 +176,17 @@ int wlc_plan_sizes(wlc_plan plan, wlc_sizes *out);
  *   distinct [n_data]       index of the row's distinct (sorted) row. */
 int wlc_plan_index(wlc_plan plan, int32_t *tri, int32_t *rows, int32_t *distinct);
 
+/* Row order of the one-halo Gram product (eq. General1h over the distinct
+ * rows), into a HOST buffer of n_distinct int32: pos[e] is the product row of
+ * distinct row e.  The bf16 precisions order the distinct rows stably by their
+ * lowest redshift bin, so that a 256-row panel's factor ends where the lensing
+ * kernel of that bin does (eq. KernelLensing1); the panels of
+ * wlc_gram_split_tiles and of the gram_tol bound are runs of 256 in this
+ * order.  The other precisions keep the distinct order (pos[e] = e).  The
+ * covariance and every other output keep the data-vector order whatever this
+ * order is.  WLC_EINVAL for a null argument. */
+int wlc_plan_gram_order(wlc_plan plan, int32_t *pos);
+
 /* The plan's bin-averaging lists into HOST buffers (any may be NULL):
  *   off [n_cfg + 1]    entries off[c] .. off[c+1]-1 belong to configuration c
  *                      (ell-bins first, then triangles in data-vector order);
@@ -343,6 +354,10 @@ int wlc_gram_split_tiles(wlc_plan plan, const void *ws_run, int64_t *split, int6
  *   panel_f    WLC_BF16_AUTO: DEVICE, n_pad / 256 doubles F_I; the 256 x 256
  *              tile (I, J) takes the split product iff F_I F_J > lim, one
  *              product otherwise.  Ignored (may be NULL) for the others.
+ *   panel_ext  DEVICE, n_pad / 256 int32 or NULL: the rows of panel I are
+ *              zero from column 32 ext_I on (ext_I <= k_pad / 32), and tile
+ *              (I, J) sums only the first 32 min(ext_I, ext_J) columns (the
+ *              rest are zero products; A need not hold them).  NULL: all.
  *   g          DEVICE, FP32 [n_pad][n_pad], row-major: every entry (i, j)
  *              with i >= j is written; above the diagonal, the diagonal
  *              256 x 256 tiles hold partial or whole sums and the other tiles
@@ -353,7 +368,20 @@ int wlc_gram_split_tiles(wlc_plan plan, const void *ws_run, int64_t *split, int6
  * too large, a missing pointer or an unaligned workspace. */
 int wlc_gram_ws_bytes(int precision, int64_t n, int64_t k, size_t *bytes);
 int wlc_gram(int precision, int64_t n, int64_t k, const uint16_t *a_hi, const uint16_t *a_lo,
-             const double *panel_f, double lim, float *g, void *ws, void *stream);
+             const double *panel_f, double lim, const int32_t *panel_ext, float *g, void *ws, void *stream);
+
+/* Work of the last run's one-halo product, into HOST doubles: flops counts
+ * one product per tile over the columns it summed (2 x 256 x 256 per column
+ * and tile I >= J for the bf16 products, which stop where the shorter of the
+ * two panels' factors ends; the FP32 and FP64 products cover every column of
+ * their tiles), mfma_flops the same with the split tiles counted three times.
+ * factor_bytes (may be NULL): the bytes of the factor A that the product's
+ * operands need, over the distinct rows and the K columns (the bf16 factors
+ * up to each panel's extent, with the lo half where a tile of the panel can
+ * take the split product).  All 0 for WLC_FP64_CHI.  ws_run: the DEVICE
+ * workspace of a completed wlc_run with this plan; synchronises the device
+ * for the copies. */
+int wlc_gram_work(wlc_plan plan, const void *ws_run, double *flops, double *mfma_flops, double *factor_bytes);
 
 /* ---- phase timing (per-plan HIP events; not for plans shared by concurrent runs)
  * With timing enabled, wlc_run and wlc_snr2 record a HIP event pair on their

@@ -53,7 +53,8 @@ constexpr int64_t K_ALIGN = 64;
 enum Buf {
   B_ROWR, B_ROWO, B_CFGT, B_CENT, B_NMODES, B_NTRI, B_THR, B_TRI, B_FLAGS,
   B_U, B_PK, B_NE, B_X, B_R, B_DR, B_RR, B_PS, B_G, B_GMAX, B_TS, B_SEXP,
-  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, B_SW, B_SOFF, B_SLEG, B_SWT, B_SQ, B_GD, B_FP, NBUF
+  B_A0, B_A1, B_GM, B_PART, B_H, B_G2, B_H2, B_TS2, B_T2, B_SW, B_SOFF, B_SLEG, B_SWT, B_SQ, B_GD, B_FP,
+  B_AROW, B_POS, B_EXT, B_GP, NBUF
 };
 
 // Columns per chi node of the configuration factor G: the mass nodes, and
@@ -103,6 +104,12 @@ static Layout run_layout(const Plan &p) {
   const size_t ael = c.precision == WLC_FP64 ? 8 : (c.precision == WLC_FP32 ? 4 : 2);
   sz[B_A0] = chi ? 0 : (size_t)p.r_pad * p.k_pad * ael;
   sz[B_A1] = c.precision == WLC_BF16X3 || c.precision == WLC_BF16_AUTO ? sz[B_A0] : 0;
+  if (!p.arow.empty()) {  // A-rows in their own order: index maps, panel extents, the product in that order
+    sz[B_AROW] = p.arow.size() * 4;
+    sz[B_POS] = p.pos.size() * 4;
+    sz[B_EXT] = (size_t)(p.r_pad / GRAM_TILE) * 4;
+    sz[B_GP] = (size_t)p.r_pad * p.r_pad * 4;
+  }
   if (c.precision == WLC_BF16_AUTO) {  // the per-tile precision plan
     sz[B_SQ] = (size_t)n_cfg * c.n_chi * 8;
     sz[B_GD] = (size_t)p.n_R * 8;
@@ -174,10 +181,35 @@ size_t snr_structured_ws_bytes(const Plan &p) {
          align_up(chol_scratch_bytes(n), 256) + 256 + 256;
 }
 
+// The A-row order of the bf16 products: distinct rows by their lowest
+// redshift bin (rows hold their bins in increasing order), stably.  The
+// factor of a row vanishes beyond the far edge of its lowest bin (eq.
+// KernelLensing1: W_i(chi) = 0 past the sources of bin i), so panels of rows
+// with the same lowest bin end at the same chi node, and a tile's product
+// stops where the shorter of its two panels ends.
+static void order_arows(Plan &p) {
+  p.arow.clear();
+  p.pos.clear();
+  const int prec = p.cfg.precision;
+  if (prec != WLC_BF16 && prec != WLC_BF16X3 && prec != WLC_BF16_AUTO) return;
+  const int nz = p.cfg.n_z;
+  std::vector<int64_t> start((size_t)nz + 1, 0);
+  for (int64_t e = 0; e < p.n_R; ++e) ++start[(size_t)p.rowR[4 * e + 1] + 1];
+  for (int z = 0; z < nz; ++z) start[(size_t)z + 1] += start[(size_t)z];
+  p.arow.assign((size_t)p.r_pad, -1);
+  p.pos.assign((size_t)p.n_R, 0);
+  for (int64_t e = 0; e < p.n_R; ++e) {
+    const int64_t r = start[(size_t)p.rowR[4 * e + 1]]++;
+    p.arow[(size_t)r] = (int32_t)e;
+    p.pos[(size_t)e] = (int32_t)r;
+  }
+}
+
 static void finish_sizes(Plan &p) {
   p.k_len = (int64_t)p.cfg.n_chi * g_cols(p.cfg);
   p.k_pad = round_up(p.k_len, K_ALIGN);
   p.r_pad = round_up(p.n_R, GRAM_TILE);
+  order_arows(p);
   p.ws_run = run_ws_bytes(p);
   p.ws_snr = snr_ws_bytes(p);
 }
@@ -301,6 +333,8 @@ static int upload_index(const Plan &p, void *ws, const Layout &L, hipStream_t s)
       {B_NTRI, p.n_tri_closed.data(), p.n_tri_closed.size() * 8},
       {B_THR, p.lattice_thr.data(), p.lattice_thr.size() * 8},
       {B_TRI, p.triT.data(), p.triT.size() * 4},
+      {B_AROW, p.arow.data(), p.arow.size() * 4},
+      {B_POS, p.pos.data(), p.pos.size() * 4},
   };
   return upload(ups, sizeof(ups) / sizeof(ups[0]), ws, L, s);
 }
@@ -377,9 +411,14 @@ int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t
   if (ssc_chi) launch_sigma_w2(T, theta_sky(p), sw, s);
   launch_gfactor(T, cfgT, n_cfg, sl, U, R, sw, std::sqrt(p.omega), n_mg, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
+  const bool arows = !p.arow.empty();  // the bf16 products run on A-rows in their own order
+  const int32_t *arow = arows ? at<int32_t>(ws, L, B_AROW) : nullptr;
+  const int32_t *pos = arows ? at<int32_t>(ws, L, B_POS) : nullptr;
+  int32_t *ext = arows ? at<int32_t>(ws, L, B_EXT) : nullptr;
+  if (arows) launch_panel_ext(Ts, arow, p.r_pad, c.n_chi, n_mg, p.k_pad, ext, s);
   if (c.precision == WLC_BF16_AUTO)
     launch_split_plan(asm_args(p, ws, L), rowR, Ts, G, p.n_R, n_cfg, c.n_chi, n_mg, at<double>(ws, L, B_SQ),
-                      at<double>(ws, L, B_GD), at<double>(ws, L, B_FP), (int)(p.r_pad / GRAM_TILE), s);
+                      at<double>(ws, L, B_GD), at<double>(ws, L, B_FP), (int)(p.r_pad / GRAM_TILE), s, pos);
   if (c.flags & WLC_FLAG_NGINS) {
     // the projected one-halo trispectrum of two legs per triangle (the P.T
     // term), in FP64 through the factorisation along chi
@@ -398,7 +437,7 @@ int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t
     const bool auto_split = c.precision == WLC_BF16_AUTO;
     launch_abuild(fmt, rowR, Ts, G, p.n_R, p.r_pad, c.n_chi, n_mg, p.k_pad, p.k_pad, at<void>(ws, L, B_A0),
                   at<void>(ws, L, B_A1), s, auto_split ? at<double>(ws, L, B_FP) : nullptr,
-                  auto_split ? split_lim(p) : 0.0);
+                  auto_split ? split_lim(p) : 0.0, arow, ext);
   }
   if (hooks) hooks->end(WLC_PHASE_ABUILD);
   return hip_check(hipGetLastError(), "run launch");
@@ -417,10 +456,19 @@ static double split_lim(const Plan &p) {
   return (tol / eps) * (tol / eps);
 }
 
+// The product of the bf16 modes goes to GP (A-row order) and is put back in
+// the distinct-row order by run_enqueue_back; the others write G directly.
+static void *gram_out(const Plan &p, void *ws, const Layout &L) {
+  return at<void>(ws, L, p.arow.empty() ? B_GM : B_GP);
+}
+static const int32_t *gram_ext(const Plan &p, void *ws, const Layout &L) {
+  return p.arow.empty() ? nullptr : at<int32_t>(ws, L, B_EXT);
+}
+
 int run_enqueue_gram(const Plan &p, void *ws, hipStream_t s, PhaseHooks *hooks) {
   const wlc_config &c = p.cfg;
   const Layout L = run_layout(p);
-  void *Gm = at<void>(ws, L, B_GM);
+  void *Gm = gram_out(p, ws, L);
   if (hooks) hooks->begin(WLC_PHASE_GRAM);
   if (c.precision == WLC_FP64_CHI) {
     // no flattened factor: the one-halo product from T and G directly
@@ -430,7 +478,7 @@ int run_enqueue_gram(const Plan &p, void *ws, hipStream_t s, PhaseHooks *hooks) 
                    (double *)Gm, p.r_pad, s);
   } else {
     launch_gram(c.precision, gram_shape(p), at<void>(ws, L, B_A0), at<void>(ws, L, B_A1), Gm, at<void>(ws, L, B_PART),
-                s, at<double>(ws, L, B_FP), split_lim(p));
+                s, at<double>(ws, L, B_FP), split_lim(p), gram_ext(p, ws, L));
   }
   if (hooks) hooks->end(WLC_PHASE_GRAM);
   return hip_check(hipGetLastError(), "gram launch");
@@ -440,13 +488,13 @@ bool run_gram_batchable(const Plan &p) { return gram_batchable(p.cfg.precision);
 
 void run_gram_job(const Plan &p, void *ws, GramJob &job) {
   const Layout L = run_layout(p);
-  gram_job(p.cfg.precision, gram_shape(p), at<void>(ws, L, B_A0), at<void>(ws, L, B_A1), at<void>(ws, L, B_GM),
-           at<void>(ws, L, B_PART), job, at<double>(ws, L, B_FP), split_lim(p));
+  gram_job(p.cfg.precision, gram_shape(p), at<void>(ws, L, B_A0), at<void>(ws, L, B_A1), gram_out(p, ws, L),
+           at<void>(ws, L, B_PART), job, at<double>(ws, L, B_FP), split_lim(p), gram_ext(p, ws, L));
 }
 
 int run_enqueue_gram_reduce(const Plan &p, void *ws, hipStream_t s) {
   const Layout L = run_layout(p);
-  launch_gram_reduce(p.cfg.precision, gram_shape(p), at<void>(ws, L, B_GM), at<void>(ws, L, B_PART), s);
+  launch_gram_reduce(p.cfg.precision, gram_shape(p), gram_out(p, ws, L), at<void>(ws, L, B_PART), s);
   return hip_check(hipGetLastError(), "gram reduce launch");
 }
 
@@ -485,7 +533,13 @@ int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, d
   void *Gm = at<void>(ws, L, B_GM);
   const AsmArgs a = asm_args(p, ws, L);
   if (hooks) hooks->begin(WLC_PHASE_ASSEMBLE);
-  launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
+  if (p.arow.empty()) {
+    launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
+  } else {  // the product of the A-rows, made symmetric, back in the distinct-row order
+    float *GP = at<float>(ws, L, B_GP);
+    launch_gram_mirror(1, GP, p.r_pad, p.r_pad, s);
+    launch_gram_unpermute(GP, at<int32_t>(ws, L, B_POS), p.n_R, p.r_pad, (float *)Gm, s);
+  }
   launch_rowexp(a, row_exp2, d, r, s);
   launch_assemble(a, row_exp2, C, s);
   if (hooks) hooks->end(WLC_PHASE_ASSEMBLE);
@@ -736,6 +790,13 @@ int wlc_plan_index(wlc_plan plan, int32_t *tri, int32_t *rows, int32_t *distinct
   return WLC_OK;
 }
 
+int wlc_plan_gram_order(wlc_plan plan, int32_t *pos) {
+  if (!plan || !pos) return fail(WLC_EINVAL, "null argument");
+  const Plan &p = plan->p;
+  for (int64_t e = 0; e < p.n_R; ++e) pos[e] = p.pos.empty() ? (int32_t)e : p.pos[(size_t)e];
+  return WLC_OK;
+}
+
 int wlc_counts_closed(wlc_plan plan, double *n_modes, double *n_tri) {
   if (!plan) return fail(WLC_EINVAL, "null plan");
   const Plan &p = plan->p;
@@ -856,7 +917,7 @@ int wlc_gram_ws_bytes(int precision, int64_t n, int64_t k, size_t *bytes) {
 }
 
 int wlc_gram(int precision, int64_t n, int64_t k, const uint16_t *a_hi, const uint16_t *a_lo,
-             const double *panel_f, double lim, float *g, void *ws, void *stream) {
+             const double *panel_f, double lim, const int32_t *panel_ext, float *g, void *ws, void *stream) {
   GramShape sh;
   int rc = gram_shape_of(precision, n, k, sh);
   if (rc) return rc;
@@ -867,8 +928,68 @@ int wlc_gram(int precision, int64_t n, int64_t k, const uint16_t *a_hi, const ui
   if (part > 0 && !ws) return fail(WLC_EINVAL, "wlc_gram: null workspace");
   if (((uintptr_t)ws & 255) != 0) return fail(WLC_EINVAL, "wlc_gram: workspace must be 256-byte aligned");
   launch_gram(precision, sh, a_hi, precision == WLC_BF16 ? a_hi : a_lo, g, ws, (hipStream_t)stream,
-              precision == WLC_BF16_AUTO ? panel_f : nullptr, precision == WLC_BF16_AUTO ? lim : 0.0);
+              precision == WLC_BF16_AUTO ? panel_f : nullptr, precision == WLC_BF16_AUTO ? lim : 0.0, panel_ext);
   return hip_check(hipGetLastError(), "wlc_gram launch");
+}
+
+int wlc_gram_work(wlc_plan plan, const void *ws_run, double *flops, double *mfma_flops, double *factor_bytes) {
+  if (!plan || !ws_run || !flops || !mfma_flops) return fail(WLC_EINVAL, "null argument");
+  const Plan &p = plan->p;
+  const int prec = p.cfg.precision;
+  if (prec == WLC_FP64_CHI) {
+    *flops = *mfma_flops = 0.0;
+    if (factor_bytes) *factor_bytes = 0.0;
+    return WLC_OK;
+  }
+  const Layout L = run_layout(p);
+  const bool f64 = prec == WLC_FP64 && p.r_pad % 256 == 0;  // the FP64 product covers 128 x 256 tiles
+  const int64_t tile = (prec == WLC_FP64 || prec == WLC_FP32) ? 128 : GRAM_TILE, np = p.r_pad / tile;
+  std::vector<int32_t> ext;
+  if (!p.arow.empty()) {
+    ext.resize((size_t)np);
+    int rc = hip_check(hipMemcpy(ext.data(), static_cast<const char *>(ws_run) + L.off[B_EXT], (size_t)np * 4,
+                                 hipMemcpyDeviceToHost), "panel extent copy");
+    if (rc) return rc;
+  }
+  std::vector<double> F;
+  if (prec == WLC_BF16_AUTO) {
+    F.resize((size_t)np + 1);  // per panel, then the largest
+    int rc = hip_check(hipMemcpy(F.data(), static_cast<const char *>(ws_run) + L.off[B_FP], (size_t)(np + 1) * 8,
+                                 hipMemcpyDeviceToHost), "split plan copy");
+    if (rc) return rc;
+  }
+  const double lim = split_lim(p), t2 = 2.0 * (double)tile * (double)tile;
+  double f = 0.0, m = 0.0;
+  for (int64_t I = 0; I < np; ++I)
+    for (int64_t J = 0; J <= I; ++J) {
+      const double k = ext.empty() ? (double)p.k_pad : (double)GRAM_KB * std::min(ext[(size_t)I], ext[(size_t)J]);
+      const double one = t2 * k;
+      f += one;
+      const bool split = prec == WLC_BF16X3 || (prec == WLC_BF16_AUTO && F[(size_t)I] * F[(size_t)J] > lim);
+      m += split ? 3.0 * one : one;
+    }
+  if (f64) {  // J <= I / 2 in 128 x 256 tiles: the diagonal pairs add a quarter tile each
+    const double extra = (double)(np / 2) * 2.0 * 128.0 * 128.0 * (double)p.k_pad;
+    f += extra;
+    m += extra;
+  }
+  *flops = f;
+  *mfma_flops = m;
+  if (factor_bytes) {
+    double b = 0.0;
+    if (ext.empty()) {
+      b = (double)p.n_R * (double)p.k_len * (prec == WLC_FP64 ? 8.0 : prec == WLC_FP32 ? 4.0 : 2.0);
+    } else {  // the distinct rows lead the A-row order; a panel's rows end at its extent
+      for (int64_t P = 0; P < np; ++P) {
+        const double rows = (double)std::max<int64_t>(0, std::min<int64_t>(tile, p.n_R - P * tile));
+        const double k = (double)std::min<int64_t>((int64_t)GRAM_KB * ext[(size_t)P], p.k_len);
+        const bool lo = prec == WLC_BF16X3 || (prec == WLC_BF16_AUTO && F[(size_t)P] * F[(size_t)np] > lim);
+        b += rows * k * (lo ? 4.0 : 2.0);
+      }
+    }
+    *factor_bytes = b;
+  }
+  return WLC_OK;
 }
 
 int wlc_snr2_noalloc(wlc_plan plan, const void *C, const int32_t *row_exp2, const double *d, double *snr2_dev,

@@ -187,7 +187,8 @@ __global__ void k_zero_f64(double *p, int n) {
   if (i < n) p[i] = 0.0;
 }
 
-__global__ void k_split_share(AsmArgs A, const double *__restrict__ gd, double *__restrict__ F) {
+__global__ void k_split_share(AsmArgs A, const double *__restrict__ gd, double *__restrict__ F,
+                              const int32_t *__restrict__ pos) {
   const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (a >= A.n) return;
   const int32_t *ra = A.rowO + 8 * a;
@@ -199,17 +200,18 @@ __global__ void k_split_share(AsmArgs A, const double *__restrict__ gd, double *
   const double f = c > 0.0 && isfinite(c) ? c1h / c : 1.0;
   // non-negative doubles order like their bit patterns
   const unsigned long long bits = (unsigned long long)__double_as_longlong(f);
-  atomicMax((unsigned long long *)&F[e / SPLIT_PANEL], bits);
+  atomicMax((unsigned long long *)&F[(pos ? pos[e] : e) / SPLIT_PANEL], bits);  // the panel of its A-row
   atomicMax((unsigned long long *)&F[A.ld_g / SPLIT_PANEL], bits);  // the largest of all panels
 }
 
 void launch_split_plan(const AsmArgs &a, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R,
-                       int n_cfg, int n_chi, int n_mg, double *S, double *gd, double *F, int n_panels, hipStream_t s) {
+                       int n_cfg, int n_chi, int n_mg, double *S, double *gd, double *F, int n_panels, hipStream_t s,
+                       const int32_t *pos) {
   const int64_t items = (int64_t)n_cfg * n_chi;
   hipLaunchKernelGGL(k_gsq, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, s, G, items, n_mg, S);
   hipLaunchKernelGGL(k_gdiag, dim3((unsigned)((n_R + 3) / 4)), dim3(256), 0, s, rowR, Ts, S, n_R, n_chi, gd);
   hipLaunchKernelGGL(k_zero_f64, dim3((n_panels + 256) / 256), dim3(256), 0, s, F, n_panels + 1);
-  hipLaunchKernelGGL(k_split_share, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, gd, F);
+  hipLaunchKernelGGL(k_split_share, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, gd, F, pos);
 }
 
 // 64 x 64 output tiles (I >= J); each thread computes 16 entries of one

@@ -303,7 +303,7 @@ __device__ __forceinline__ void gram_bf16_tile1(const uint16_t *__restrict__ Ahi
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
   const int64_t kb = (int64_t)split * k_split;
-  const int64_t ke = min(k_pad, kb + k_split);
+  const int64_t ke = max(kb, min(k_pad, kb + k_split));  // an empty slice stores zeros
   GramAcc<false, NW> acc;
   acc.init(wave, lane);
   GramDma<1, NW> dma;
@@ -370,7 +370,7 @@ __device__ __forceinline__ void gram_bf16_tile3(const uint16_t *__restrict__ Ahi
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t row0 = (int64_t)I * T2, col0 = (int64_t)J * T2;
   const int64_t kb = (int64_t)split * k_split;
-  const int64_t ke = min(k_pad, kb + k_split);
+  const int64_t ke = max(kb, min(k_pad, kb + k_split));  // an empty slice stores zeros
   GramAcc<true, NW> acc;
   acc.init(wave, lane);
   GramDma<2, NW> dma;
@@ -410,13 +410,21 @@ __device__ __forceinline__ bool tile_split(const double *__restrict__ panel_f, d
   return panel_f[I] * panel_f[J] > lim;
 }
 
+// With panel_ext, the k range of tile (I, J) ends after min(ext_I, ext_J)
+// k-blocks (beyond it one of the two panels is zero), and the tile's slices
+// split that range evenly, as the host splits the whole range without it, so
+// that the work items of a product stay alike in length.
 template <int MODE, int NW>
 __device__ __forceinline__ void gram_bf16_item(const uint16_t *__restrict__ Ahi, const uint16_t *__restrict__ Alo,
-                                               int64_t k_pad, int64_t r_pad, int64_t k_split, int I, int J,
-                                               int split, float *__restrict__ out, float *__restrict__ partial,
+                                               int64_t k_pad, int64_t r_pad, int64_t k_split, int n_split, int I,
+                                               int J, int split, float *__restrict__ out, float *__restrict__ partial,
                                                int64_t ld, int64_t part_stride, const double *__restrict__ panel_f,
-                                               double lim, GramStage &b0, GramStage &b1, GramStage &b2,
-                                               GramStage &b3) {
+                                               double lim, const int32_t *__restrict__ panel_ext, GramStage &b0,
+                                               GramStage &b1, GramStage &b2, GramStage &b3) {
+  if (panel_ext) {
+    k_pad = min(k_pad, (int64_t)max(min(panel_ext[I], panel_ext[J]), 0) * BK2);
+    k_split = (k_pad / BK2 + n_split - 1) / n_split * BK2;
+  }
   if (MODE != 0 && tile_split<MODE>(panel_f, lim, I, J))
     gram_bf16_tile3<NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, b0, b1, b2, b3);
   else
@@ -428,15 +436,16 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16(const uint16_t *__restric
                                                   int64_t k_pad, int64_t r_pad, int64_t k_split, int n_split,
                                                   int nt, int64_t n_work, float *__restrict__ out,
                                                   float *__restrict__ partial, int64_t ld, int64_t part_stride,
-                                                  const double *__restrict__ panel_f, double lim) {
+                                                  const double *__restrict__ panel_f, double lim,
+                                                  const int32_t *__restrict__ panel_ext) {
   __shared__ __attribute__((aligned(16))) GramStage b0;
   __shared__ __attribute__((aligned(16))) GramStage b1;
   __shared__ __attribute__((aligned(16))) GramStage b2;
   __shared__ __attribute__((aligned(16))) GramStage b3;  // split tiles only (unused, and not allocated, in MODE 0)
   int I, J, split;
   if (!gram_work<GRAM_XC>(n_work, n_split, nt, I, J, split)) return;
-  gram_bf16_item<MODE, NW>(Ahi, Alo, k_pad, r_pad, k_split, I, J, split, out, partial, ld, part_stride, panel_f, lim,
-                           b0, b1, b2, b3);
+  gram_bf16_item<MODE, NW>(Ahi, Alo, k_pad, r_pad, k_split, n_split, I, J, split, out, partial, ld, part_stride,
+                           panel_f, lim, panel_ext, b0, b1, b2, b3);
 }
 
 // ---------------------------------------------------------------- batched
@@ -491,9 +500,9 @@ __global__ __launch_bounds__(64 * NW) void k_gram_bf16_batch(const GramJob *__re
     const GramJob &jb = jobs[a];
     int I, J, split;
     gram_item(g - jb.item0, jb.n_work, jb.n_split, jb.nt, I, J, split);
-    gram_bf16_item<MODE, NW>((const uint16_t *)jb.A0, (const uint16_t *)jb.A1, jb.k_pad, jb.r_pad, jb.k_split, I,
-                             J, split, (float *)jb.out, (float *)jb.partial, jb.ld, jb.part_stride, jb.panel_f,
-                             jb.split_lim, b0, b1, b2, b3);
+    gram_bf16_item<MODE, NW>((const uint16_t *)jb.A0, (const uint16_t *)jb.A1, jb.k_pad, jb.r_pad, jb.k_split,
+                             jb.n_split, I, J, split, (float *)jb.out, (float *)jb.partial, jb.ld, jb.part_stride,
+                             jb.panel_f, jb.split_lim, jb.panel_ext, b0, b1, b2, b3);
   }
 }
 
@@ -703,6 +712,33 @@ void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s) 
     hipLaunchKernelGGL(k_gram_mirror<double>, dim3(tiles), dim3(256), 0, s, (double *)G, ld);
 }
 
+// G in the order of the distinct rows from the product of the A-rows (GP,
+// symmetric): G[e][f] = GP[pos[e]][pos[f]], in 64 x 64 tiles of G.  Within a
+// configuration the rows of one lowest bin are consecutive in both orders,
+// so a wavefront's 64 reads of one GP row fall in a few contiguous runs.
+__global__ __launch_bounds__(256) void k_gram_unpermute(const float *__restrict__ GP, const int32_t *__restrict__ pos,
+                                                       int64_t n, int64_t ld, float *__restrict__ G) {
+  __shared__ int32_t prow[64];
+  const int64_t nt = (n + 63) / 64;
+  const int64_t I = blockIdx.x / nt, J = blockIdx.x % nt;
+  const int c = threadIdx.x & 63, rb = (threadIdx.x >> 6) * 16;
+  if (threadIdx.x < 64) prow[threadIdx.x] = I * 64 + threadIdx.x < n ? pos[I * 64 + threadIdx.x] : 0;
+  __syncthreads();
+  const int64_t f = J * 64 + c;
+  if (f >= n) return;
+  const int64_t pf = pos[f];
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int64_t e = I * 64 + rb + q;
+    if (e < n) G[e * ld + f] = GP[(int64_t)prow[rb + q] * ld + pf];
+  }
+}
+
+void launch_gram_unpermute(const float *GP, const int32_t *pos, int64_t n, int64_t ld, float *G, hipStream_t s) {
+  const int64_t nt = (n + 63) / 64;
+  hipLaunchKernelGGL(k_gram_unpermute, dim3((unsigned)(nt * nt)), dim3(256), 0, s, GP, pos, n, ld, G);
+}
+
 // Slices of K per tile: enough workgroups to cover the chip several times.
 // The bf16 kernels, whose time is set by their operand stream, also take two
 // slices on large problems (measured 5 % faster at 33280 rows and K = 131072
@@ -767,9 +803,10 @@ static GramSplit gram_split(int prec, const GramShape &g) {
 bool gram_batchable(int prec) { return is_bf16(prec); }
 
 void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job,
-              const double *panel_f, double split_lim) {
+              const double *panel_f, double split_lim, const int32_t *panel_ext) {
   const GramSplit q = gram_split(prec, g);
   job.panel_f = panel_f;
+  job.panel_ext = panel_ext;
   job.split_lim = split_lim;
   job.A0 = A0;
   job.A1 = A1;
@@ -838,7 +875,7 @@ void launch_gram_reduce(int prec, const GramShape &g, void *out, void *partial, 
 }
 
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
-                 hipStream_t s, const double *panel_f, double split_lim) {
+                 hipStream_t s, const double *panel_f, double split_lim, const int32_t *panel_ext) {
   const GramSplit q = gram_split(prec, g);
   const int64_t nt = q.nt, tiles = q.tiles, ksplit = q.ksplit, pstride = q.pstride, n_work = q.n_work;
   const int ns = q.ns;
@@ -849,17 +886,17 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
     case WLC_BF16:
       hipLaunchKernelGGL((k_gram_bf16<0, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
                          (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
-                         g.ld_out, pstride, panel_f, split_lim);
+                         g.ld_out, pstride, panel_f, split_lim, panel_ext);
       break;
     case WLC_BF16X3:
       hipLaunchKernelGGL((k_gram_bf16<1, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
                          (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
-                         g.ld_out, pstride, panel_f, split_lim);
+                         g.ld_out, pstride, panel_f, split_lim, panel_ext);
       break;
     case WLC_BF16_AUTO:
       hipLaunchKernelGGL((k_gram_bf16<2, GRAM_NW>), grid, dim3(64 * GRAM_NW), 0, s, (const uint16_t *)A0,
                          (const uint16_t *)A1, g.k_pad, g.r_pad, ksplit, ns, nti, n_work, (float *)out, (float *)partial,
-                         g.ld_out, pstride, panel_f, split_lim);
+                         g.ld_out, pstride, panel_f, split_lim, panel_ext);
       break;
     case WLC_FP32:
       hipLaunchKernelGGL(k_gram_x4<float>, grid, dim3(256), 0, s, (const float *)A0, g.k_pad, g.lda, ksplit, ns, nti,

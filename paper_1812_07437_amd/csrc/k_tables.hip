@@ -554,36 +554,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FMT == 1 ? 
                                                    const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
                                                    int64_t k_pad, int64_t r_pad, uint16_t *__restrict__ A0,
                                                    uint16_t *__restrict__ A1, const double *__restrict__ panel_f,
-                                                   double lim) {
+                                                   double lim, const int32_t *__restrict__ arow,
+                                                   const int32_t *__restrict__ ext) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int chunk = lane & 3;
-  const int64_t row0 = (int64_t)blockIdx.y * 64 + (lane >> 2);
-  // a workgroup's 64 rows lie in one 256-row panel
-  const bool need_lo = FMT == 2 && (panel_f == nullptr || panel_f[blockIdx.y / 4] * panel_f[r_pad / 256] > lim);
+  const int64_t row0 = (int64_t)blockIdx.y * 64 + (lane >> 2);  // A-rows row0 + 16 j
+  // a workgroup's 64 rows lie in one 256-row panel; with ext the panel's rows
+  // are zero from k-block ext[panel] on, and no product reads them there
+  const int panel = blockIdx.y / 4;
+  const int n_kb =
+      (int)min((int64_t)AB_KB, (ext ? (int64_t)ext[panel] : k_pad / GRAM_KB) - (int64_t)blockIdx.x * AB_KB);
+  if (n_kb <= 0) return;  // workgroup-uniform, before any barrier
+  const bool need_lo = FMT == 2 && (panel_f == nullptr || panel_f[panel] * panel_f[r_pad / 256] > lim);
   const int64_t k_len = (int64_t)n_chi * n_m;
   const bool whole = (n_m & 7) == 0;  // a chunk of 8 k lies in one chi node
+  // the distinct row of an A-row (-1 for padding)
+  auto distinct = [&](int64_t r) -> int { return arow ? arow[r] : (r < n_R ? (int)r : -1); };
   int cfg[AB_RW];
   const double *Tr[AB_RW];
 #pragma unroll
   for (int j = 0; j < AB_RW; ++j) {
-    const int64_t row = row0 + 16 * j;
-    cfg[j] = row < n_R ? rowR[4 * row] : -1;
-    Tr[j] = Ts + (size_t)(row < n_R ? row : 0) * n_chi;
+    const int e = distinct(row0 + 16 * j);
+    cfg[j] = e >= 0 ? rowR[4 * e] : -1;
+    Tr[j] = Ts + (size_t)(e >= 0 ? e : 0) * n_chi;
   }
   // T of the workgroup's 64 rows at the chi nodes of its k range, staged in
   // LDS with coalesced loads (a lane would otherwise gather T of its rows
   // from 16 rows n_chi apart at every node change)
   __shared__ double Tl[64][AB_TN + 1];
+  __shared__ int c_rng[2];  // smallest and largest configuration of the workgroup's rows
   const int64_t kbeg = (int64_t)blockIdx.x * AB_KB * GRAM_KB;
   const int n_lo = kbeg < k_len ? (int)(kbeg / n_m) : 0;
-  const int n_hi = kbeg < k_len ? (int)((min(kbeg + AB_KB * GRAM_KB, k_len) - 1) / n_m) : 0;
+  const int n_hi = kbeg < k_len ? (int)((min(kbeg + (int64_t)n_kb * GRAM_KB, k_len) - 1) / n_m) : 0;
   const int nodes = n_hi - n_lo + 1;
   const bool staged = whole && kbeg < k_len && nodes <= AB_TN;  // workgroup-uniform
   if (staged) {
+    if (threadIdx.x == 0) c_rng[0] = 0x7FFFFFFF, c_rng[1] = -1;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int e = distinct((int64_t)blockIdx.y * 64 + threadIdx.x);
+      if (e >= 0) {
+        atomicMin(&c_rng[0], rowR[4 * e]);
+        atomicMax(&c_rng[1], rowR[4 * e]);
+      }
+    }
     for (int idx = threadIdx.x; idx < 64 * nodes; idx += 256) {
       const int r = idx / nodes, q = idx % nodes;
-      const int64_t row = (int64_t)blockIdx.y * 64 + r;
-      Tl[r][q] = row < n_R ? Ts[row * n_chi + n_lo + q] : 0.0;
+      const int e = distinct((int64_t)blockIdx.y * 64 + r);
+      Tl[r][q] = e >= 0 ? Ts[(int64_t)e * n_chi + n_lo + q] : 0.0;
     }
     __syncthreads();
   }
@@ -591,11 +609,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FMT == 1 ? 
   // two alternating buffers: the barrier after filling one for pass p also
   // ends every wavefront's reads of pass p - 1, whose buffer pass p + 1 fills
   __shared__ double Gl[2][AB_GC][4 * GRAM_KB];
-  const int64_t rfirst = (int64_t)blockIdx.y * 64, rlast = min(rfirst + 63, n_R - 1);
-  const int c_first = rfirst < n_R ? rowR[4 * rfirst] : 0;
-  const int c_last = rfirst < n_R ? rowR[4 * rlast] : 0;
-  const bool gstaged = staged && rfirst < n_R && c_last - c_first < AB_GC;  // workgroup-uniform
-  const int n_kb = (int)min((int64_t)AB_KB, k_pad / GRAM_KB - (int64_t)blockIdx.x * AB_KB);
+  const int c_first = staged ? c_rng[0] : 0, c_last = staged ? c_rng[1] : -1;
+  const bool gstaged = staged && c_last >= c_first && c_last - c_first < AB_GC;  // workgroup-uniform
   int node[AB_RW];
   double tn[AB_RW];
 #pragma unroll
@@ -613,7 +628,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FMT == 1 ? 
       }
       __syncthreads();
     }
-    if (q >= n_kb) continue;  // past k_pad (later passes' barriers still to come: no break)
+    if (q >= n_kb) continue;  // past the panel's k-blocks (later passes' barriers still to come: no break)
     const int64_t kblk = (int64_t)blockIdx.x * AB_KB + q;
     const int64_t k0 = kblk * GRAM_KB + 8 * chunk;
     const int n = k0 < k_len ? (int)(k0 / n_m) : 0;
@@ -674,19 +689,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FMT == 1 ? 
   }
 }
 
+// One workgroup per 256-row panel of A-rows: each thread scans its row's T
+// back from the last chi node to the last nonzero one; the panel keeps the
+// largest count of k-blocks (the k of node n are n N_M .. n N_M + N_M - 1).
+__global__ __launch_bounds__(256) void k_panel_ext(const double *__restrict__ Ts, const int32_t *__restrict__ arow,
+                                                  int n_chi, int n_mg, int64_t k_pad, int32_t *__restrict__ ext) {
+  __shared__ int32_t best;
+  if (threadIdx.x == 0) best = 0;
+  __syncthreads();
+  const int e = arow[(int64_t)blockIdx.x * 256 + threadIdx.x];
+  int last = -1;
+  if (e >= 0) {
+    const double *t = Ts + (size_t)e * n_chi;
+    for (int n = n_chi - 1; n >= 0; --n)
+      if (t[n] != 0.0) {
+        last = n;
+        break;
+      }
+  }
+  const int64_t kb = min(((int64_t)(last + 1) * n_mg + GRAM_KB - 1) / GRAM_KB, k_pad / GRAM_KB);
+  if (kb > 0) atomicMax(&best, (int32_t)kb);
+  __syncthreads();
+  if (threadIdx.x == 0) ext[blockIdx.x] = best;
+}
+
+void launch_panel_ext(const double *Ts, const int32_t *arow, int64_t r_pad, int n_chi, int n_mg, int64_t k_pad,
+                      int32_t *ext, hipStream_t s) {
+  hipLaunchKernelGGL(k_panel_ext, dim3((unsigned)(r_pad / 256)), dim3(256), 0, s, Ts, arow, n_chi, n_mg, k_pad, ext);
+}
+
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
                    int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s,
-                   const double *panel_f, double lim) {
+                   const double *panel_f, double lim, const int32_t *arow, const int32_t *ext) {
   if (fmt == 1 || fmt == 2) {
     // r_pad is a multiple of 64 and k_pad of GRAM_KB (rows are padded to the
     // Gram tile, columns to 64)
     const dim3 grid((unsigned)((k_pad / GRAM_KB + AB_KB - 1) / AB_KB), (unsigned)(r_pad / 64));
     if (fmt == 1)
       hipLaunchKernelGGL(k_abuild_blk<1>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, r_pad,
-                         (uint16_t *)A0, (uint16_t *)A1, nullptr, 0.0);
+                         (uint16_t *)A0, (uint16_t *)A1, nullptr, 0.0, arow, ext);
     else
       hipLaunchKernelGGL(k_abuild_blk<2>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, r_pad,
-                         (uint16_t *)A0, (uint16_t *)A1, panel_f, lim);
+                         (uint16_t *)A0, (uint16_t *)A1, panel_f, lim, arow, ext);
     return;
   }
   // r_pad is a multiple of AB_ROWS (rows are padded to the Gram tile)

@@ -41,9 +41,18 @@ void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT
 constexpr int GRAM_KB = 32;
 // panel_f, lim (fmt 2 only): write the lo half only for panels that can
 // take the split product (WLC_BF16_AUTO); nullptr writes it everywhere.
+// arow, ext (bf16 formats): the distinct row of each A-row and the k-blocks
+// each 256-row panel of A-rows needs (see launch_panel_ext); nullptr: A-row =
+// distinct row, every k-block.
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
                    int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s,
-                   const double *panel_f = nullptr, double lim = 0.0);
+                   const double *panel_f = nullptr, double lim = 0.0, const int32_t *arow = nullptr,
+                   const int32_t *ext = nullptr);
+// Per 256-row panel of A-rows, ext[P] = the 32-column k-blocks up to the last
+// chi node where T (Ts [n_R][n_chi]) of one of its rows is nonzero: the
+// factor of a row is zero beyond it (T carries the lensing kernels).
+void launch_panel_ext(const double *Ts, const int32_t *arow, int64_t r_pad, int n_chi, int n_mg, int64_t k_pad,
+                      int32_t *ext, hipStream_t s);
 
 // Two-leg factors of the projected one-halo trispectrum (P.T term): G2
 // [n2][n_chi][n_m] and Ts2 [rows][n_chi] for the n2 = n_ell (n_ell + 1) / 2
@@ -64,8 +73,12 @@ struct GramShape {
 };
 size_t gram_partial_bytes(int prec, const GramShape &g);
 // panel_f, split_lim: WLC_BF16_AUTO only (see k_gram.hip); ignored otherwise.
+// panel_ext (bf16 only): per 256-row panel the k-blocks where its rows can
+// be nonzero; tile (I, J) then sums only the first min(ext_I, ext_J) k-blocks
+// (the rest are zero products).  nullptr: every k-block.
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
-                 hipStream_t s, const double *panel_f = nullptr, double split_lim = 0.0);
+                 hipStream_t s, const double *panel_f = nullptr, double split_lim = 0.0,
+                 const int32_t *panel_ext = nullptr);
 // Batched bf16 Gram products (one persistent launch over the work items of
 // several products, e.g. of the requests of a server).  A product in a
 // batch computes exactly what launch_gram computes for it: the same tiles,
@@ -78,11 +91,12 @@ struct GramJob {
   int64_t item0;         // first item of this product in the batch (set by the caller)
   const double *panel_f; // WLC_BF16_AUTO: per-panel largest one-halo share
   double split_lim;      // WLC_BF16_AUTO: split tile (I, J) iff panel_f[I] panel_f[J] > split_lim
+  const int32_t *panel_ext;  // per panel the k-blocks that can be nonzero (nullptr: all)
   int32_t n_split, nt;
 };
 bool gram_batchable(int prec);  // the bf16 precisions
 void gram_job(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial, GramJob &job,
-              const double *panel_f = nullptr, double split_lim = 0.0);
+              const double *panel_f = nullptr, double split_lim = 0.0, const int32_t *panel_ext = nullptr);
 // counters: N_XCD x 16 uint32 of device scratch, cleared by the launch itself
 constexpr int GRAM_BATCH_COUNTERS = 8 * 16;
 int launch_gram_batch(int prec, const GramJob *jobs_dev, int n_jobs, int64_t total, uint32_t *counters,
@@ -98,6 +112,10 @@ void launch_chifact(const double *Ts, const double *G, double *H, int n_cfg, int
 // Copy the lower triangle of the first n rows/columns of G (row pitch ld,
 // f32 or f64) onto the upper one, so that G is exactly symmetric.
 void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s);
+// G[e][f] = GP[pos[e]][pos[f]] for e, f < n (both triangles, FP32, pitch ld):
+// the product of the A-rows (GP, made symmetric first) back in the order of
+// the distinct rows.
+void launch_gram_unpermute(const float *GP, const int32_t *pos, int64_t n, int64_t ld, float *G, hipStream_t s);
 
 // ---- assembly (k_assemble.hip)
 struct AsmArgs {
@@ -126,8 +144,10 @@ void launch_rowexp(const AsmArgs &a, int32_t *row_exp2, double *d, double *r, hi
 // Gram factors in FP64 before the product: S [n_cfg][n_chi] and gd [n_R]
 // are scratch.  C_aa leaves out the in-survey terms (positive on the
 // diagonal), so F errs on the large side.
+// pos (nullptr: identity) maps a distinct row to its A-row, whose panel F holds.
 void launch_split_plan(const AsmArgs &a, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R,
-                       int n_cfg, int n_chi, int n_mg, double *S, double *gd, double *F, int n_panels, hipStream_t s);
+                       int n_cfg, int n_chi, int n_mg, double *S, double *gd, double *F, int n_panels, hipStream_t s,
+                       const int32_t *pos = nullptr);
 // C in the type of the one-halo block Gm: FP32 when gm_f32, else FP64.
 void launch_assemble(const AsmArgs &a, const int32_t *row_exp2, void *C, hipStream_t s);
 

@@ -82,6 +82,7 @@ def _load():
     L.wlc_plan_destroy.restype = None
     L.wlc_plan_sizes.argtypes = [vp, ct.POINTER(wlc_sizes)]
     L.wlc_plan_index.argtypes = [vp, vp, vp, vp]
+    L.wlc_plan_gram_order.argtypes = [vp, vp]
     L.wlc_counts_closed.argtypes = [vp, vp, vp]
     L.wlc_plan_averaging.argtypes = [vp, vp, vp, vp, vp]
     L.wlc_lattice_counts.argtypes = [vp, vp, vp, vp, vp]
@@ -93,7 +94,8 @@ def _load():
     L.wlc_snr2_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.wlc_gram_split_tiles.argtypes = [vp, vp, vp, vp]
     L.wlc_gram_ws_bytes.argtypes = [ct.c_int, ct.c_int64, ct.c_int64, vp]
-    L.wlc_gram.argtypes = [ct.c_int, ct.c_int64, ct.c_int64, vp, vp, vp, ct.c_double, vp, vp, vp]
+    L.wlc_gram.argtypes = [ct.c_int, ct.c_int64, ct.c_int64, vp, vp, vp, ct.c_double, vp, vp, vp, vp]
+    L.wlc_gram_work.argtypes = [vp, vp, vp, vp, vp]
     L.wlc_pca.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.wlc_plan_set_timing.argtypes = [vp, ct.c_int]
     L.wlc_plan_timings.argtypes = [vp, vp]
@@ -103,9 +105,10 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_averaging",
+EXPORTED = ["wlc_plan_create", "wlc_plan_destroy", "wlc_plan_sizes", "wlc_plan_index", "wlc_plan_gram_order",
+            "wlc_plan_averaging",
             "wlc_counts_closed",
-            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_noalloc", "wlc_gram_split_tiles", "wlc_gram_ws_bytes", "wlc_gram", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
+            "wlc_lattice_counts", "wlc_run", "wlc_sigma_w2", "wlc_snr2", "wlc_snr2_noalloc", "wlc_gram_split_tiles", "wlc_gram_ws_bytes", "wlc_gram", "wlc_gram_work", "wlc_snr2_lmax", "wlc_pca", "wlc_snr2_structured", "wlc_plan_set_timing",
             "wlc_plan_timings",
             "wlc_plan_kernel_stats", "wlc_last_error"]
 PHASES = ["tables", "abuild", "gram", "assemble", "snr_prep", "chol"]
@@ -156,6 +159,10 @@ def wlc_plan_index(plan, tri, rows, distinct):
     _check(lib.wlc_plan_index(plan, tri, rows, distinct))
 
 
+def wlc_plan_gram_order(plan, pos):
+    _check(lib.wlc_plan_gram_order(plan, pos))
+
+
 def wlc_plan_averaging(plan, off, legs, ell, w):
     _check(lib.wlc_plan_averaging(plan, off, legs, ell, w))
 
@@ -202,10 +209,17 @@ def wlc_gram_ws_bytes(precision, n, k):
     return b.value
 
 
-def wlc_gram(precision, n, k, a_hi, a_lo, panel_f, lim, g, ws, stream):
+def wlc_gram(precision, n, k, a_hi, a_lo, panel_f, lim, g, ws, stream, panel_ext=None):
     """Enqueue the lower 256-tiles of A A^T (FP32, DEVICE g [n_pad][n_pad]) of a
     k-blocked bf16 factor (DEVICE a_hi, a_lo; see include/wlcov.h)."""
-    _check(lib.wlc_gram(_prec(precision), int(n), int(k), a_hi, a_lo, panel_f, float(lim), g, ws, stream))
+    _check(lib.wlc_gram(_prec(precision), int(n), int(k), a_hi, a_lo, panel_f, float(lim), panel_ext, g, ws, stream))
+
+
+def wlc_gram_work(plan, ws_run):
+    """(flops, MFMA flops, factor bytes) of the last run's one-halo product."""
+    a, b, c = ct.c_double(), ct.c_double(), ct.c_double()
+    _check(lib.wlc_gram_work(plan, ws_run, ct.byref(a), ct.byref(b), ct.byref(c)))
+    return a.value, b.value, c.value
 
 
 def wlc_snr2_lmax(plan, C, row_exp2, d, ws, stream, n_ell):
@@ -329,6 +343,10 @@ class Problem:
         self.torch.cuda.synchronize()
         return wlc_gram_split_tiles(self.plan, _ptr(self.ws))
 
+    def gram_work(self):
+        """(flops, MFMA flops, factor bytes) of the last run's one-halo product."""
+        return wlc_gram_work(self.plan, _ptr(self.ws))
+
     def snr2_lmax(self, stream=None):
         """(S/N)^2 of the data vector cut after each ell-bin (numpy array)."""
         if self.ws_snr is None:
@@ -379,6 +397,13 @@ class Problem:
         wlc_plan_index(self.plan, tri.ctypes.data_as(ct.c_void_p), rows.ctypes.data_as(ct.c_void_p),
                        distinct.ctypes.data_as(ct.c_void_p))
         return tri[:s.n_tri], rows, distinct
+
+    def gram_order(self):
+        """pos[e]: the row of the one-halo product that holds distinct row e."""
+        import numpy as np
+        pos = np.zeros(self.sizes.n_distinct, np.int32)
+        wlc_plan_gram_order(self.plan, pos.ctypes.data_as(ct.c_void_p))
+        return pos
 
     def lattice_counts(self, stream=None):
         torch = self.torch

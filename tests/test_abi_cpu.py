@@ -115,6 +115,30 @@ def test_invalid_config_rejected(bad):
     assert w.wlc_last_error()
 
 
+@pytest.mark.parametrize("preset,tomo", [("mid", "paper"), ("euclid5", "paper"), ("euclid5", "sorted")])
+def test_gram_order(preset, tomo):
+    """The bf16 products take the distinct rows stably by their lowest
+    redshift bin (a permutation); the others keep the distinct order."""
+    t = dict(synth.PRESETS[preset]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 0.3 * synth.RHO_CRIT
+    for prec in ("bf16", "bf16x3", "bf16_auto", "fp32", "fp64"):
+        plan = w.wlc_plan_create(w.make_config(t, prec, tomo))
+        s, _, rows, dist = _index(plan)
+        pos = np.zeros(s.n_distinct, np.int32)
+        w.wlc_plan_gram_order(plan, pos.ctypes.data_as(ct.c_void_p))
+        w.wlc_plan_destroy(plan)
+        ident = np.arange(s.n_distinct)
+        if not prec.startswith("bf16"):
+            assert np.array_equal(pos, ident)
+            continue
+        assert np.array_equal(np.sort(pos), ident)
+        z = rows[:, 5:8].astype(np.int64)
+        low = np.full(s.n_distinct, -1, np.int64)
+        low[dist] = np.where(z >= 0, z, 1 << 30).min(1)  # every data row of a distinct row has its bins
+        assert (low >= 0).all()
+        order = np.argsort(pos)  # distinct rows in product order
+        assert np.array_equal(order, np.lexsort((ident, low)))
+
+
 def test_precision_modes():
     t = dict(synth.PRESETS["tiny"]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 1e11
     for name, code in w.PRECISIONS.items():

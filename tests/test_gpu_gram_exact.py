@@ -9,7 +9,9 @@ product (lo lo^T dropped).
 The shapes cover one and several 256-row tiles, padding rows and columns, and
 split-K slices whose stage counts (32 columns each) take every residue mod 3
 of the one-product ring (three stage buffers) as well as slices too short for
-its steady state."""
+its steady state.  With panel extents, the factors hold NaN past each
+panel's extent: a product that read a column it must skip would not be
+finite."""
 import sys
 
 import numpy as np
@@ -75,15 +77,18 @@ def case(request, wl):
 
 def _run(wl, c, precision, panel_f=None, lim=0.0):
     n, k, n_pad = c["n"], c["k"], c["n_pad"]
+    ext = c.get("ext")
     dev = torch.device("cuda:0")
     ws_b = wl.wlc_gram_ws_bytes(precision, n, k)
     ws = torch.empty(max(ws_b, 256), dtype=torch.uint8, device=dev)
     g = torch.full((n_pad, n_pad), float("nan"), dtype=torch.float32, device=dev)
     pf = None if panel_f is None else torch.as_tensor(panel_f, dtype=torch.float64).to(dev)
+    pe = None if ext is None else torch.as_tensor(ext, dtype=torch.int32).to(dev)
     stream = torch.cuda.current_stream()
-    _say("case gram exact n=%d k=%d %s" % (n, k, precision))
+    _say("case gram exact n=%d k=%d %s ext %s" % (n, k, precision, ext))
     wl.wlc_gram(precision, n, k, wl._ptr(c["a_hi"]), wl._ptr(c["a_lo"]), wl._ptr(pf) if pf is not None else None,
-                lim, wl._ptr(g), wl._ptr(ws), wl._stream_handle(stream))
+                lim, wl._ptr(g), wl._ptr(ws), wl._stream_handle(stream),
+                panel_ext=wl._ptr(pe) if pe is not None else None)
     torch.cuda.synchronize()
     return g.cpu().numpy().astype(np.float64)
 
@@ -127,3 +132,63 @@ def test_upper_tiles_untouched(wl, case):
         pytest.skip("one tile")
     G = _run(wl, case, "bf16")
     assert np.isnan(G[0:256, 256:512]).all()
+
+
+# Panel extents: the rows of panel I are zero from column 32 ext_I on, and the
+# k-blocked factors hold NaN there, which the product must not read.
+EXT_CASES = [(200, 4000), (1280, 33024), (1100, 34816)]
+BF16_NAN = 0x7FC0
+
+
+def _extents(nt, nb):
+    """Full, about half, one block, none (a panel of zeros), all but five."""
+    if nt == 1:
+        return [nb // 2 + 3]
+    pattern = [nb, nb // 2 + 3, 1, 0, nb - 5]
+    return [pattern[I % len(pattern)] for I in range(nt)]
+
+
+@pytest.fixture(scope="module", params=EXT_CASES, ids=["n%d_k%d" % c for c in EXT_CASES])
+def ext_case(request, wl):
+    n, k = request.param
+    rng = np.random.default_rng(20190220 + n + k)
+    n_pad, k_pad = -(-n // 256) * 256, -(-k // 64) * 64
+    nt, nb = n_pad // 256, k_pad // 32
+    ext = _extents(nt, nb)
+    hi = rng.integers(-8, 9, size=(n, k)).astype(np.float64)
+    lo = rng.integers(-4, 5, size=(n, k)).astype(np.float64)
+    for I in range(nt):
+        hi[256 * I:256 * I + 256, 32 * ext[I]:] = 0.0
+        lo[256 * I:256 * I + 256, 32 * ext[I]:] = 0.0
+
+    def blocked(x):
+        b = _kblocked(_bf16_bits(x), n_pad, k_pad).reshape(nb, n_pad, 32)
+        for I in range(nt):
+            b[ext[I]:, 256 * I:256 * I + 256, :] = BF16_NAN
+        return b.reshape(-1)
+
+    dev = torch.device("cuda:0")
+    a_hi = torch.from_numpy(blocked(hi).view(np.int16)).to(dev)
+    a_lo = torch.from_numpy(blocked(lo).view(np.int16)).to(dev)
+    hh = np.zeros((n_pad, n_pad))
+    hl = np.zeros((n_pad, n_pad))
+    hh[:n, :n] = hi @ hi.T
+    hl[:n, :n] = hi @ lo.T
+    return dict(n=n, k=k, n_pad=n_pad, ext=ext, a_hi=a_hi, a_lo=a_lo, hh=hh, split=hh + hl + hl.T)
+
+
+def test_extent_one_product_exact(wl, ext_case):
+    G = _run(wl, ext_case, "bf16")
+    _check_tiles(G, lambda I, J: ext_case["hh"], ext_case["n_pad"])
+
+
+def test_extent_split_product_exact(wl, ext_case):
+    G = _run(wl, ext_case, "bf16x3")
+    _check_tiles(G, lambda I, J: ext_case["split"], ext_case["n_pad"])
+
+
+def test_extent_per_tile_choice_exact(wl, ext_case):
+    nt = ext_case["n_pad"] // 256
+    F = np.array([1.0 if I % 2 else 0.1 for I in range(nt)])
+    G = _run(wl, ext_case, "bf16_auto", panel_f=F, lim=0.5)
+    _check_tiles(G, lambda I, J: ext_case["split"] if F[I] * F[J] > 0.5 else ext_case["hh"], ext_case["n_pad"])

@@ -98,14 +98,16 @@ def test_mixed_precision_euclid5(env, precision, tol_diag, tol_off, tol_snr):
 # ---------------------------------------------------------------- per-tile precision
 def _panel_shares(o, prob):
     """F_I: the largest one-halo share C1h_aa / C_aa of the data rows whose
-    distinct row lies in 256-row panel I, from the oracle's FP64 diagonal."""
+    distinct row lies in 256-row panel I of the product's row order, from the
+    oracle's FP64 diagonal; and the panel of each data row."""
     idx = np.arange(o.N)
     pairs = np.stack([idx, idx], 1)
     f = o.cov1h_pairs(pairs) / o.cov_pairs(pairs)
     _, _, dist = prob.index()
+    pan = prob.gram_order()[dist] // 256
     F = np.zeros((prob.sizes.n_distinct + 255) // 256)
-    np.maximum.at(F, dist // 256, f)
-    return F, dist
+    np.maximum.at(F, pan, f)
+    return F, pan
 
 
 def _tile_bound(F, k_len):
@@ -157,17 +159,17 @@ def test_auto_limits(env, tol, other):
 
 
 def test_auto_mixed_tiles_euclid5(env):
-    """With a bound of 1e-6 the five tiles whose one-product bound exceeds it
-    (the ones touching the first panel's large one-halo share) take the split
-    product and the others one product: every entry equals the bf16x3 or the
-    bf16 result of its tile, and every entry is within the bound of the
-    oracle (relative to sqrt(C_aa C_bb), plus the FP32 storage of C)."""
+    """With a bound of 1e-6 the tiles whose one-product bound exceeds it (the
+    ones touching the panels of large one-halo share) take the split product
+    and the others one product: every entry equals the bf16x3 or the bf16
+    result of its tile, and every entry is within the bound of the oracle
+    (relative to sqrt(C_aa C_bb), plus the FP32 storage of C)."""
     wl, t, ref = env
     tol = 1e-6
     _say("case precision euclid5 bf16_auto mixed tiles (tol %g)" % tol)
     o = oracle.Oracle(t)
     pa = wl.Problem(t.cfg, t.arrays(), precision="bf16_auto", gram_tol=tol)
-    F, dist = _panel_shares(o, pa)
+    F, pan = _panel_shares(o, pa)
     split = _tile_bound(F, pa.sizes.k_len) > tol
     n_split = int(np.sum(np.tril(split)))
     _say("  split tiles %d of %d" % (n_split, split.shape[0] * (split.shape[0] + 1) // 2))
@@ -181,7 +183,6 @@ def test_auto_mixed_tiles_euclid5(env):
         torch.cuda.synchronize()
         runs[prec] = p.covariance_true()
         p.close()
-    pan = dist // 256
     use_x3 = split[pan[:, None], pan[None, :]]
     want = np.where(use_x3, runs["bf16x3"], runs["bf16"])
     assert np.array_equal(Ca, want)
