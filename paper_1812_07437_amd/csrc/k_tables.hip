@@ -521,9 +521,10 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
 // wavefront takes every fourth k-block of the block; in one, lane l converts
 // 8 consecutive k (chunk l % 4) of the rows l / 4 + 16 j, j < AB_RW, so that
 // each of its stores writes 16 whole rows of the k-block, 1 KB contiguous.
-// Consecutive distinct rows mostly share their configuration, so a lane's
-// 8 values of G serve all its rows of one configuration, and T is taken once
-// per row and chi node.  When N_M is a multiple of 8 a chunk lies in one chi
+// Rows of one configuration are consecutive (in the A-row order of the bf16
+// products, those of one lowest redshift bin), so a lane's 8 values of G
+// serve all its rows of one configuration, and T is taken once per row and
+// chi node.  When N_M is a multiple of 8 a chunk lies in one chi
 // node, and T of the workgroup's rows and G of its configurations (at most
 // AB_GC of them) are staged in LDS with coalesced loads; otherwise the values
 // are taken one by one from global memory.
@@ -533,10 +534,11 @@ constexpr int AB_RW = 4;
 // AB_KB 32 / N_M + 1 nodes at most (33 for N_M >= 32); more go to global memory
 constexpr int AB_TN = 40;
 // configurations whose G a workgroup stages in LDS, pass by pass (a pass is
-// the four k-blocks the wavefronts convert together): 64 consecutive
-// distinct rows span at most three when a configuration holds 55 rows or
-// more (n_z >= 10); smaller ones take the global path
-constexpr int AB_GC = 3;
+// the four k-blocks the wavefronts convert together): in the A-row order at
+// n_z = 10, 64 rows of one lowest bin z span at most eight configurations
+// for z <= 6 (10 or more rows each); wider spans take the global path
+// (measured at large10: 1.58 ms with 6 or 8, 1.63 with 3, 1.82 with 12)
+constexpr int AB_GC = 8;
 
 // Two floats to packed bf16, rounded to nearest even (v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint32_t pack_bf16_rne(float a, float b) {
