@@ -884,8 +884,10 @@ int wlc_gram_split_tiles(wlc_plan plan, const void *ws_run, int64_t *split, int6
   if (p.cfg.precision != WLC_BF16_AUTO) return WLC_OK;
   const Layout L = run_layout(p);
   std::vector<double> F((size_t)np);
-  int rc = hip_check(hipMemcpy(F.data(), static_cast<const char *>(ws_run) + L.off[B_FP], (size_t)np * 8,
-                               hipMemcpyDeviceToHost), "split plan copy");
+  int rc = hip_check(hipDeviceSynchronize(), "split plan sync");  // the run may be on any stream
+  if (!rc)
+    rc = hip_check(hipMemcpy(F.data(), static_cast<const char *>(ws_run) + L.off[B_FP], (size_t)np * 8,
+                             hipMemcpyDeviceToHost), "split plan copy");
   if (rc) return rc;
   const double lim = split_lim(p);
   int64_t n = 0;
@@ -942,6 +944,8 @@ int wlc_gram_work(wlc_plan plan, const void *ws_run, double *flops, double *mfma
     return WLC_OK;
   }
   const Layout L = run_layout(p);
+  int src = hip_check(hipDeviceSynchronize(), "gram work sync");  // the run may be on any stream
+  if (src) return src;
   const bool f64 = prec == WLC_FP64 && p.r_pad % 256 == 0;  // the FP64 product covers 128 x 256 tiles
   const int64_t tile = (prec == WLC_FP64 || prec == WLC_FP32) ? 128 : GRAM_TILE, np = p.r_pad / tile;
   std::vector<int32_t> ext;
