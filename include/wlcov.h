@@ -58,7 +58,8 @@ enum { WLC_TOMO_PAPER = 0, WLC_TOMO_SORTED = 1 };
  * BF16_AUTO: per 256 x 256 tile of the product, the split product where an
  *            a-priori bound needs it and one bf16 product elsewhere.  With
  *            f_a the one-halo share of the diagonal entry C_aa (in FP64, before
- *            the product) and F_I the largest f_a of the rows of panel I, a
+ *            the product) and F_I the largest f_a of the rows of panel I (256
+ *            rows of the product's row order, wlc_plan_gram_order), a
  *            single bf16 product changes an entry of tile (I, J) by at most
  *            (2u + u^2 + K 2^-24) sqrt(F_I F_J) sqrt(C_aa C_bb) (u = 2^-8
  *            for bf16 operands, K 2^-24 for the FP32 accumulation of K
