@@ -293,13 +293,15 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs A, const int32_t *__re
     tileT[ra][cb] = v;
   }
   __syncthreads();
-  // transposed half: C[b][a] for the same pairs, rows of the output contiguous
+  // transposed half: C[b][a] for the same pairs, rows of the output contiguous,
+  // with non-temporal stores (measured 1 ms faster at N = 82575; both halves
+  // non-temporal was 2 ms slower)
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int rb = rbase + q;  // row of the transposed tile (b index)
     const int ca = cb;         // column (a index)
     const int64_t bb = b0 + rb, aa = a0 + ca;
-    if (aa < A.n && bb < A.n && aa > bb) C[bb * A.n + aa] = tileT[ca][rb];
+    if (aa < A.n && bb < A.n && aa > bb) __builtin_nontemporal_store(tileT[ca][rb], &C[bb * A.n + aa]);
   }
 }
 

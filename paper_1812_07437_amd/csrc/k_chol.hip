@@ -25,6 +25,7 @@ constexpr int64_t PART_ROWS = 524288;  // split-k scratch: slices x rows of 256 
 // ------------------------------------------------------------- prepare
 // Lower triangle of M from the scaled covariance (f32 or f64) and d: one
 // block per row and PREP_COLS columns, blocks right of the row's end exit.
+// M is written with non-temporal stores (it is far larger than the caches).
 constexpr int PREP_COLS = 2048;
 template <typename InT>
 __global__ void k_chol_prep(const InT *__restrict__ C, const int32_t *__restrict__ t, const double *__restrict__ d,
@@ -39,7 +40,7 @@ __global__ void k_chol_prep(const InT *__restrict__ C, const int32_t *__restrict
     const int64_t j = jb + q * 256 + threadIdx.x;
     if (j <= i && j < n) {
       const int64_t pj = perm ? perm[j] : j;
-      Wm[i * ld + j] = i < n ? (double)C[pi * n + pj] : ldexp(d[pj], t[pj]);
+      __builtin_nontemporal_store(i < n ? (double)C[pi * n + pj] : ldexp(d[pj], t[pj]), &Wm[i * ld + j]);
     }
   }
 }
