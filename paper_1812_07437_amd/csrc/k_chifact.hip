@@ -163,7 +163,9 @@ __global__ __launch_bounds__(256) void k_chifact(const double *__restrict__ Ts, 
         for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
     }
   }
-  // accumulator value v of lane l: row l / 16 + 4 v, column l % 16
+  // accumulator value v of lane l: row l / 16 + 4 v, column l % 16; the
+  // product is written non-temporal (the later kernels then run 2.6 ms faster
+  // at large10: fewer dirty lines left to write back under them)
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void k_chifact(const double *__restrict__ Ts, 
       for (int v = 0; v < 4; ++v) {
         const int r = wr + x * 16 + (lane >> 4) + 4 * v;
         const int c = wc + y * 16 + (lane & 15);
-        if (r < A.cnt && c < B.cnt) out[(A.e0 + r) * ld + B.e0 + c] = acc[x][y][v];
+        if (r < A.cnt && c < B.cnt) __builtin_nontemporal_store(acc[x][y][v], &out[(A.e0 + r) * ld + B.e0 + c]);
       }
 }
 

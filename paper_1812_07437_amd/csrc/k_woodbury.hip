@@ -427,7 +427,8 @@ __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
         for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
     }
   }
-  // accumulator value v of lane l: row l / 16 + 4 v, column l % 16
+  // accumulator value v of lane l: row l / 16 + 4 v, column l % 16; W goes
+  // out non-temporal (fewer dirty lines under the kernels after it)
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(256) void k_wb_prod(WbArgs a) {
         const int64_t f = f0 + wc + y * 16 + (lane & 15);
         if (e >= nR || f >= nR) continue;
         if (MODE == 0) a.T[e * a.ld_t + f] = acc[x][y][v];
-        else if (e >= f) a.W[e * a.ld_w + f] = acc[x][y][v] + (e == f ? 1.0 : 0.0);
+        else if (e >= f) __builtin_nontemporal_store(acc[x][y][v] + (e == f ? 1.0 : 0.0), &a.W[e * a.ld_w + f]);
       }
 }
 
