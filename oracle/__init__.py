@@ -8,6 +8,10 @@ The combinatorics (ell-bins, triangles, tomographic orderings, counts) are
 plain Python here; the heavy sums are plain C in ``wlc_oracle.c`` (built with
 gcc, loaded through ctypes).  Each function cites the passage of Rizzato et
 al. (2019), arXiv 1812.07437, that it writes out.
+
+Parity unpinned: the B_G2 term of the bispectrum response (eq. RespB).  The
+paper never defines B_G2; the tidal-kernel reading in ``wlc_oracle.c`` is
+checked only against its own closed-form values, not against the paper.
 """
 from __future__ import annotations
 

@@ -18,6 +18,11 @@
  *
  * Readings of points the paper leaves open (grids, interpolation, the
  * undefined B_G2, the super-sample form) are stated where they are used.
+ *
+ * Parity unpinned: the B_G2 term of the bispectrum response.  The paper uses
+ * B_G2 without defining it; the tidal-kernel reading below is pinned only to
+ * itself (its values at the equilateral and right-isosceles triangles), not
+ * to anything the paper fixes.
  */
 #include <math.h>
 #include <stdint.h>

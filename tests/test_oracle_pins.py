@@ -190,6 +190,35 @@ def test_bispectrum_equilateral_polynomial():
     assert np.allclose(RB, quad * P ** 2 + lin * P + I30, rtol=1e-11)
 
 
+def test_bispectrum_right_isosceles_closed_form():
+    """Right isosceles triangle k1 = k2 = k, k3 = sqrt(2) k (k1 perpendicular to
+    k2): from the geometry alone the cosines are mu_12 = 0 and mu_13 = mu_23 =
+    -1/sqrt(2), so F2(k1, k2) = 5/7 and F2(k1, k3) = F2(k2, k3) = 5/7 - 3/4 + 1/7
+    = 3/28, and the tidal kernel mu^2 - 1 is -1 on the perpendicular pair and
+    -1/2 on the other two.  With u = 1 and b1 = 1 (I_1^1 = 1, I_2^1 = I_2^0,
+    I_3^1 = I_3^0, b2 = 0 so I_2^2 = 0) and P = A k^alpha, the tree-level
+    bispectrum and its response (eq. RespB under the tidal-kernel reading of
+    B_G2, with the dilation sum_i dB_PT/dln k_i = 2 alpha B_PT of a power law)
+    follow in closed form.  Unlike the equilateral case, every pair of legs has
+    its own cosine here, so a cosine taken between the wrong legs fails."""
+    alpha = -1.3
+    o, _ = _uniform_profile_oracle(alpha=alpha)
+    I20 = o.halo_I(2, 0, [0.1, 0.1])
+    I30 = o.halo_I(3, 0, [0.1, 0.1, 0.1])
+    r2 = math.sqrt(2.0)
+    for k in (0.05, 0.2, 0.7):
+        kv = [k, k, r2 * k]
+        P1 = 1e4 * k ** alpha
+        P3 = 1e4 * (r2 * k) ** alpha
+        b_pt = 2.0 * (5.0 / 7.0 * P1 * P1 + 2.0 * 3.0 / 28.0 * P1 * P3)
+        b_g2 = 2.0 * (-1.0 * P1 * P1 + 2.0 * (-0.5) * P1 * P3)
+        X, R = o.spectrum(0, kv)
+        assert X == pytest.approx(b_pt + I20 * (2.0 * P1 + P3) + I30, rel=1e-11)
+        r_lin = (47.0 / 21.0 - alpha / 3.0) * (2.0 * P1 + P3)
+        want = 433.0 / 126.0 * b_pt + 5.0 / 126.0 * b_g2 - 2.0 * alpha * b_pt / 3.0 + I20 * r_lin + I30
+        assert R == pytest.approx(want, rel=1e-11)
+
+
 def test_bispectrum_scaling_generic_triangle():
     """For P = A k^alpha the tree-level part scales as lambda^(2 alpha)."""
     alpha = -1.2
