@@ -740,19 +740,34 @@ void launch_gram_unpermute(const float *GP, const int32_t *pos, int64_t n, int64
   hipLaunchKernelGGL(k_gram_unpermute, dim3((unsigned)(nt * nt)), dim3(256), 0, s, GP, pos, n, ld, G);
 }
 
-// Slices of K per tile: enough workgroups to cover the chip several times.
-// The bf16 kernels, whose time is set by their operand stream, also take two
-// slices on large problems (measured 5 % faster at 33280 rows and K = 131072
-// with the slice-outer order of gram_work, at the cost of one more Gram-sized
-// buffer).
+// Slices of K per tile.  Every slice beyond the first costs a Gram-sized
+// partial buffer, its reduction and, per work item, a ring start-up and a
+// 256 KB tile store.  The bf16 kernels run one 512-thread workgroup per CU;
+// measured on the 256 x 128 (chi, M) grid (K = 32768) from 10 to 8515 tiles
+// and at K = 131072, small products want few, long items: at 55 tiles one
+// product took 0.23 ms with four slices and 0.96 ms with 32; at 90-230 tiles
+// three or four slices were best, at 465-1275 tiles two; from about 2000
+// tiles one slice is as fast as two or faster (11.5 against 12.1 ms at 8515
+// tiles and K = 32768, equal at K = 131072) and needs no partial buffer.  The
+// split product liked the same counts or somewhat more (8 below 100 tiles),
+// within 2 % of its best beyond.  All bf16 modes take the same count, so a
+// per-tile product (WLC_BF16_AUTO) sums each tile exactly as the one-product
+// or the split-product mode would.  Each slice keeps at least 64 k-blocks.
+// The FP32 and FP64 kernels aim at enough workgroups to cover the chip
+// several times, with at least 4 K-steps per slice.
 static int pick_split(int64_t n_tiles, int64_t k_pad, int bk, bool bf16) {
-  const int64_t target = 2048;  // workgroups to cover 256 CUs several times
-  int64_t s = (target + n_tiles - 1) / n_tiles;
   const int64_t kb = k_pad / bk;
-  if (bf16 && s < 2 && kb >= 256) s = 2;
-  if (s > kb / 4) s = kb / 4;  // keep at least 4 K-steps per slice
-  if (s < 1) s = 1;
-  if (s > 32) s = 32;
+  int64_t s;
+  if (bf16) {
+    s = n_tiles >= 2048 ? 1 : std::clamp<int64_t>((600 + n_tiles - 1) / n_tiles, 2, 4);
+    s = std::min<int64_t>(s, std::max<int64_t>(1, kb / 64));
+  } else {
+    const int64_t target = 2048;  // workgroups to cover 256 CUs several times
+    s = (target + n_tiles - 1) / n_tiles;
+    if (s > kb / 4) s = kb / 4;  // keep at least 4 K-steps per slice
+    if (s < 1) s = 1;
+    if (s > 32) s = 32;
+  }
   return (int)s;
 }
 

@@ -239,7 +239,12 @@ def test_gram_arguments_rejected():
     """wlc_gram checks its arguments before anything touches the device (the
     pointers below are never dereferenced: every case fails a check first)."""
     assert w.wlc_gram_ws_bytes("bf16", 256, 64) == 0
-    assert w.wlc_gram_ws_bytes("bf16", 33165, 131072) == 33280 * 33280 * 4  # two k-slices
+    # one k-slice from about 2000 tiles on, for every bf16 mode
+    assert w.wlc_gram_ws_bytes("bf16", 33165, 131072) == 0
+    assert w.wlc_gram_ws_bytes("bf16x3", 33165, 131072) == 0
+    # 55 tiles of the Euclid-like shape: four slices
+    assert w.wlc_gram_ws_bytes("bf16", 2390, 32768) == 3 * 2560 * 2560 * 4
+    assert w.wlc_gram_ws_bytes("bf16x3", 2390, 32768) == 3 * 2560 * 2560 * 4
     fake = 4096  # a non-null, 256-byte-aligned stand-in
     bad = [
         dict(precision="fp64"), dict(precision="fp32"), dict(n=0), dict(k=0), dict(n=(1 << 20) + 1),

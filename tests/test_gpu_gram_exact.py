@@ -8,8 +8,10 @@ product (lo lo^T dropped).
 
 The shapes cover one and several 256-row tiles, padding rows and columns, and
 split-K slices whose stage counts (32 columns each) take every residue mod 3
-of the one-product ring (three stage buffers) as well as slices too short for
-its steady state.  With panel extents, the factors hold NaN past each
+of the one-product ring (three stage buffers) and both parities of the split
+product's two stage buffers, as well as slices too short for the ring's
+steady state (two stages; with panel extents, slices of one stage and empty
+ones).  With panel extents, the factors hold NaN past each
 panel's extent: a product that read a column it must skip would not be
 finite."""
 import sys
@@ -20,15 +22,17 @@ import pytest
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-# (n, k): stage counts per slice, with the split-K choice of the library
-# (two k-slices at least on long products, at most 32, at least 4 stages each)
+# (n, k): stage counts per slice with the split-K choice of the library (the
+# same for every bf16 mode; the one-product ring has three stage buffers, the
+# split product two)
 CASES = [
     (256, 64),      # one tile, one slice of 2 stages
-    (256, 2048),    # one tile, 16 slices of 4 stages
-    (200, 4000),    # padding rows and columns (k_pad 4032): slices of 5 stages and one of 1
-    (1280, 32768),  # 15 tiles, 32 slices of 32 stages (32 = 2 mod 3)
-    (1280, 33024),  # 31 slices of 33 stages (0 mod 3) and one of 9
-    (1100, 34816),  # padding rows, slices of 34 stages (1 mod 3)
+    (256, 2048),    # one slice of 64 stages (1 mod 3, even)
+    (200, 4000),    # padding rows and columns (k_pad 4032): one slice of 126 (0 mod 3)
+    (1280, 32768),  # 15 tiles: four slices of 256 (1 mod 3)
+    (1280, 33024),  # four slices of 258 (0 mod 3)
+    (1100, 34816),  # padding rows: four slices of 272 (2 mod 3)
+    (768, 8320),    # 6 tiles: four slices of 65 (2 mod 3, odd)
 ]
 
 
