@@ -123,9 +123,9 @@ struct Slot {
   bool busy = false;
 };
 
-// Products below this many work units (items x k per item) go to the
-// narrow batch lane: at the serving grid (K = 32768) that is every request
-// but the largest few (n_z >= 7 with l_max = 5000).
+// Products below this many work units (items x k per item, about tiles x K)
+// go to the narrow batch lane: at the serving grid (K = 32768, 512 tiles) that
+// is every request but the largest (n_z = 7 with l_max >= 3000, and n_z = 10).
 constexpr double LANE_SPLIT = 16777216.0;
 constexpr int MAX_BATCH = 64;
 
