@@ -4,8 +4,11 @@ times: n_z = 10, 15 ell-bins over 10-5000, N_chi x N_M = 512 x 256
 
 The oracle evaluates the data vector and response entirely and the
 covariance on seeded samples, one entry at a time.  The FP64 GPU path must
-match it to 1e-10; the split-bf16 (bf16x3) path to 1e-5 on the diagonal and
-on off-diagonal entries relative to sqrt(C_aa C_bb).  The oracle's Cholesky
+match it to 1e-10; the split-bf16 (bf16x3) path and the per-tile precision
+the benchmark runs (bf16_auto: one bf16 product on every tile whose
+a-priori bound is within 2^-17 of sqrt(C_aa C_bb), which at this size is
+every tile) to 1e-5 on the diagonal and on off-diagonal entries relative to
+sqrt(C_aa C_bb).  The oracle's Cholesky
 cannot reach N = 82575, so the mixed-precision S/N is compared with the FP64
 GPU path's, which the smaller workloads pin to the oracle."""
 import sys
@@ -77,7 +80,7 @@ def _check(prob, ref, tol_diag, tol_off):
     assert err_o < tol_off
 
 
-def test_large10_fp64_chi_and_bf16x3(wl, ref):
+def test_large10_fp64_chi_and_mixed(wl, ref):
     t = ref["t"]
     _say("case large10 fp64")
     p64 = wl.Problem(t.cfg, t.arrays(), precision="fp64")
@@ -120,6 +123,21 @@ def test_large10_fp64_chi_and_bf16x3(wl, ref):
     assert abs(snr_st - snr64) / snr64 < 1e-4
     pm.close()
     del pm
+    torch.cuda.empty_cache()
+
+    _say("case large10 bf16_auto (the benchmark's precision)")
+    pa = wl.Problem(t.cfg, t.arrays(), precision="bf16_auto")
+    pa.run()
+    snr = pa.snr2()
+    torch.cuda.synchronize()
+    split, tiles = pa.split_tiles()
+    _say("  split tiles %d of %d" % (split, tiles))
+    assert tiles == 130 * 131 // 2 and split == 0
+    _check(pa, ref, 1e-5, 1e-5)
+    _say("  (S/N)^2 bf16_auto %.9e fp64 %.9e" % (snr, snr64))
+    assert abs(snr - snr64) / snr64 < 1e-4
+    pa.close()
+    del pa
     torch.cuda.empty_cache()
 
 
