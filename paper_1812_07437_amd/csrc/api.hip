@@ -108,7 +108,7 @@ static Layout run_layout(const Plan &p) {
     sz[B_AROW] = p.arow.size() * 4;
     sz[B_POS] = p.pos.size() * 4;
     sz[B_EXT] = (size_t)(p.r_pad / GRAM_TILE) * 4;
-    sz[B_GP] = (size_t)p.r_pad * p.r_pad * 4;
+    sz[B_GP] = (size_t)p.r_pad * p.r_pad * (c.precision == WLC_FP64 ? 8 : 4);
   }
   if (c.precision == WLC_BF16_AUTO) {  // the per-tile precision plan
     sz[B_SQ] = (size_t)n_cfg * c.n_chi * 8;
@@ -181,7 +181,7 @@ size_t snr_structured_ws_bytes(const Plan &p) {
          align_up(chol_scratch_bytes(n), 256) + 256 + 256;
 }
 
-// The A-row order of the bf16 products: distinct rows by their lowest
+// The A-row order of the bf16 and FP64 products: distinct rows by their lowest
 // redshift bin (rows hold their bins in increasing order), stably.  The
 // factor of a row vanishes beyond the far edge of its lowest bin (eq.
 // KernelLensing1: W_i(chi) = 0 past the sources of bin i), so panels of rows
@@ -191,7 +191,7 @@ static void order_arows(Plan &p) {
   p.arow.clear();
   p.pos.clear();
   const int prec = p.cfg.precision;
-  if (prec != WLC_BF16 && prec != WLC_BF16X3 && prec != WLC_BF16_AUTO) return;
+  if (prec != WLC_BF16 && prec != WLC_BF16X3 && prec != WLC_BF16_AUTO && prec != WLC_FP64) return;
   const int nz = p.cfg.n_z;
   std::vector<int64_t> start((size_t)nz + 1, 0);
   for (int64_t e = 0; e < p.n_R; ++e) ++start[(size_t)p.rowR[4 * e + 1] + 1];
@@ -411,7 +411,7 @@ int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t
   if (ssc_chi) launch_sigma_w2(T, theta_sky(p), sw, s);
   launch_gfactor(T, cfgT, n_cfg, sl, U, R, sw, std::sqrt(p.omega), n_mg, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
-  const bool arows = !p.arow.empty();  // the bf16 products run on A-rows in their own order
+  const bool arows = !p.arow.empty();  // the bf16 and FP64 products run on A-rows in their own order
   const int32_t *arow = arows ? at<int32_t>(ws, L, B_AROW) : nullptr;
   const int32_t *pos = arows ? at<int32_t>(ws, L, B_POS) : nullptr;
   int32_t *ext = arows ? at<int32_t>(ws, L, B_EXT) : nullptr;
@@ -456,8 +456,9 @@ static double split_lim(const Plan &p) {
   return (tol / eps) * (tol / eps);
 }
 
-// The product of the bf16 modes goes to GP (A-row order) and is put back in
-// the distinct-row order by run_enqueue_back; the others write G directly.
+// The product of the bf16 modes and FP64 goes to GP (A-row order) and is put
+// back in the distinct-row order by run_enqueue_back; the others write G
+// directly.
 static void *gram_out(const Plan &p, void *ws, const Layout &L) {
   return at<void>(ws, L, p.arow.empty() ? B_GM : B_GP);
 }
@@ -536,9 +537,9 @@ int run_enqueue_back(const Plan &p, const wlc_tables &tb, void *ws, double *d, d
   if (p.arow.empty()) {
     launch_gram_mirror(a.gm_f32, Gm, p.n_R, p.r_pad, s);
   } else {  // the product of the A-rows, made symmetric, back in the distinct-row order
-    float *GP = at<float>(ws, L, B_GP);
-    launch_gram_mirror(1, GP, p.r_pad, p.r_pad, s);
-    launch_gram_unpermute(GP, at<int32_t>(ws, L, B_POS), p.n_R, p.r_pad, (float *)Gm, s);
+    void *GP = at<void>(ws, L, B_GP);
+    launch_gram_mirror(a.gm_f32, GP, p.r_pad, p.r_pad, s);
+    launch_gram_unpermute(a.gm_f32, GP, at<int32_t>(ws, L, B_POS), p.n_R, p.r_pad, Gm, s);
   }
   launch_rowexp(a, row_exp2, d, r, s);
   launch_assemble(a, row_exp2, C, s);
@@ -946,8 +947,8 @@ int wlc_gram_work(wlc_plan plan, const void *ws_run, double *flops, double *mfma
   const Layout L = run_layout(p);
   int src = hip_check(hipDeviceSynchronize(), "gram work sync");  // the run may be on any stream
   if (src) return src;
-  const bool f64 = prec == WLC_FP64 && p.r_pad % 256 == 0;  // the FP64 product covers 128 x 256 tiles
-  const int64_t tile = (prec == WLC_FP64 || prec == WLC_FP32) ? 128 : GRAM_TILE, np = p.r_pad / tile;
+  // 256-row panels: the units of the panel extents and of the per-tile precision
+  const int64_t np = p.r_pad / GRAM_TILE;
   std::vector<int32_t> ext;
   if (!p.arow.empty()) {
     ext.resize((size_t)np);
@@ -962,29 +963,40 @@ int wlc_gram_work(wlc_plan plan, const void *ws_run, double *flops, double *mfma
                                  hipMemcpyDeviceToHost), "split plan copy");
     if (rc) return rc;
   }
-  const double lim = split_lim(p), t2 = 2.0 * (double)tile * (double)tile;
+  // k summed by a tile of panels I and J: up to the shorter extent, or all of K
+  auto k_of = [&](int64_t I, int64_t J) {
+    return ext.empty() ? (double)p.k_pad : (double)GRAM_KB * std::min(ext[(size_t)I], ext[(size_t)J]);
+  };
+  const double lim = split_lim(p);
   double f = 0.0, m = 0.0;
-  for (int64_t I = 0; I < np; ++I)
-    for (int64_t J = 0; J <= I; ++J) {
-      const double k = ext.empty() ? (double)p.k_pad : (double)GRAM_KB * std::min(ext[(size_t)I], ext[(size_t)J]);
-      const double one = t2 * k;
-      f += one;
-      const bool split = prec == WLC_BF16X3 || (prec == WLC_BF16_AUTO && F[(size_t)I] * F[(size_t)J] > lim);
-      m += split ? 3.0 * one : one;
-    }
-  if (f64) {  // J <= I / 2 in 128 x 256 tiles: the diagonal pairs add a quarter tile each
-    const double extra = (double)(np / 2) * 2.0 * 128.0 * 128.0 * (double)p.k_pad;
-    f += extra;
-    m += extra;
+  if (prec == WLC_FP64 && gram_f64_tiles(gram_shape(p))) {
+    // two 128 x 256 tiles (row halves of panel P) per panel pair P >= J
+    for (int64_t P = 0; P < np; ++P)
+      for (int64_t J = 0; J <= P; ++J) f += 2.0 * 2.0 * 128.0 * 256.0 * k_of(P, J);
+    m = f;
+  } else if (prec == WLC_FP64 || prec == WLC_FP32) {
+    // 128 x 128 tiles over the lower triangle, every k
+    const double nt = (double)(p.r_pad / 128);
+    f = m = nt * (nt + 1.0) / 2.0 * 2.0 * 128.0 * 128.0 * (double)p.k_pad;
+  } else {
+    const double t2 = 2.0 * (double)GRAM_TILE * (double)GRAM_TILE;
+    for (int64_t I = 0; I < np; ++I)
+      for (int64_t J = 0; J <= I; ++J) {
+        const double one = t2 * k_of(I, J);
+        f += one;
+        const bool split = prec == WLC_BF16X3 || (prec == WLC_BF16_AUTO && F[(size_t)I] * F[(size_t)J] > lim);
+        m += split ? 3.0 * one : one;
+      }
   }
   *flops = f;
   *mfma_flops = m;
   if (factor_bytes) {
     double b = 0.0;
-    if (ext.empty()) {
+    if (ext.empty() || prec == WLC_FP64) {  // the FP64 factor is written over all of K
       b = (double)p.n_R * (double)p.k_len * (prec == WLC_FP64 ? 8.0 : prec == WLC_FP32 ? 4.0 : 2.0);
     } else {  // the distinct rows lead the A-row order; a panel's rows end at its extent
       for (int64_t P = 0; P < np; ++P) {
+        const int64_t tile = GRAM_TILE;
         const double rows = (double)std::max<int64_t>(0, std::min<int64_t>(tile, p.n_R - P * tile));
         const double k = (double)std::min<int64_t>((int64_t)GRAM_KB * ext[(size_t)P], p.k_len);
         const bool lo = prec == WLC_BF16X3 || (prec == WLC_BF16_AUTO && F[(size_t)P] * F[(size_t)np] > lim);

@@ -648,19 +648,31 @@ __device__ __forceinline__ void f64_gram_tile(int64_t t, int &I, int &J) {
   J = (int)(u % (m + 1));
 }
 
+// With panel_ext (per 256-row panel the 32-column k-blocks where its rows can
+// be nonzero), tile (I, J) sums only the k-blocks where both of its panels
+// (the 256-row panel I / 2 and panel J) can be nonzero, and its slices split
+// that range evenly; an empty slice stores zeros.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gram_f64(
     const double *__restrict__ A, int64_t k_pad, int64_t lda, int64_t k_split, int n_split, int64_t n_work,
-    double *__restrict__ out, double *__restrict__ partial, int64_t ld, int64_t part_stride) {
-  // XCD x takes work items [x per, (x + 1) per), as in gram_work
-  const int64_t per = (int64_t)gridDim.x / N_XCD;
-  const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
+    double *__restrict__ out, double *__restrict__ partial, int64_t ld, int64_t part_stride,
+    const int32_t *__restrict__ panel_ext) {
+  // items dealt to the XCDs in chunks of GRAM_XC (one per resident
+  // workgroup), as gram_work<GRAM_XC> deals them: with panel extents the
+  // items of the later panels are longer, and contiguous runs per XCD left
+  // the last XCD 17 % more work than the mean at large10 (5 % dealt)
+  const int64_t x = blockIdx.x % N_XCD, j = blockIdx.x / N_XCD;
+  const int64_t w = (j / GRAM_XC) * (N_XCD * GRAM_XC) + x * GRAM_XC + j % GRAM_XC;
   if (w >= n_work) return;
   const int split = (int)(w % n_split);
   int I, J;
   f64_gram_tile(w / n_split, I, J);
   const int64_t row0 = (int64_t)I * FT_R, col0 = (int64_t)J * FT_S;
+  if (panel_ext) {
+    k_pad = min(k_pad, (int64_t)max(min(panel_ext[I >> 1], panel_ext[J]), 0) * GRAM_KB);
+    k_split = (k_pad / FT_K + n_split - 1) / n_split * FT_K;
+  }
   const int64_t kb = (int64_t)split * k_split;
-  const int64_t ke = min(k_pad, kb + k_split);
+  const int64_t ke = max(kb, min(k_pad, kb + k_split));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave / 4) * 64, wc = (wave % 4) * 64;
   f64x4 acc[4][4];
@@ -717,8 +729,9 @@ void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s) 
 // symmetric): G[e][f] = GP[pos[e]][pos[f]], in 64 x 64 tiles of G.  Within a
 // configuration the rows of one lowest bin are consecutive in both orders,
 // so a wavefront's 64 reads of one GP row fall in a few contiguous runs.
-__global__ __launch_bounds__(256) void k_gram_unpermute(const float *__restrict__ GP, const int32_t *__restrict__ pos,
-                                                       int64_t n, int64_t ld, float *__restrict__ G) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_unpermute(const T *__restrict__ GP, const int32_t *__restrict__ pos,
+                                                       int64_t n, int64_t ld, T *__restrict__ G) {
   __shared__ int32_t prow[64];
   const int64_t nt = (n + 63) / 64;
   const int64_t I = blockIdx.x / nt, J = blockIdx.x % nt;
@@ -735,9 +748,15 @@ __global__ __launch_bounds__(256) void k_gram_unpermute(const float *__restrict_
   }
 }
 
-void launch_gram_unpermute(const float *GP, const int32_t *pos, int64_t n, int64_t ld, float *G, hipStream_t s) {
+void launch_gram_unpermute(int f32, const void *GP, const int32_t *pos, int64_t n, int64_t ld, void *G,
+                           hipStream_t s) {
   const int64_t nt = (n + 63) / 64;
-  hipLaunchKernelGGL(k_gram_unpermute, dim3((unsigned)(nt * nt)), dim3(256), 0, s, GP, pos, n, ld, G);
+  if (f32)
+    hipLaunchKernelGGL(k_gram_unpermute<float>, dim3((unsigned)(nt * nt)), dim3(256), 0, s, (const float *)GP, pos,
+                       n, ld, (float *)G);
+  else
+    hipLaunchKernelGGL(k_gram_unpermute<double>, dim3((unsigned)(nt * nt)), dim3(256), 0, s, (const double *)GP, pos,
+                       n, ld, (double *)G);
 }
 
 // Slices of K per tile.  Every slice beyond the first costs a Gram-sized
@@ -780,6 +799,7 @@ static int gram_bk(int prec) { return prec == WLC_FP64 ? 16 : (prec == WLC_FP32 
 static bool f64_tiles(int prec, const GramShape &g) {
   return prec == WLC_FP64 && g.lda % 2 == 0 && (int64_t)FT_S * g.lda * 8 < ((int64_t)1 << 31) && g.r_pad % FT_S == 0;
 }
+bool gram_f64_tiles(const GramShape &g) { return f64_tiles(WLC_FP64, g); }
 static int64_t gram_tile_count(int prec, const GramShape &g) {
   if (f64_tiles(prec, g)) {
     const int64_t pairs = g.r_pad / FT_S;
@@ -895,7 +915,8 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
   const GramSplit q = gram_split(prec, g);
   const int64_t nt = q.nt, tiles = q.tiles, ksplit = q.ksplit, pstride = q.pstride, n_work = q.n_work;
   const int ns = q.ns;
-  const int64_t gq = is_bf16(prec) ? (int64_t)N_XCD * GRAM_XC : N_XCD;  // whole item groups (gram_work)
+  // whole item groups of the dealt schedules (gram_work<GRAM_XC>, k_gram_f64)
+  const int64_t gq = is_bf16(prec) || f64_tiles(prec, g) ? (int64_t)N_XCD * GRAM_XC : N_XCD;
   const dim3 grid((unsigned)((n_work + gq - 1) / gq * gq));
   const int nti = (int)nt;
   switch (prec) {
@@ -921,7 +942,7 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
     default:
       if (f64_tiles(prec, g)) {
         hipLaunchKernelGGL(k_gram_f64, grid, dim3(512), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, n_work,
-                           (double *)out, (double *)partial, g.ld_out, pstride);
+                           (double *)out, (double *)partial, g.ld_out, pstride, panel_ext);
         break;
       }
       hipLaunchKernelGGL(k_gram_x4<double>, grid, dim3(256), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, nti,

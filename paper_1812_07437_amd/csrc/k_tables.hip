@@ -454,13 +454,16 @@ void launch_twoleg(const DevTables &T, int n_ell, const double *U, double *G2, d
 // Row-major f64 / f32 ([r_pad][lda]): consecutive rows mostly share their
 // configuration, so each block holds 8 consecutive k of G_cfg per thread in
 // registers and writes them, times T_row, for AB_ROWS consecutive rows,
-// reloading G only where the configuration changes.
+// reloading G only where the configuration changes.  With arow, row r of A
+// is the distinct row arow[r] (zero where it is negative); every k is
+// written.
 constexpr int AB_ROWS = 16;
 
 template <int FMT>
 __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR, const double *__restrict__ Ts,
                                                const double *__restrict__ G, int64_t n_R, int n_chi, int n_m,
-                                               int64_t k_pad, int64_t lda, void *A0, void *A1) {
+                                               int64_t k_pad, int64_t lda, void *A0, void *A1,
+                                               const int32_t *__restrict__ arow) {
   const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
   if (k0 >= k_pad) return;
   const int64_t k_len = (int64_t)n_chi * n_m;
@@ -478,9 +481,10 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
   const int64_t r0 = (int64_t)blockIdx.y * AB_ROWS;
   for (int rr = 0; rr < AB_ROWS; ++rr) {
     const int64_t row = r0 + rr;
+    const int64_t e = arow ? (int64_t)arow[row] : (row < n_R ? row : -1);  // its distinct row
     double v[8];
-    if (row < n_R) {
-      const int c = rowR[4 * row];
+    if (e >= 0) {
+      const int c = rowR[4 * e];
       if (c != cc) {
         cc = c;
         const double *Gc = G + (size_t)c * k_len + k0;
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(256) void k_abuild(const int32_t *__restrict__ rowR
           for (int q = 0; q < 8; ++q) g[q] = nq[q] >= 0 ? Gc[q] : 0.0;
         }
       }
-      const double *Tr = Ts + (size_t)row * n_chi;
+      const double *Tr = Ts + (size_t)e * n_chi;
 #pragma unroll
       for (int q = 0; q < 8; ++q) v[q] = nq[q] >= 0 ? Tr[nq[q]] * g[q] : 0.0;
     } else {
@@ -739,9 +743,9 @@ void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double 
   // r_pad is a multiple of AB_ROWS (rows are padded to the Gram tile)
   const dim3 grid((unsigned)((k_pad / 8 + 255) / 256), (unsigned)((r_pad + AB_ROWS - 1) / AB_ROWS));
   if (fmt == 0)
-    hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1);
+    hipLaunchKernelGGL(k_abuild<0>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1, arow);
   else
-    hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1);
+    hipLaunchKernelGGL(k_abuild<3>, grid, dim3(256), 0, s, rowR, Ts, G, n_R, n_chi, n_m, k_pad, lda, A0, A1, arow);
 }
 
 }  // namespace wlc
