@@ -179,12 +179,13 @@ int wlc_plan_index(wlc_plan plan, int32_t *tri, int32_t *rows, int32_t *distinct
 
 /* Row order of the one-halo Gram product (eq. General1h over the distinct
  * rows), into a HOST buffer of n_distinct int32: pos[e] is the product row of
- * distinct row e.  The bf16 precisions and FP64 order the distinct rows stably
- * by their lowest redshift bin, so that a 256-row panel's factor ends where
- * the lensing kernel of that bin does (eq. KernelLensing1) and a tile's
- * product stops where the shorter of its two panels' factors ends; the
- * panels of wlc_gram_split_tiles and of the gram_tol bound are runs of 256 in
- * this order.  FP32 and FP64_CHI keep the distinct order (pos[e] = e).  The
+ * distinct row e.  The flattened products (every precision but FP64_CHI)
+ * order the distinct rows stably by their lowest redshift bin, so that a
+ * 256-row panel's factor ends where the lensing kernel of that bin does (eq.
+ * KernelLensing1) and a tile's product stops where the shorter of its two
+ * panels' factors ends; the panels of wlc_gram_split_tiles and of the
+ * gram_tol bound are runs of 256 in this order.  FP64_CHI keeps the distinct
+ * order (pos[e] = e).  The
  * covariance and every other output keep the data-vector order whatever this
  * order is.  WLC_EINVAL for a null argument. */
 int wlc_plan_gram_order(wlc_plan plan, int32_t *pos);
@@ -374,11 +375,11 @@ int wlc_gram(int precision, int64_t n, int64_t k, const uint16_t *a_hi, const ui
 
 /* Work of the last run's one-halo product, into HOST doubles: flops counts
  * one product per tile over the columns it summed (2 x 256 x 256 per column
- * and tile I >= J for the bf16 products, 2 x 128 x 256 per column on the
- * 128 x 256 tiles of the FP64 product, both of which stop where the shorter
- * of the two panels' factors ends; the FP32 product covers every column of
- * its 128 x 128 tiles), mfma_flops the same with the split tiles counted
- * three times.  factor_bytes (may be NULL): the bytes of the factor A that
+ * and tile I >= J for the bf16 products, 2 x 128 x 256 on the 128 x 256
+ * tiles of the FP64 product, 2 x 128 x 128 on the FP32 product's tiles; each
+ * stops where the shorter of its two 256-row panels' factors ends),
+ * mfma_flops the same with the split tiles counted three times.
+ * factor_bytes (may be NULL): the bytes of the factor A that
  * the product's operands need, over the distinct rows and the K columns (the
  * bf16 factors up to each panel's extent, with the lo half where a tile of
  * the panel can take the split product; FP32 and FP64 over all K).  All 0

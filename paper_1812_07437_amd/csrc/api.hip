@@ -181,7 +181,7 @@ size_t snr_structured_ws_bytes(const Plan &p) {
          align_up(chol_scratch_bytes(n), 256) + 256 + 256;
 }
 
-// The A-row order of the bf16 and FP64 products: distinct rows by their lowest
+// The A-row order of the flattened one-halo products: distinct rows by their lowest
 // redshift bin (rows hold their bins in increasing order), stably.  The
 // factor of a row vanishes beyond the far edge of its lowest bin (eq.
 // KernelLensing1: W_i(chi) = 0 past the sources of bin i), so panels of rows
@@ -191,7 +191,7 @@ static void order_arows(Plan &p) {
   p.arow.clear();
   p.pos.clear();
   const int prec = p.cfg.precision;
-  if (prec != WLC_BF16 && prec != WLC_BF16X3 && prec != WLC_BF16_AUTO && prec != WLC_FP64) return;
+  if (prec == WLC_FP64_CHI) return;  // no flattened product
   const int nz = p.cfg.n_z;
   std::vector<int64_t> start((size_t)nz + 1, 0);
   for (int64_t e = 0; e < p.n_R; ++e) ++start[(size_t)p.rowR[4 * e + 1] + 1];
@@ -411,7 +411,7 @@ int run_enqueue_front(const Plan &p, const wlc_tables &tb, void *ws, hipStream_t
   if (ssc_chi) launch_sigma_w2(T, theta_sky(p), sw, s);
   launch_gfactor(T, cfgT, n_cfg, sl, U, R, sw, std::sqrt(p.omega), n_mg, G, Gmax, s);
   launch_tfactor(T, rowR, cfgT, p.n_R, Gmax, Ts, sexp, s);
-  const bool arows = !p.arow.empty();  // the bf16 and FP64 products run on A-rows in their own order
+  const bool arows = !p.arow.empty();  // the flattened products run on A-rows in their own order
   const int32_t *arow = arows ? at<int32_t>(ws, L, B_AROW) : nullptr;
   const int32_t *pos = arows ? at<int32_t>(ws, L, B_POS) : nullptr;
   int32_t *ext = arows ? at<int32_t>(ws, L, B_EXT) : nullptr;
@@ -456,8 +456,8 @@ static double split_lim(const Plan &p) {
   return (tol / eps) * (tol / eps);
 }
 
-// The product of the bf16 modes and FP64 goes to GP (A-row order) and is put
-// back in the distinct-row order by run_enqueue_back; the others write G
+// The flattened product goes to GP (A-row order) and is put back in the
+// distinct-row order by run_enqueue_back; the chi-factorised one writes G
 // directly.
 static void *gram_out(const Plan &p, void *ws, const Layout &L) {
   return at<void>(ws, L, p.arow.empty() ? B_GM : B_GP);
@@ -975,9 +975,11 @@ int wlc_gram_work(wlc_plan plan, const void *ws_run, double *flops, double *mfma
       for (int64_t J = 0; J <= P; ++J) f += 2.0 * 2.0 * 128.0 * 256.0 * k_of(P, J);
     m = f;
   } else if (prec == WLC_FP64 || prec == WLC_FP32) {
-    // 128 x 128 tiles over the lower triangle, every k
-    const double nt = (double)(p.r_pad / 128);
-    f = m = nt * (nt + 1.0) / 2.0 * 2.0 * 128.0 * 128.0 * (double)p.k_pad;
+    // 128 x 128 tiles over the lower triangle, in 256-row panels I / 2, J / 2
+    const int64_t nt = p.r_pad / 128;
+    for (int64_t I = 0; I < nt; ++I)
+      for (int64_t J = 0; J <= I; ++J) f += 2.0 * 128.0 * 128.0 * k_of(I / 2, J / 2);
+    m = f;
   } else {
     const double t2 = 2.0 * (double)GRAM_TILE * (double)GRAM_TILE;
     for (int64_t I = 0; I < np; ++I)

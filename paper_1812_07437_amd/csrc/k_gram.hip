@@ -527,10 +527,16 @@ __device__ __forceinline__ void mfma16x16x4<float>(float a, float b, f32x4 &c) {
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// With panel_ext (per 256-row panel the 32-column k-blocks where its rows can
+// be nonzero), tile (I, J) sums only the k-blocks where both of its 256-row
+// panels (I / 2 and J / 2) can be nonzero, split evenly over its slices; an
+// empty slice stores zeros.  Items are dealt to the XCDs in chunks
+// (gram_work<GRAM_XC>), which keeps the XCDs' shares of unequal items alike.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_t k_pad, int64_t lda, int64_t k_split,
                                                  int n_split, int nt, int64_t n_work, T *__restrict__ out,
-                                                 T *__restrict__ partial, int64_t ld, int64_t part_stride) {
+                                                 T *__restrict__ partial, int64_t ld, int64_t part_stride,
+                                                 const int32_t *__restrict__ panel_ext) {
   using acc_t = typename std::conditional<sizeof(T) == 8, f64x4, f32x4>::type;
   constexpr int BK = 128 / sizeof(T);  // 128 bytes of k per row
   constexpr int LDR = BK + 1;          // padded row length
@@ -541,8 +547,12 @@ __global__ __launch_bounds__(256) void k_gram_x4(const T *__restrict__ A, int64_
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   int I, J, split;
-  if (!gram_work<0>(n_work, n_split, nt, I, J, split)) return;
+  if (!gram_work<GRAM_XC>(n_work, n_split, nt, I, J, split)) return;
   const int64_t row0 = (int64_t)I * TILE, col0 = (int64_t)J * TILE;
+  if (panel_ext) {
+    k_pad = min(k_pad, (int64_t)max(min(panel_ext[I >> 1], panel_ext[J >> 1]), 0) * GRAM_KB);
+    k_split = (k_pad / BK + n_split - 1) / n_split * BK;
+  }
   const int64_t kb = (int64_t)split * k_split;
   const int64_t ke = min(k_pad, kb + k_split);
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
@@ -915,8 +925,7 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
   const GramSplit q = gram_split(prec, g);
   const int64_t nt = q.nt, tiles = q.tiles, ksplit = q.ksplit, pstride = q.pstride, n_work = q.n_work;
   const int ns = q.ns;
-  // whole item groups of the dealt schedules (gram_work<GRAM_XC>, k_gram_f64)
-  const int64_t gq = is_bf16(prec) || f64_tiles(prec, g) ? (int64_t)N_XCD * GRAM_XC : N_XCD;
+  const int64_t gq = (int64_t)N_XCD * GRAM_XC;  // whole item groups of the dealt schedules
   const dim3 grid((unsigned)((n_work + gq - 1) / gq * gq));
   const int nti = (int)nt;
   switch (prec) {
@@ -937,7 +946,7 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
       break;
     case WLC_FP32:
       hipLaunchKernelGGL(k_gram_x4<float>, grid, dim3(256), 0, s, (const float *)A0, g.k_pad, g.lda, ksplit, ns, nti,
-                         n_work, (float *)out, (float *)partial, g.ld_out, pstride);
+                         n_work, (float *)out, (float *)partial, g.ld_out, pstride, panel_ext);
       break;
     default:
       if (f64_tiles(prec, g)) {
@@ -946,7 +955,7 @@ void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, v
         break;
       }
       hipLaunchKernelGGL(k_gram_x4<double>, grid, dim3(256), 0, s, (const double *)A0, g.k_pad, g.lda, ksplit, ns, nti,
-                         n_work, (double *)out, (double *)partial, g.ld_out, pstride);
+                         n_work, (double *)out, (double *)partial, g.ld_out, pstride, panel_ext);
       break;
   }
   (void)tiles;

@@ -41,10 +41,10 @@ void launch_tfactor(const DevTables &T, const int32_t *rowR, const int32_t *cfgT
 constexpr int GRAM_KB = 32;
 // panel_f, lim (fmt 2 only): write the lo half only for panels that can
 // take the split product (WLC_BF16_AUTO); nullptr writes it everywhere.
-// arow: the distinct row of each A-row (bf16 formats and FP64; -1 past the
-// distinct rows); ext (bf16 formats): the k-blocks each 256-row panel of
-// A-rows needs (see launch_panel_ext), written only that far.  nullptr:
-// A-row = distinct row, every k-block.
+// arow: the distinct row of each A-row (-1 past the distinct rows); ext
+// (bf16 formats): the k-blocks each 256-row panel of A-rows needs (see
+// launch_panel_ext), written only that far (the FP32 and FP64 formats write
+// every k-block).  nullptr: A-row = distinct row, every k-block.
 void launch_abuild(int fmt, const int32_t *rowR, const double *Ts, const double *G, int64_t n_R, int64_t r_pad,
                    int n_chi, int n_m, int64_t k_pad, int64_t lda, void *A0, void *A1, hipStream_t s,
                    const double *panel_f = nullptr, double lim = 0.0, const int32_t *arow = nullptr,
@@ -74,10 +74,9 @@ struct GramShape {
 };
 size_t gram_partial_bytes(int prec, const GramShape &g);
 // panel_f, split_lim: WLC_BF16_AUTO only (see k_gram.hip); ignored otherwise.
-// panel_ext (bf16, and FP64 on its 128 x 256 tiles): per 256-row panel the
-// 32-column k-blocks where its rows can be nonzero; a tile then sums only
-// the first min over its two panels (the rest are zero products).  nullptr:
-// every k-block.
+// panel_ext: per 256-row panel the 32-column k-blocks where its rows can be
+// nonzero; a tile then sums only the first min over its two panels (the
+// rest are zero products).  nullptr: every k-block.
 void launch_gram(int prec, const GramShape &g, const void *A0, const void *A1, void *out, void *partial,
                  hipStream_t s, const double *panel_f = nullptr, double split_lim = 0.0,
                  const int32_t *panel_ext = nullptr);
@@ -119,8 +118,8 @@ void launch_gram_mirror(int f32, void *G, int64_t n, int64_t ld, hipStream_t s);
 // order of the distinct rows.
 void launch_gram_unpermute(int f32, const void *GP, const int32_t *pos, int64_t n, int64_t ld, void *G,
                            hipStream_t s);
-// Whether the FP64 product of this shape runs on 128 x 256 tiles (the tiles
-// that honour panel_ext); otherwise it sums every k-block.
+// Whether the FP64 product of this shape runs on 128 x 256 tiles (else on
+// the 128 x 128 tiles of the FP32 product).
 bool gram_f64_tiles(const GramShape &g);
 
 // ---- assembly (k_assemble.hip)

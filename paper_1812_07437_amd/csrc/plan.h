@@ -45,11 +45,11 @@ struct Plan {
   std::vector<int32_t> lmax_ends;
   double omega = 0.0;                       // 4 pi f_sky
   double noise = 0.0;                       // sigma_eps^2 / n_i
-  // bf16 and FP64 Gram products: the rows of A in order of their lowest
-  // redshift bin (stable), so that the rows whose lensing kernels end
-  // earliest share panels; arow [r_pad] is the distinct row of each A-row (-1
-  // past n_R), pos [n_R] its inverse.  Empty for the other precisions (A-row
-  // = row).
+  // Flattened Gram products (every precision but FP64_CHI): the rows of A in
+  // order of their lowest redshift bin (stable), so that the rows whose
+  // lensing kernels end earliest share panels; arow [r_pad] is the distinct
+  // row of each A-row (-1 past n_R), pos [n_R] its inverse.  Empty for
+  // FP64_CHI.
   std::vector<int32_t> arow, pos;
   // sizes
   int64_t k_len = 0, k_pad = 0, r_pad = 0, n_pad = 0;

@@ -117,17 +117,18 @@ def test_invalid_config_rejected(bad):
 
 @pytest.mark.parametrize("preset,tomo", [("mid", "paper"), ("euclid5", "paper"), ("euclid5", "sorted")])
 def test_gram_order(preset, tomo):
-    """The bf16 and FP64 products take the distinct rows stably by their
-    lowest redshift bin (a permutation); FP32 keeps the distinct order."""
+    """The flattened products take the distinct rows stably by their lowest
+    redshift bin (a permutation); the chi-factorised one keeps the distinct
+    order."""
     t = dict(synth.PRESETS[preset]); t.update(synth.SURVEY_DEFAULTS); t["rho_mean"] = 0.3 * synth.RHO_CRIT
-    for prec in ("bf16", "bf16x3", "bf16_auto", "fp32", "fp64"):
+    for prec in ("bf16", "bf16x3", "bf16_auto", "fp32", "fp64", "fp64_chi"):
         plan = w.wlc_plan_create(w.make_config(t, prec, tomo))
         s, _, rows, dist = _index(plan)
         pos = np.zeros(s.n_distinct, np.int32)
         w.wlc_plan_gram_order(plan, pos.ctypes.data_as(ct.c_void_p))
         w.wlc_plan_destroy(plan)
         ident = np.arange(s.n_distinct)
-        if prec == "fp32":
+        if prec == "fp64_chi":
             assert np.array_equal(pos, ident)
             continue
         assert np.array_equal(np.sort(pos), ident)
