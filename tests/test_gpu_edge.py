@@ -59,7 +59,7 @@ def test_degenerate_shapes(wl, n_z, n_ell, precision):
 @pytest.mark.parametrize("precision", ["bf16_auto", "bf16x3"])
 def test_degenerate_shapes_mixed(wl, n_z, n_ell, precision):
     """The bf16 products on the smallest shapes (one 256-row tile, mostly
-    padding rows, at most two k-slices): the data vector stays FP64 (1e-10);
+    padding rows, one k-slice): the data vector stays FP64 (1e-10);
     covariance entries within 1e-5 of sqrt(C_aa C_bb) and (S/N)^2 within
     1e-4, the targets of the mixed-precision path."""
     _say("case edge mixed n_z=%d n_ell=%d %s" % (n_z, n_ell, precision))
