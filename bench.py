@@ -153,18 +153,30 @@ def precision_report(workload, torch, wl):
     default): bf16, split bf16 x 3, the per-tile choice and FP32 against the FP64 path on the same
     tables -- Gram time, its rate on the flops done against peak, its dense-equivalent rate,
     diagonal max / median relative error, off-diagonal error relative to
-    sqrt(C_aa C_bb), and the (S/N)^2 error."""
+    sqrt(C_aa C_bb), and the (S/N)^2 error -- and for each precision the
+    whole step (wlc_run and the direct S/N) in ms with the unique covariance
+    entries per second."""
     import synth
     t = synth.make_tables(workload)
     out = {"workload": workload}
     p64 = wl.Problem(t.cfg, t.arrays(), precision="fp64", device="cuda:0")
     s = p64.sizes
     NR, K = s.n_distinct, s.k_len
+    N = s.n_data
+    entries = N * (N + 1) / 2
+
+    def step_figures(prob):
+        dt, _, _, _ = timed_steps(prob, 3, 1, torch, wl)
+        return dict(step_ms=dt / 3 * 1e3, entries_per_s=entries / (dt / 3))
+
     ph = timed_runs(p64, 2, 1, torch, wl)
     snr64 = p64.snr2()
     C64 = true_cov(p64, torch)
     d64 = torch.diagonal(C64).clone()
-    out["fp64"] = dict(gram=gram_figures(ph["gram"], NR, K, "fp64", p64.gram_work()), snr2=snr64)
+    out["fp64"] = dict(gram=gram_figures(ph["gram"], NR, K, "fp64", p64.gram_work()), snr2=snr64,
+                       **step_figures(p64))
+    log("precision %s fp64: step %.2f ms (%.3g entries/s), gram %.3f ms" % (
+        workload, out["fp64"]["step_ms"], out["fp64"]["entries_per_s"], ph["gram"]))
     del p64
     scale = torch.sqrt(torch.outer(d64, d64))
     for prec in ("bf16", "bf16x3", "bf16_auto", "fp32"):
@@ -180,11 +192,12 @@ def precision_report(workload, torch, wl):
         out[prec] = dict(gram=gram_figures(ph["gram"], NR, K, prec, pm.gram_work(), split),
                          diag_max_rel=float(ed.max()),
                          diag_median_rel=float(ed.median()), offdiag_max_rel_sqrt_caa_cbb=float(off.max()),
-                         snr2_rel=abs(snr - snr64) / snr64)
-        log("precision %s %s: gram %.3f ms (%.1f %% of peak on the flops done), diag max %.2e median %.2e, "
-            "off %.2e, snr %.2e" % (workload, prec, ph["gram"], 100 * out[prec]["gram"]["frac_peak_mfma_work"],
-                          out[prec]["diag_max_rel"], out[prec]["diag_median_rel"],
-                          out[prec]["offdiag_max_rel_sqrt_caa_cbb"], out[prec]["snr2_rel"]))
+                         snr2_rel=abs(snr - snr64) / snr64, **step_figures(pm))
+        log("precision %s %s: step %.2f ms, gram %.3f ms (%.1f %% of peak on the flops done), diag max %.2e "
+            "median %.2e, off %.2e, snr %.2e" % (workload, prec, out[prec]["step_ms"], ph["gram"],
+                                                 100 * out[prec]["gram"]["frac_peak_mfma_work"],
+                                                 out[prec]["diag_max_rel"], out[prec]["diag_median_rel"],
+                                                 out[prec]["offdiag_max_rel_sqrt_caa_cbb"], out[prec]["snr2_rel"]))
         del pm, Cm, off
         torch.cuda.empty_cache()
     del C64, scale
