@@ -100,6 +100,26 @@ def test_fp64_euclid5_sampled(wl, precision):
     prob.close()
 
 
+@pytest.mark.parametrize("precision", ["bf16_auto", "bf16x3", "fp32"])
+def test_mixed_precision_sorted(wl, precision):
+    """SORTED tomography (N = N_R: the data vector is the distinct rows, the
+    product's A-row order a permutation of the output's) with the
+    mixed-precision targets: 1e-5 on the diagonal and on entries relative to
+    sqrt(C_aa C_bb), 1e-4 on (S/N)^2."""
+    for preset in ("tiny", "mid"):
+        _say("case mixed sorted %s %s" % (precision, preset))
+        t, o, ref = _oracle_full(preset, "sorted")
+        prob, snr2 = _run(wl, t, precision, "sorted")
+        C = prob.covariance_true()
+        dr = np.diag(ref["C"])
+        err_off = np.max(np.abs(C - ref["C"]) / np.sqrt(np.outer(dr, dr)))
+        err_snr = abs(snr2 - ref["snr2"]) / ref["snr2"]
+        _say("  %s sorted %s: C %.2e snr %.2e" % (precision, preset, err_off, err_snr))
+        assert _rel(prob.d.cpu().numpy(), ref["d"]) < 1e-10
+        assert err_off < 1e-5 and err_snr < 1e-4
+        prob.close()
+
+
 @pytest.mark.parametrize("precision,tol_diag,tol_off,tol_snr", [("bf16x3", 1e-5, 1e-5, 1e-4),
                                                                 ("fp32", 1e-5, 1e-5, 1e-4),
                                                                 ("bf16", 5e-3, 6e-3, 5e-2)])
